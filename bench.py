@@ -1,0 +1,237 @@
+"""Benchmark of the Vanka / multigrid / GMRES hot path on one MI355X.
+
+One step = the whole hot path on one Newton system: vanka_setup (patch gather,
+FP64 patch inverses stored in the chosen precision, coarse inverse) followed by
+gmres_solve from x = 0 to a relative residual of 1e-8 (GMRES(30), one V-cycle
+with 2 pre- and 2 post-smoothing additive coloured Vanka sweeps, omega = 0.7).
+
+value = Vanka cell-sweeps performed per second over the timed steps: every
+V-cycle applies nu_pre + nu_post sweeps on each level l >= 1, each sweep visits
+every cell of the level once.  The headline runs with FP32 patch inverses; the
+same line carries the FP64 run, the GMRES time to 1e-8 of both, the roofline of
+the dominant kernel (the patch apply) and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+
+python bench.py [--steps K] [--warmup W] [--config NAME] [--prec f32|f64|bf16]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PREC_BYTES = {"f64": 8, "f32": 4, "bf16": 2}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cells_sweeps_per_vcycle(P, nu1, nu2):
+    return sum(L.mesh.n_cells for L in P.levels[1:]) * (nu1 + nu2)
+
+
+def patch_apply_bytes(L, prec, cells):
+    """Algorithmic bytes of one additive patch-apply launch over `cells` cells:
+    A_K (n_K^2 entries), the cell's DoF list (int32), the gathered defect, the
+    read and write of d, and 1/p, all per DoF of the cell; plus the cell id."""
+    nK = L.mesh.n_K
+    return cells * (nK * nK * PREC_BYTES[prec] + nK * (4 + 8 + 8 + 8 + 8) + 4)
+
+
+def run_step(S, b, x, nu, restart, max_iter):
+    S.vanka_setup(0.7, "additive")
+    x.zero_()
+    its, rel, _, ok = S.gmres_solve(b, x, restart=restart, max_iter=max_iter, rtol=1e-8, nu_pre=nu[0],
+                                    nu_post=nu[1])
+    if not ok:
+        raise RuntimeError(f"GMRES did not reach 1e-8 ({its} its, rel {rel:.2e})")
+    return its, rel
+
+
+def phase_times(torch, S, b, x, nu, restart, max_iter, reps=3):
+    """Median setup and GMRES wall times (ms), each phase bracketed by syncs."""
+    ts, tg = [], []
+    its = rel = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.vanka_setup(0.7, "additive")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x.zero_()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        its, rel, _, ok = S.gmres_solve(b, x, restart=restart, max_iter=max_iter, rtol=1e-8,
+                                        nu_pre=nu[0], nu_post=nu[1])
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        ts.append((t1 - t0) * 1e3)
+        tg.append((t3 - t2) * 1e3)
+    return float(np.median(ts)), float(np.median(tg)), its, rel
+
+
+def sweep_rate(torch, S, P, b_np, sweeps=40):
+    """Finest-level additive sweeps in isolation: cells*sweeps/s."""
+    l = len(P.levels) - 1
+    b = torch.from_numpy(b_np).cuda()
+    d = torch.zeros_like(b)
+    S.vanka_smooth(l, b, d, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.vanka_smooth(l, b, d, sweeps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return P.finest.mesh.n_cells * sweeps / dt
+
+
+def cpu_baseline(P, nu, restart, n_steps_total_cells):
+    """The FP64 oracle on the host: one full step (setup + GMRES to 1e-8)."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    t0 = time.perf_counter()
+    H = oracle.OracleHierarchy(P.levels)
+    x, its, hist, conv, rel = oracle.gmres(P.finest.J, P.b, lambda v: oracle.vcycle(H, v, *nu),
+                                           restart=restart, max_iter=300, rtol=1e-8)
+    dt = time.perf_counter() - t0
+    cs = its * n_steps_total_cells
+    return {"value": cs / dt, "unit": "cell-sweeps/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"one full step (setup + GMRES to 1e-8, {its} iterations) of the same workload, "
+                      f"{dt:.1f} s"}, x, its
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="channel2d_176x32_k2")
+    ap.add_argument("--prec", default="f32", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP64/BF16 comparison runs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2210_02690_amd as vk
+    from synth import build_problem, CONFIGS
+
+    restart, max_iter, nu = 30, 300, (2, 2)
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    P = build_problem(args.config)
+    log(f"[bench] built {args.config}: n = {P.finest.n}, levels = {len(P.levels)}, "
+        f"{time.perf_counter() - t0:.1f} s")
+    levels = [vk.upload_level(L, dev) for L in P.levels]
+    b = torch.from_numpy(P.b).to(dev)
+    x = torch.zeros_like(b)
+    cs_per_vc = cells_sweeps_per_vcycle(P, *nu)
+    fine = P.finest
+    l_fine = len(P.levels) - 1
+
+    def make(prec):
+        S = vk.Solver(levels)
+        S.vk_set_workspace(prec, restart, device=dev)
+        return S
+
+    S = make(args.prec)
+    for w in range(args.warmup):
+        its, rel = run_step(S, b, x, nu, restart, max_iter)
+        log(f"[bench] warmup {w}: {its} its, rel {rel:.2e}")
+    # timed region
+    S.vk_timing_enable(True, l_fine)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    total_its = 0
+    for _ in range(args.steps):
+        its, rel = run_step(S, b, x, nu, restart, max_iter)
+        total_its += its
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n_apply, ms_apply = S.vk_timing_read("patch_apply", l_fine)
+    S.vk_timing_enable(False)
+    log(f"[bench] timed {args.steps} steps in {dt:.3f} s, {total_its} GMRES its")
+    value = total_its * cs_per_vc / dt
+    ms_per_step = dt / args.steps * 1e3
+
+    # roofline of the dominant kernel: finest-level patch apply, one colour per launch
+    cells_per_launch = fine.mesh.n_cells / fine.mesh.n_colours
+    bytes_launch = patch_apply_bytes(fine, args.prec, cells_per_launch)
+    avg_ms = ms_apply / max(n_apply, 1)
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+
+    setup_ms, gmres_ms, its_h, rel_h = phase_times(torch, S, b, x, nu, restart, max_iter)
+    x_head = x.cpu().numpy()
+    out = {
+        "metric": "Vanka cells·sweeps/s + GMRES time to 1e-8 rel. residual, FP32-patch vs FP64",
+        "value": value, "unit": "cell-sweeps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f32": "f32+f64", "bf16": "bf16+f32+f64", "f64": "f64"}[args.prec],
+        "data": "synthetic (seeded Newton linearisation of a channel flow; no dataset)",
+        "config": {"workload": args.config, "unknowns": int(fine.n), "levels": len(P.levels),
+                   "finest_cells": int(fine.mesh.n_cells), "patch_size": int(fine.mesh.n_K),
+                   "nnz_finest": int(fine.J.nnz), "patch_precision": args.prec, "gmres_restart": restart,
+                   "nu_pre": nu[0], "nu_post": nu[1], "omega": 0.7, "parallelism": "single GPU"},
+        "gmres_iterations": its_h, "gmres_true_rel_residual": rel_h,
+        "gmres_ms_to_1e-8": gmres_ms, "setup_ms": setup_ms,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "patch_apply (finest level, one colour per launch)",
+                     "bytes_per_launch": bytes_launch, "avg_launch_ms": avg_ms, "launches": n_apply},
+    }
+    try:
+        out["finest_sweep_rate"] = {args.prec: sweep_rate(torch, S, P, P.b)}
+    except Exception as e:  # pragma: no cover
+        log(f"[bench] sweep rate failed: {e}")
+    S.close()
+
+    if not args.no_compare:
+        for prec in [p for p in ("f64", "bf16") if p != args.prec]:
+            S2 = make(prec)
+            run_step(S2, b, x, nu, restart, max_iter)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            k_its = 0
+            reps = max(3, args.steps // 4)
+            for _ in range(reps):
+                its2, _ = run_step(S2, b, x, nu, restart, max_iter)
+                k_its += its2
+            torch.cuda.synchronize()
+            dt2 = time.perf_counter() - t0
+            s_ms, g_ms, its2, rel2 = phase_times(torch, S2, b, x, nu, restart, max_iter)
+            xs = x.cpu().numpy()
+            out[prec] = {"value": k_its * cs_per_vc / dt2, "ms_per_step": dt2 / reps * 1e3,
+                         "gmres_ms_to_1e-8": g_ms, "setup_ms": s_ms, "gmres_iterations": its2,
+                         "gmres_true_rel_residual": rel2,
+                         "rel_diff_solution_vs_headline": float(np.linalg.norm(xs - x_head) / np.linalg.norm(xs))}
+            try:
+                out["finest_sweep_rate"][prec] = sweep_rate(torch, S2, P, P.b)
+            except Exception:
+                pass
+            S2.close()
+            log(f"[bench] {prec}: {its2} its, gmres {g_ms:.2f} ms, setup {s_ms:.2f} ms")
+
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle ...")
+        cb, x_or, its_or = cpu_baseline(P, nu, restart, cs_per_vc)
+        cb["oracle_gmres_iterations"] = its_or
+        cb["rel_diff_headline_solution_vs_oracle"] = float(np.linalg.norm(x_head - x_or) / np.linalg.norm(x_or))
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * vk.h -- C ABI of the MI355X (gfx950) Vanka / geometric-multigrid / GMRES
+ * solver for the Newton systems of dG(k)-in-time, Q2/P1disc-in-space
+ * Navier-Stokes slabs (Anselmann & Bause, "Efficiency of local Vanka smoother
+ * geometric multigrid preconditioning for space-time finite element methods
+ * to the Navier-Stokes equations", Sec. 3).
+ *
+ * Conventions
+ *   - Array arguments are DEVICE pointers unless marked (host).
+ *   - The caller owns every array it passes (level matrices, transfer
+ *     matrices, cell maps, workspace, vectors) and keeps them alive and
+ *     unchanged until vk_destroy; the context stores the pointers, not copies.
+ *   - Apart from one 4 KiB status block allocated by vk_create, the library
+ *     allocates no device memory: all scratch lives in the caller-provided
+ *     workspace (vk_workspace_bytes / vk_set_workspace).
+ *   - All work is enqueued on the stream given to vk_create.  Calls are
+ *     asynchronous except those returning host outputs (vanka_setup's singular
+ *     check, gmres_solve's counts), which synchronise that stream.
+ *   - Every call returns a vk_status; nothing throws across the ABI.
+ *     vk_last_error returns a message for the last failure on a context.
+ *   - Calls on one context must not overlap (one host thread at a time).
+ *   - Floating point: matrices, vectors, residuals, Krylov vectors, patch
+ *     factorisations and the coarse direct solve are FP64.  Only the stored
+ *     patch inverses follow vk_prec (FP32/BF16 storage is applied with FP32
+ *     accumulation and the product is added in FP64).
+ */
+#ifndef VK_H
+#define VK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VK_OK = 0,
+  VK_ERR_ARG = 1,        /* invalid argument or malformed input (message says which) */
+  VK_ERR_HIP = 2,        /* a HIP runtime call or kernel launch failed */
+  VK_ERR_SINGULAR = 3,   /* a zero pivot in a patch (or coarse) factorisation */
+  VK_ERR_NOCONV = 4,     /* gmres_solve reached max_iter before the tolerance */
+  VK_ERR_BREAKDOWN = 5,  /* GMRES produced a non-finite value */
+  VK_ERR_WORKSPACE = 6,  /* workspace missing or smaller than vk_workspace_bytes */
+  VK_ERR_STATE = 7       /* call order violated (e.g. smoothing before setup) */
+} vk_status;
+
+/* Storage of the patch inverses A_K = J_K^{-1}. */
+typedef enum { VK_F64 = 0, VK_F32 = 1, VK_BF16 = 2 } vk_prec;
+
+/* Smoother update rule.
+ * VK_ADDITIVE: the averaged element-wise Vanka iteration of Sec. 3, Eq. 3.4
+ *   and 3.5a-d: every cell applies S_K to the same iterate d^{j-1}, the local
+ *   results are summed and divided by the number of cells sharing a DoF.
+ * VK_MULT_COLOURED: the "overwriting successively" alternative the paper
+ *   mentions after Eq. 3.5, in cell-coloured order: colour by colour, every
+ *   cell of the colour computes its local defect from the iterate left by the
+ *   previous colour and adds omega J_K^{-1} R_K (b - J d) to its DoFs. */
+typedef enum { VK_ADDITIVE = 0, VK_MULT_COLOURED = 1 } vk_mode;
+
+/* Compressed sparse rows, FP64 values, int64 row pointers, int32 columns.
+ * Columns must be strictly increasing within each row and lie in [0, n_cols). */
+typedef struct {
+  int64_t n_rows;
+  int64_t n_cols;
+  int64_t nnz;
+  const int64_t* row_ptr;  /* n_rows + 1 entries, row_ptr[0] = 0, row_ptr[n_rows] = nnz */
+  const int32_t* col;      /* nnz */
+  const double* val;       /* nnz */
+} vk_csr;
+
+typedef struct vk_ctx vk_ctx;
+
+/* Create a context for an n_levels hierarchy (level 0 = coarsest T_0,
+ * level n_levels-1 = finest T_L, Sec. 2).  hip_stream may be NULL (default
+ * stream).  Allocates the 4 KiB device status block. */
+vk_status vk_create(vk_ctx** ctx, int32_t n_levels, void* hip_stream);
+void vk_destroy(vk_ctx* ctx);
+const char* vk_last_error(const vk_ctx* ctx);
+
+/* Describe level l.
+ *   J          level matrix J_l (the Newton Jacobian of Eq. 3.3 on T_l), square.
+ *   P, R       prolongation T_{l-1} -> T_l (n_l x n_{l-1}) and restriction
+ *              (n_{l-1} x n_l); both NULL on level 0.
+ *   cell_dofs  n_cells x n_K row-major int32: dof(K, mu^) of Sec. 3, the
+ *              global DoFs of cell K for all k+1 Radau nodes.  Ignored (may
+ *              be NULL) on level 0, which is solved directly.
+ *   colour_cells  device int32[n_cells]: the cells sorted by colour;
+ *   colour_ptr    (host) int32[n_colours + 1]: colour c owns
+ *              colour_cells[colour_ptr[c] .. colour_ptr[c+1]).  Cells of one
+ *              colour must share no DoF (the caller's contract; the additive
+ *              sweep relies on it for a race-free scatter, the multiplicative
+ *              sweep for its update order).
+ * Validates sizes on the host; validates CSR structure and DoF ranges on the
+ * device (one synchronisation).  Returns VK_ERR_ARG on malformed input. */
+vk_status vk_set_level(vk_ctx* ctx, int32_t l, const vk_csr* J, const vk_csr* P, const vk_csr* R,
+                       int32_t n_cells, int32_t n_K, const int32_t* cell_dofs,
+                       const int32_t* colour_cells, const int32_t* colour_ptr, int32_t n_colours);
+
+/* Bytes of device workspace needed for patch inverses stored in `prec`, GMRES
+ * restart length `restart` and the current levels.  Host-only query. */
+size_t vk_workspace_bytes(const vk_ctx* ctx, vk_prec prec, int32_t restart);
+
+/* Hand the workspace to the context (device memory, 256-byte aligned, at
+ * least vk_workspace_bytes(prec, restart) bytes).  The context keeps the
+ * pointer; previous setup results are invalidated. */
+vk_status vk_set_workspace(vk_ctx* ctx, void* dev, size_t bytes, vk_prec prec, int32_t restart);
+
+/* Vanka setup (Sec. 3, the paragraph after Eq. 3.4): for every cell K of every
+ * level l >= 1 gather J_K = J_l restricted to dof(K, .) x dof(K, .), entries
+ * not stored in J_l being zero, invert it in FP64 by Gauss-Jordan elimination
+ * with partial pivoting (first row of maximal |pivot|; the LU pivot sequence)
+ * and store A_K in `prec`; compute 1/p_mu, p_mu = number of cells containing
+ * DoF mu (Eq. 3.5b); and form the FP64 inverse of J_0 for the coarsest-level
+ * direct solve.  omega is the under-relaxation of Eq. 3.4 (the paper uses 0.7).
+ * On a zero pivot returns VK_ERR_SINGULAR with *bad_level / *bad_cell (host,
+ * may be NULL) naming the first failing level and cell (cell -1 = the coarse
+ * matrix).  Synchronises the stream. */
+vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_level, int32_t* bad_cell);
+
+/* `sweeps` Vanka iterations on level l >= 1 for J_l d = b (Eq. 3.5, or the
+ * multiplicative variant selected at setup).  b, d: n_l FP64.  d is updated in
+ * place; d_is_zero != 0 declares d = 0 on entry (d is then cleared by the
+ * library and the first defect is b itself, as in the pre-smoothing d^0 = 0). */
+vk_status vanka_smooth(vk_ctx* ctx, int32_t l, const double* b, double* d, int32_t sweeps,
+                       int32_t d_is_zero);
+
+/* One V-cycle x = V(b) on the finest level from the zero initial guess
+ * (Sec. 3): nu_pre sweeps from d = 0, defect restriction, recursion, direct
+ * solve on T_0, prolongation of the correction, nu_post sweeps.  b, x: n_L FP64;
+ * x may not alias b. */
+vk_status vcycle(vk_ctx* ctx, const double* b, double* x, int32_t nu_pre, int32_t nu_post);
+
+/* Restarted GMRES(restart) for J_L x = b, right-preconditioned by one V-cycle
+ * per Arnoldi step (Sec. 3; [S03]).  x holds the initial guess on entry and the
+ * iterate on exit.  Stops when the residual estimate is <= max(rtol ||b||, atol)
+ * (Sec. 4 uses an absolute GMRES tolerance; relative 1e-8 is the default of the
+ * tests), after max_iter Arnoldi steps summed over restarts, or on a happy
+ * breakdown.  Orthogonalisation: classical Gram-Schmidt applied twice.
+ * restart must not exceed the value given to vk_set_workspace.
+ * Outputs (host): *iters Arnoldi steps, *true_rel_res = ||b - J x|| / ||b||
+ * recomputed at the end, history[0..*iters] residual estimates (the initial
+ * residual first) if history != NULL (max_iter + 1 entries).
+ * b = 0 returns x = 0 and *iters = 0.  Returns VK_ERR_NOCONV if max_iter was
+ * reached with the tolerance unmet (x is the last iterate). */
+vk_status gmres_solve(vk_ctx* ctx, const double* b, double* x, int32_t restart, int32_t max_iter,
+                      double rtol, double atol, int32_t nu_pre, int32_t nu_post, int32_t* iters,
+                      double* true_rel_res, double* history);
+
+/* ---- inspection helpers used by tests and the benchmark ----------------- */
+
+/* y = alpha * J_l x + beta * z (z may alias y; beta = 0 ignores z). */
+vk_status vk_spmv(vk_ctx* ctx, int32_t l, double alpha, const double* x, double beta,
+                  const double* z, double* y);
+
+/* Copy the stored inverses of cells [cell0, cell0 + n) of level l into out
+ * (device, FP64, n x n_K x n_K row-major), widening FP32/BF16 storage. */
+vk_status vk_get_patch_inverses(vk_ctx* ctx, int32_t l, int32_t cell0, int32_t n, double* out);
+
+/* Copy the FP64 inverse of the coarsest matrix J_0 (row-major n_0 x n_0). */
+vk_status vk_get_coarse_inverse(vk_ctx* ctx, double* out);
+
+/* Per-launch tuning of the patch kernels: cells per 256-thread workgroup
+ * (1, 2, 4 or 8; 0 = library default chosen from n_K and vk_prec). */
+vk_status vk_set_patch_tile(vk_ctx* ctx, int32_t l, int32_t cells_per_block);
+
+/* Stored bytes per patch inverse on level l (including padding) and the
+ * leading dimension used (the inverse is stored column by column). */
+vk_status vk_patch_layout(const vk_ctx* ctx, int32_t l, int64_t* bytes_per_cell, int32_t* ld);
+
+/* ---- per-launch timing (benchmarks) --------------------------------------
+ * With timing enabled, the library brackets every launch of the kernel classes
+ * below with a pair of HIP events on the context's stream (a pool of 16384
+ * pairs; launches beyond it are not recorded).  vk_timing_enable(ctx, 1, l)
+ * clears earlier records and records launches on level l only (l = -1: all
+ * levels); enable = 0 stops recording.  vk_timing_read synchronises the
+ * stream and returns the number of recorded launches of class `kind` on level
+ * l (l = -1: all levels) and their summed duration in milliseconds. */
+typedef enum {
+  VK_KERNEL_PATCH_APPLY = 0,    /* gather - patch GEMV - scatter, one colour */
+  VK_KERNEL_SPMV = 1,           /* level defect b - J d */
+  VK_KERNEL_PATCH_SETUP = 2,    /* patch gather + Gauss-Jordan inverse */
+  VK_KERNEL_PATCH_RESIDUAL = 3  /* multiplicative mode local defects */
+} vk_kernel_kind;
+vk_status vk_timing_enable(vk_ctx* ctx, int32_t enable, int32_t level);
+vk_status vk_timing_read(vk_ctx* ctx, int32_t kind, int32_t l, int64_t* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VK_H */

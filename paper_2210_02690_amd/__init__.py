@@ -1,0 +1,243 @@
+"""Python binding of libvk, the MI355X (gfx950) Vanka / geometric-multigrid /
+GMRES solver for Newton-linearised space-time Navier-Stokes systems.
+
+The functions below carry the names of the C ABI in include/vk.h and only
+marshal arguments: torch tensors (device memory) become pointers, Python
+numbers become C scalars.  Every numerical step runs in the library's HIP
+kernels.  There is no fallback: if libvk.so is missing the import fails.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libvk.so")
+HEADER = os.path.join(os.path.dirname(_PKG), "include", "vk.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python paper_2210_02690_amd/build.py`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+VK_OK, VK_ERR_ARG, VK_ERR_HIP, VK_ERR_SINGULAR, VK_ERR_NOCONV, VK_ERR_BREAKDOWN, VK_ERR_WORKSPACE, VK_ERR_STATE = range(8)
+STATUS_NAMES = ["VK_OK", "VK_ERR_ARG", "VK_ERR_HIP", "VK_ERR_SINGULAR", "VK_ERR_NOCONV", "VK_ERR_BREAKDOWN",
+                "VK_ERR_WORKSPACE", "VK_ERR_STATE"]
+VK_F64, VK_F32, VK_BF16 = 0, 1, 2
+VK_ADDITIVE, VK_MULT_COLOURED = 0, 1
+PRECISIONS = {"f64": VK_F64, "f32": VK_F32, "bf16": VK_BF16}
+MODES = {"additive": VK_ADDITIVE, "multiplicative": VK_MULT_COLOURED}
+
+
+class vk_csr(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("n_cols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+_P = ctypes.c_void_p
+_I32, _I64, _D, _SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+_PI32, _PI64, _PD = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
+
+_SIGS = {
+    "vk_create": (ctypes.c_int, [ctypes.POINTER(_P), _I32, _P]),
+    "vk_destroy": (None, [_P]),
+    "vk_last_error": (ctypes.c_char_p, [_P]),
+    "vk_set_level": (ctypes.c_int, [_P, _I32, ctypes.POINTER(vk_csr), ctypes.POINTER(vk_csr),
+                                    ctypes.POINTER(vk_csr), _I32, _I32, _P, _P, _PI32, _I32]),
+    "vk_workspace_bytes": (_SZ, [_P, ctypes.c_int, _I32]),
+    "vk_set_workspace": (ctypes.c_int, [_P, _P, _SZ, ctypes.c_int, _I32]),
+    "vanka_setup": (ctypes.c_int, [_P, _D, ctypes.c_int, _PI32, _PI32]),
+    "vanka_smooth": (ctypes.c_int, [_P, _I32, _P, _P, _I32, _I32]),
+    "vcycle": (ctypes.c_int, [_P, _P, _P, _I32, _I32]),
+    "gmres_solve": (ctypes.c_int, [_P, _P, _P, _I32, _I32, _D, _D, _I32, _I32, _PI32, _PD, _PD]),
+    "vk_spmv": (ctypes.c_int, [_P, _I32, _D, _P, _D, _P, _P]),
+    "vk_get_patch_inverses": (ctypes.c_int, [_P, _I32, _I32, _I32, _P]),
+    "vk_get_coarse_inverse": (ctypes.c_int, [_P, _P]),
+    "vk_set_patch_tile": (ctypes.c_int, [_P, _I32, _I32]),
+    "vk_patch_layout": (ctypes.c_int, [_P, _I32, _PI64, _PI32]),
+    "vk_timing_enable": (ctypes.c_int, [_P, _I32, _I32]),
+    "vk_timing_read": (ctypes.c_int, [_P, _I32, _I32, _PI64, _PD]),
+}
+KERNEL_KINDS = {"patch_apply": 0, "spmv": 1, "patch_setup": 2, "patch_residual": 3}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def header_functions(path=HEADER):
+    """Names of the functions declared in include/vk.h."""
+    with open(path) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(?:vk_status|void|size_t|const char\*)\s+\*?(\w+)\s*\(", text)))
+
+
+class VkError(RuntimeError):
+    def __init__(self, status, msg):
+        self.status = status
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else status}: {msg}")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def csr_struct(t):
+    """vk_csr from a dict of device tensors {n_rows, n_cols, row_ptr, col, val}."""
+    if t is None:
+        return None
+    return vk_csr(int(t["n_rows"]), int(t["n_cols"]), int(t["val"].numel()),
+                  t["row_ptr"].data_ptr(), t["col"].data_ptr() if t["val"].numel() else None,
+                  t["val"].data_ptr() if t["val"].numel() else None)
+
+
+def upload_csr(A, device):
+    """scipy CSR -> dict of device tensors (int64 row pointers, int32 columns, FP64 values)."""
+    import torch
+    A = A.tocsr()
+    A.sort_indices()
+    return {
+        "n_rows": A.shape[0], "n_cols": A.shape[1],
+        "row_ptr": torch.from_numpy(A.indptr.astype(np.int64)).to(device),
+        "col": torch.from_numpy(A.indices.astype(np.int32)).to(device),
+        "val": torch.from_numpy(A.data.astype(np.float64)).to(device),
+    }
+
+
+def upload_level(level, device):
+    """Device tensors of one level (an object with J, P, R, cell_dofs, colours)."""
+    import torch
+    out = {"J": upload_csr(level.J, device),
+           "P": upload_csr(level.P, device) if level.P is not None else None,
+           "R": upload_csr(level.R, device) if level.R is not None else None}
+    cd = np.ascontiguousarray(level.cell_dofs, dtype=np.int32)
+    colours = np.asarray(level.colours, dtype=np.int32)
+    order = np.argsort(colours, kind="stable").astype(np.int32)
+    n_col = int(colours.max()) + 1 if colours.size else 1
+    ptr = np.concatenate([[0], np.cumsum(np.bincount(colours, minlength=n_col))]).astype(np.int32)
+    out.update(n_cells=cd.shape[0], n_K=cd.shape[1], cell_dofs=torch.from_numpy(cd).to(device),
+               colour_cells=torch.from_numpy(order).to(device), colour_ptr=ptr, n_colours=n_col)
+    return out
+
+
+class Solver:
+    """Owns a vk_ctx and the device tensors it points to."""
+
+    def __init__(self, levels, stream=None):
+        self._keep = []
+        self.levels = levels
+        self.stream = stream
+        ctx = _P()
+        st = _lib.vk_create(ctypes.byref(ctx), len(levels), _stream_handle(stream))
+        if st != VK_OK:
+            raise VkError(st, "vk_create failed")
+        self.ctx = ctx
+        for l, lv in enumerate(levels):
+            J = csr_struct(lv["J"])
+            P = csr_struct(lv["P"]) if l > 0 else None
+            R = csr_struct(lv["R"]) if l > 0 else None
+            ptr = np.ascontiguousarray(lv["colour_ptr"], dtype=np.int32)
+            self._keep.append(ptr)
+            self._check(_lib.vk_set_level(
+                self.ctx, l, ctypes.byref(J), ctypes.byref(P) if P is not None else None,
+                ctypes.byref(R) if R is not None else None, int(lv["n_cells"]), int(lv["n_K"]),
+                _ptr(lv["cell_dofs"]), _ptr(lv["colour_cells"]),
+                ptr.ctypes.data_as(_PI32), int(lv["n_colours"])))
+        self.workspace = None
+        self.prec = None
+        self.restart = None
+
+    def _check(self, st):
+        if st != VK_OK:
+            raise VkError(st, _lib.vk_last_error(self.ctx).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            _lib.vk_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n(self):
+        return int(self.levels[-1]["J"]["n_rows"])
+
+    def vk_workspace_bytes(self, prec="f64", restart=30):
+        return int(_lib.vk_workspace_bytes(self.ctx, PRECISIONS[prec], restart))
+
+    def vk_set_workspace(self, prec="f64", restart=30, device="cuda"):
+        import torch
+        nbytes = self.vk_workspace_bytes(prec, restart)
+        if nbytes == 0:
+            raise VkError(VK_ERR_STATE, "levels inconsistent or arguments invalid")
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-ws.data_ptr()) % 256
+        self._check(_lib.vk_set_workspace(self.ctx, ctypes.c_void_p(ws.data_ptr() + off), nbytes,
+                                          PRECISIONS[prec], restart))
+        self.workspace, self.prec, self.restart = ws, prec, restart
+
+    def vanka_setup(self, omega=0.7, mode="additive"):
+        bl, bc = _I32(-1), _I32(-1)
+        st = _lib.vanka_setup(self.ctx, omega, MODES[mode], ctypes.byref(bl), ctypes.byref(bc))
+        if st != VK_OK:
+            err = VkError(st, _lib.vk_last_error(self.ctx).decode())
+            err.bad_level, err.bad_cell = bl.value, bc.value
+            raise err
+
+    def vanka_smooth(self, l, b, d, sweeps, d_is_zero=False):
+        self._check(_lib.vanka_smooth(self.ctx, l, _ptr(b), _ptr(d), sweeps, 1 if d_is_zero else 0))
+
+    def vcycle(self, b, x, nu_pre=2, nu_post=2):
+        self._check(_lib.vcycle(self.ctx, _ptr(b), _ptr(x), nu_pre, nu_post))
+
+    def gmres_solve(self, b, x, restart=30, max_iter=300, rtol=1e-8, atol=0.0, nu_pre=2, nu_post=2,
+                    raise_on_noconv=True):
+        its = _I32(0)
+        rel = _D(0.0)
+        hist = (ctypes.c_double * (max_iter + 1))()
+        st = _lib.gmres_solve(self.ctx, _ptr(b), _ptr(x), restart, max_iter, rtol, atol, nu_pre, nu_post,
+                              ctypes.byref(its), ctypes.byref(rel), hist)
+        if st != VK_OK and not (st == VK_ERR_NOCONV and not raise_on_noconv):
+            raise VkError(st, _lib.vk_last_error(self.ctx).decode())
+        return its.value, rel.value, np.array(hist[: its.value + 1]), st == VK_OK
+
+    def vk_spmv(self, l, x, y, alpha=1.0, beta=0.0, z=None):
+        self._check(_lib.vk_spmv(self.ctx, l, alpha, _ptr(x), beta, _ptr(z), _ptr(y)))
+
+    def vk_get_patch_inverses(self, l, cell0, n, out):
+        self._check(_lib.vk_get_patch_inverses(self.ctx, l, cell0, n, _ptr(out)))
+
+    def vk_get_coarse_inverse(self, out):
+        self._check(_lib.vk_get_coarse_inverse(self.ctx, _ptr(out)))
+
+    def vk_set_patch_tile(self, l, cells_per_block):
+        self._check(_lib.vk_set_patch_tile(self.ctx, l, cells_per_block))
+
+    def vk_timing_enable(self, enable=True, level=-1):
+        self._check(_lib.vk_timing_enable(self.ctx, 1 if enable else 0, level))
+
+    def vk_timing_read(self, kind, l=-1):
+        cnt, ms = _I64(0), _D(0.0)
+        self._check(_lib.vk_timing_read(self.ctx, KERNEL_KINDS[kind], l, ctypes.byref(cnt), ctypes.byref(ms)))
+        return cnt.value, ms.value
+
+    def vk_patch_layout(self, l):
+        b, ld = _I64(0), _I32(0)
+        self._check(_lib.vk_patch_layout(self.ctx, l, ctypes.byref(b), ctypes.byref(ld)))
+        return b.value, ld.value
+
+
+def lib():
+    return _lib

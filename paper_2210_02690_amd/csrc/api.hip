@@ -1,0 +1,600 @@
+// C ABI of libvk: context and level description, workspace planning, Vanka
+// setup, smoothing, V-cycle and GMRES driver loops.  Every numerical step runs
+// in the kernels of sparse.hip, patch.hip, coarse.hip and krylov.hip; this file
+// only sequences launches on the context's stream.
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "vk_internal.h"
+
+namespace {
+
+vk_status fail(vk_ctx* ctx, vk_status st, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return st;
+}
+
+vk_status fail_hip(vk_ctx* ctx, hipError_t e, const char* what) {
+  char buf[512];
+  snprintf(buf, sizeof(buf), "HIP error %d (%s) in %s", (int)e, hipGetErrorString(e), what);
+  return fail(ctx, VK_ERR_HIP, buf);
+}
+
+#define VK_TRY(expr)                                       \
+  do {                                                     \
+    hipError_t _e = (expr);                                \
+    if (_e != hipSuccess) return fail_hip(ctx, _e, #expr); \
+  } while (0)
+
+#define VK_CHECK(st)                 \
+  do {                               \
+    vk_status _s = (st);             \
+    if (_s != VK_OK) return _s;      \
+  } while (0)
+
+bool csr_ok(const vk_csr* A) {
+  if (!A) return false;
+  if (A->n_rows < 0 || A->n_cols < 0 || A->nnz < 0) return false;
+  if (!A->row_ptr) return false;
+  if (A->nnz > 0 && (!A->col || !A->val)) return false;
+  if (A->n_cols > INT32_MAX) return false;
+  return true;
+}
+
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// Sequential carving of the workspace (256-byte aligned pieces).
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(char* b) : base(b) {}
+  template <typename T>
+  T* take(int64_t count) {
+    off = (size_t)round_up((int64_t)off, 256);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += (size_t)count * sizeof(T);
+    return p;
+  }
+};
+
+bool levels_consistent(const vk_ctx* ctx, std::string* why) {
+  for (int l = 0; l < ctx->n_levels; ++l) {
+    const vk_level& L = ctx->lv[l];
+    if (!L.set) {
+      if (why) *why = "level " + std::to_string(l) + " not set";
+      return false;
+    }
+    if (l > 0) {
+      const int64_t nc = ctx->lv[l - 1].J.n_rows, nf = L.J.n_rows;
+      if (L.P.n_rows != nf || L.P.n_cols != nc || L.R.n_rows != nc || L.R.n_cols != nf) {
+        if (why) *why = "transfer sizes of level " + std::to_string(l) + " do not match J_l / J_{l-1}";
+        return false;
+      }
+    }
+  }
+  return true;
+}
+
+// Lays out the workspace; with base == nullptr only the size is computed.
+size_t plan_workspace(vk_ctx* ctx, vk_prec prec, int32_t restart, char* base) {
+  Carver cv(base);
+  const int nl = ctx->n_levels;
+  const int vw = vk_prec_vw(prec), sb = vk_prec_bytes(prec);
+  int32_t big_nk = 0, big_cells = 0;
+  int64_t rk = 0;
+  for (int l = 0; l < nl; ++l) {
+    vk_level& L = ctx->lv[l];
+    const int64_t n = L.J.n_rows;
+    L.b = cv.take<double>(n);
+    L.d = cv.take<double>(n);
+    L.r = cv.take<double>(n);
+    if (l == 0) continue;
+    L.ld = (int32_t)round_up(L.n_K, vw);
+    L.cell_stride = (int64_t)L.n_K * L.ld;
+    L.inv = cv.take<char>((int64_t)L.n_cells * L.cell_stride * sb);
+    L.inv_p = cv.take<double>(n);
+    if (L.n_K > VK_LDS_SETUP_MAX_NK) {
+      if (L.n_K > big_nk) big_nk = L.n_K;
+      if (L.n_cells > big_cells) big_cells = L.n_cells;
+    }
+    const int64_t r = (int64_t)L.max_colour_cells * L.n_K;
+    if (r > rk) rk = r;
+  }
+  const int64_t n0 = ctx->lv[0].J.n_rows;
+  ctx->c_inv = cv.take<double>(n0 * n0);
+  ctx->c_tmp = cv.take<double>(n0 * n0);
+  ctx->c_perm = cv.take<int32_t>(2 * n0);
+  if (big_nk > 0) {
+    const int64_t per = (int64_t)big_nk * big_nk;
+    int64_t chunk = (int64_t)(512ll << 20) / (per * 8);
+    if (chunk < 1) chunk = 1;
+    if (chunk > big_cells) chunk = big_cells;
+    ctx->big_chunk = (int32_t)chunk;
+    ctx->big_scratch = cv.take<double>(chunk * per);
+  } else {
+    ctx->big_chunk = 0;
+    ctx->big_scratch = nullptr;
+  }
+  ctx->rK = cv.take<double>(rk > 0 ? rk : 1);
+  const int64_t nL = ctx->lv[nl - 1].J.n_rows;
+  ctx->n_pad = round_up(nL, 32);
+  const int32_t m = restart;
+  ctx->V = cv.take<double>((int64_t)(m + 1) * ctx->n_pad);
+  ctx->Z = cv.take<double>((int64_t)m * ctx->n_pad);
+  ctx->H = cv.take<double>((int64_t)(m + 1) * m);
+  ctx->h2 = cv.take<double>(m + 1);
+  ctx->cs = cv.take<double>(m);
+  ctx->sn = cv.take<double>(m);
+  ctx->g = cv.take<double>(m + 1);
+  ctx->y = cv.take<double>(m);
+  ctx->n_partial = 1024 * (m + 1);
+  ctx->partial = cv.take<double>(ctx->n_partial);
+  ctx->scal = cv.take<double>(16);
+  return cv.off;
+}
+
+constexpr int32_t kTimingPool = 16384;
+
+// Brackets one launch with a pair of events when timing is on.
+struct Timed {
+  vk_ctx* ctx;
+  int32_t slot = -1;
+  Timed(vk_ctx* c, int32_t kind, int32_t level) : ctx(c) {
+    if (!ctx->timing || (int32_t)ctx->recs.size() >= kTimingPool) return;
+    if (ctx->timing_level >= 0 && level != ctx->timing_level) return;
+    slot = (int32_t)ctx->recs.size();
+    ctx->recs.push_back({kind, level, slot});
+    (void)hipEventRecord(ctx->ev[2 * slot], ctx->stream);
+  }
+  ~Timed() {
+    if (slot >= 0) (void)hipEventRecord(ctx->ev[2 * slot + 1], ctx->stream);
+  }
+};
+
+vk_status smooth(vk_ctx* ctx, int l, const double* b, double* d, int32_t sweeps, bool zero) {
+  vk_level& L = ctx->lv[l];
+  hipStream_t s = ctx->stream;
+  if (zero) VK_TRY(launch_fill(s, L.J.n_rows, 0.0, d));
+  for (int it = 0; it < sweeps; ++it) {
+    if (ctx->mode == VK_ADDITIVE) {
+      const double* r = b;
+      if (!(it == 0 && zero)) {
+        Timed t(ctx, VK_KERNEL_SPMV, l);
+        VK_TRY(launch_spmv(s, L.J, L.lpr_J, -1.0, d, 1.0, b, L.r));
+        r = L.r;
+      }
+      for (int c = 0; c < L.n_colours; ++c) {
+        Timed t(ctx, VK_KERNEL_PATCH_APPLY, l);
+        VK_TRY(launch_patch_apply(s, L, ctx->prec, c, r, nullptr, d, ctx->omega, true));
+      }
+    } else {
+      for (int c = 0; c < L.n_colours; ++c) {
+        {
+          Timed t(ctx, VK_KERNEL_PATCH_RESIDUAL, l);
+          VK_TRY(launch_patch_residual(s, L, c, b, d, ctx->rK));
+        }
+        Timed t(ctx, VK_KERNEL_PATCH_APPLY, l);
+        VK_TRY(launch_patch_apply(s, L, ctx->prec, c, nullptr, ctx->rK, d, ctx->omega, false));
+      }
+    }
+  }
+  return VK_OK;
+}
+
+vk_status vcycle_level(vk_ctx* ctx, int l, const double* b, double* x, int32_t nu1, int32_t nu2) {
+  hipStream_t s = ctx->stream;
+  if (l == 0) {
+    VK_TRY(launch_dense_gemv(s, ctx->lv[0].J.n_rows, ctx->c_inv, b, x));
+    return VK_OK;
+  }
+  vk_level& L = ctx->lv[l];
+  vk_level& C = ctx->lv[l - 1];
+  if (nu1 > 0) {
+    VK_CHECK(smooth(ctx, l, b, x, nu1, true));
+    VK_TRY(launch_spmv(s, L.J, L.lpr_J, -1.0, x, 1.0, b, L.r));
+    VK_TRY(launch_spmv(s, L.R, L.lpr_R, 1.0, L.r, 0.0, nullptr, C.b));
+  } else {
+    VK_TRY(launch_fill(s, L.J.n_rows, 0.0, x));
+    VK_TRY(launch_spmv(s, L.R, L.lpr_R, 1.0, b, 0.0, nullptr, C.b));
+  }
+  VK_CHECK(vcycle_level(ctx, l - 1, C.b, C.d, nu1, nu2));
+  VK_TRY(launch_spmv(s, L.P, L.lpr_P, 1.0, C.d, 1.0, x, x));
+  if (nu2 > 0) VK_CHECK(smooth(ctx, l, b, x, nu2, false));
+  return VK_OK;
+}
+
+vk_status read_scalars(vk_ctx* ctx, const double* dev, int count, double* out) {
+  VK_TRY(hipMemcpyAsync(ctx->host_buf, dev, sizeof(double) * count, hipMemcpyDeviceToHost, ctx->stream));
+  VK_TRY(hipStreamSynchronize(ctx->stream));
+  for (int i = 0; i < count; ++i) out[i] = ctx->host_buf[i];
+  return VK_OK;
+}
+
+vk_status ready(vk_ctx* ctx) {
+  if (!ctx) return VK_ERR_ARG;
+  if (!ctx->ws_ready) return fail(ctx, VK_ERR_WORKSPACE, "workspace not set");
+  if (!ctx->setup_done) return fail(ctx, VK_ERR_STATE, "vanka_setup has not run since the workspace was set");
+  return VK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vk_status vk_create(vk_ctx** out, int32_t n_levels, void* hip_stream) {
+  if (!out) return VK_ERR_ARG;
+  *out = nullptr;
+  if (n_levels < 1 || n_levels > 32) return VK_ERR_ARG;
+  vk_ctx* ctx = new (std::nothrow) vk_ctx;
+  if (!ctx) return VK_ERR_ARG;
+  ctx->n_levels = n_levels;
+  ctx->lv.resize(n_levels);
+  ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if (hipMalloc(&ctx->status, 4096) != hipSuccess) {
+    delete ctx;
+    return VK_ERR_HIP;
+  }
+  if (hipHostMalloc(reinterpret_cast<void**>(&ctx->host_buf), 4096, hipHostMallocDefault) != hipSuccess) {
+    (void)hipFree(ctx->status);
+    delete ctx;
+    return VK_ERR_HIP;
+  }
+  *out = ctx;
+  return VK_OK;
+}
+
+void vk_destroy(vk_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  else (void)hipDeviceSynchronize();
+  for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+  if (ctx->status) (void)hipFree(ctx->status);
+  if (ctx->host_buf) (void)hipHostFree(ctx->host_buf);
+  delete ctx;
+}
+
+const char* vk_last_error(const vk_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+vk_status vk_set_level(vk_ctx* ctx, int32_t l, const vk_csr* J, const vk_csr* P, const vk_csr* R, int32_t n_cells,
+                       int32_t n_K, const int32_t* cell_dofs, const int32_t* colour_cells,
+                       const int32_t* colour_ptr, int32_t n_colours) {
+  if (!ctx) return VK_ERR_ARG;
+  if (l < 0 || l >= ctx->n_levels) return fail(ctx, VK_ERR_ARG, "level index out of range");
+  if (!csr_ok(J) || J->n_rows != J->n_cols || J->n_rows == 0)
+    return fail(ctx, VK_ERR_ARG, "J must be a non-empty square CSR matrix with valid pointers");
+  if (J->n_rows > INT32_MAX) return fail(ctx, VK_ERR_ARG, "J too large for int32 columns");
+  vk_level L;
+  L.J = *J;
+  if (l > 0) {
+    if (!csr_ok(P) || !csr_ok(R)) return fail(ctx, VK_ERR_ARG, "levels >= 1 need prolongation P and restriction R");
+    if (P->n_rows != J->n_rows || R->n_cols != J->n_rows || P->n_cols != R->n_rows)
+      return fail(ctx, VK_ERR_ARG, "P must be n_l x n_{l-1} and R n_{l-1} x n_l");
+    if (n_cells <= 0 || n_K <= 0 || n_K > VK_MAX_NK)
+      return fail(ctx, VK_ERR_ARG, "n_cells must be positive and 1 <= n_K <= 512");
+    if (n_K > J->n_rows) return fail(ctx, VK_ERR_ARG, "n_K exceeds the number of unknowns");
+    if (!cell_dofs || !colour_cells || !colour_ptr || n_colours <= 0 || n_colours > 64)
+      return fail(ctx, VK_ERR_ARG, "cell_dofs, colour_cells, colour_ptr and 1 <= n_colours <= 64 required");
+    if (colour_ptr[0] != 0 || colour_ptr[n_colours] != n_cells)
+      return fail(ctx, VK_ERR_ARG, "colour_ptr must start at 0 and end at n_cells");
+    int32_t mx = 0;
+    for (int c = 0; c < n_colours; ++c) {
+      const int32_t cnt = colour_ptr[c + 1] - colour_ptr[c];
+      if (cnt < 0) return fail(ctx, VK_ERR_ARG, "colour_ptr must be non-decreasing");
+      if (cnt > mx) mx = cnt;
+    }
+    L.P = *P;
+    L.R = *R;
+    L.has_transfer = true;
+    L.n_cells = n_cells;
+    L.n_K = n_K;
+    L.cell_dofs = cell_dofs;
+    L.colour_cells = colour_cells;
+    L.colour_ptr.assign(colour_ptr, colour_ptr + n_colours + 1);
+    L.n_colours = n_colours;
+    L.max_colour_cells = mx;
+  }
+  // structural validation on the device
+  hipStream_t s = ctx->stream;
+  VK_TRY(launch_fill_i32(s, 1, 0, ctx->status + 1000));
+  VK_TRY(launch_validate_csr(s, L.J, ctx->status + 1000));
+  if (l > 0) {
+    VK_TRY(launch_validate_csr(s, L.P, ctx->status + 1000));
+    VK_TRY(launch_validate_csr(s, L.R, ctx->status + 1000));
+    VK_TRY(launch_validate_cells(s, L.n_cells, L.n_K, L.cell_dofs, L.J.n_rows, L.colour_cells, ctx->status + 1000));
+  }
+  int32_t flag = 0;
+  VK_TRY(hipMemcpyAsync(&flag, ctx->status + 1000, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  VK_TRY(hipStreamSynchronize(s));
+  if (flag != 0) {
+    char buf[256];
+    snprintf(buf, sizeof(buf),
+             "level %d failed validation (flags 0x%x: 1/2 row pointers, 4 column range, 8 unsorted or duplicate "
+             "columns, 16 cell DoF range, 32 colour cell range)",
+             l, flag);
+    return fail(ctx, VK_ERR_ARG, buf);
+  }
+  L.lpr_J = vk_pick_lpr(L.J.n_rows, L.J.nnz);
+  if (l > 0) {
+    L.lpr_P = vk_pick_lpr(L.P.n_rows, L.P.nnz);
+    L.lpr_R = vk_pick_lpr(L.R.n_rows, L.R.nnz);
+  }
+  L.set = true;
+  ctx->lv[l] = L;
+  ctx->ws_ready = false;
+  ctx->setup_done = false;
+  return VK_OK;
+}
+
+size_t vk_workspace_bytes(const vk_ctx* cctx, vk_prec prec, int32_t restart) {
+  if (!cctx || restart < 1 || restart > VK_MAX_RESTART) return 0;
+  if (prec != VK_F64 && prec != VK_F32 && prec != VK_BF16) return 0;
+  if (!levels_consistent(cctx, nullptr)) return 0;
+  vk_ctx tmp = *cctx;  // plan on a copy: the query does not touch the context
+  return plan_workspace(&tmp, prec, restart, nullptr);
+}
+
+vk_status vk_set_workspace(vk_ctx* ctx, void* dev, size_t bytes, vk_prec prec, int32_t restart) {
+  if (!ctx) return VK_ERR_ARG;
+  if (prec != VK_F64 && prec != VK_F32 && prec != VK_BF16) return fail(ctx, VK_ERR_ARG, "unknown precision");
+  if (restart < 1 || restart > VK_MAX_RESTART) return fail(ctx, VK_ERR_ARG, "restart must be in [1, 64]");
+  std::string why;
+  if (!levels_consistent(ctx, &why)) return fail(ctx, VK_ERR_STATE, why);
+  if (!dev || (reinterpret_cast<uintptr_t>(dev) & 255u)) return fail(ctx, VK_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  vk_ctx probe = *ctx;
+  const size_t need = plan_workspace(&probe, prec, restart, nullptr);
+  if (bytes < need) {
+    char buf[160];
+    snprintf(buf, sizeof(buf), "workspace of %zu bytes is smaller than the %zu required", bytes, need);
+    return fail(ctx, VK_ERR_WORKSPACE, buf);
+  }
+  for (int l = 1; l < ctx->n_levels; ++l) {
+    const vk_level& L = ctx->lv[l];
+    const int ld = (int)round_up(L.n_K, vk_prec_vw(prec));
+    const int cpb = L.cpb_override > 0 ? L.cpb_override : vk_default_cpb(L.n_K, ld, prec);
+    if (cpb <= 0 || VK_NT / cpb < ld / vk_prec_vw(prec))
+      return fail(ctx, VK_ERR_ARG, "patch too wide for the apply kernel at this precision / tile");
+  }
+  ctx->ws = reinterpret_cast<char*>(dev);
+  ctx->ws_bytes = bytes;
+  ctx->prec = prec;
+  ctx->restart = restart;
+  plan_workspace(ctx, prec, restart, ctx->ws);
+  ctx->ws_ready = true;
+  ctx->setup_done = false;
+  return VK_OK;
+}
+
+vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_level, int32_t* bad_cell) {
+  if (!ctx) return VK_ERR_ARG;
+  if (bad_level) *bad_level = -1;
+  if (bad_cell) *bad_cell = -1;
+  if (!ctx->ws_ready) return fail(ctx, VK_ERR_WORKSPACE, "workspace not set");
+  if (!(omega > 0.0) || !std::isfinite(omega)) return fail(ctx, VK_ERR_ARG, "omega must be positive");
+  if (mode != VK_ADDITIVE && mode != VK_MULT_COLOURED) return fail(ctx, VK_ERR_ARG, "unknown smoother mode");
+  ctx->setup_done = false;
+  ctx->omega = omega;
+  ctx->mode = mode;
+  hipStream_t s = ctx->stream;
+  VK_TRY(launch_fill_i32(s, 64, INT_MAX, ctx->status));
+  for (int l = 1; l < ctx->n_levels; ++l) {
+    vk_level& L = ctx->lv[l];
+    VK_TRY(launch_multiplicity(s, L.n_cells, L.n_K, L.cell_dofs, L.J.n_rows, reinterpret_cast<int32_t*>(L.r),
+                               L.inv_p));
+    Timed t(ctx, VK_KERNEL_PATCH_SETUP, l);
+    VK_TRY(launch_patch_setup(s, L, ctx->prec, ctx->big_scratch, ctx->big_chunk, ctx->status + l));
+  }
+  VK_TRY(launch_coarse_invert(s, ctx->lv[0].J, ctx->c_inv, ctx->c_tmp, ctx->c_perm, ctx->status));
+  int32_t st[64];
+  VK_TRY(hipMemcpyAsync(ctx->host_buf, ctx->status, sizeof(int32_t) * 64, hipMemcpyDeviceToHost, s));
+  VK_TRY(hipStreamSynchronize(s));
+  memcpy(st, ctx->host_buf, sizeof(st));
+  if (st[0] != INT_MAX) {
+    if (bad_level) *bad_level = 0;
+    if (bad_cell) *bad_cell = -1;
+    return fail(ctx, VK_ERR_SINGULAR, "coarsest-level matrix J_0 is singular (zero pivot)");
+  }
+  for (int l = 1; l < ctx->n_levels; ++l) {
+    if (st[l] != INT_MAX) {
+      if (bad_level) *bad_level = l;
+      if (bad_cell) *bad_cell = st[l];
+      char buf[128];
+      snprintf(buf, sizeof(buf), "patch matrix of cell %d on level %d is singular (zero pivot)", st[l], l);
+      return fail(ctx, VK_ERR_SINGULAR, buf);
+    }
+  }
+  ctx->setup_done = true;
+  return VK_OK;
+}
+
+vk_status vanka_smooth(vk_ctx* ctx, int32_t l, const double* b, double* d, int32_t sweeps, int32_t d_is_zero) {
+  VK_CHECK(ready(ctx));
+  if (l < 1 || l >= ctx->n_levels) return fail(ctx, VK_ERR_ARG, "smoothing needs a level >= 1");
+  if (!b || !d || sweeps < 0) return fail(ctx, VK_ERR_ARG, "null vector or negative sweep count");
+  if (d_is_zero) {
+    if (sweeps == 0) {
+      VK_TRY(launch_fill(ctx->stream, ctx->lv[l].J.n_rows, 0.0, d));
+      return VK_OK;
+    }
+    return smooth(ctx, l, b, d, sweeps, true);
+  }
+  return smooth(ctx, l, b, d, sweeps, false);
+}
+
+vk_status vcycle(vk_ctx* ctx, const double* b, double* x, int32_t nu_pre, int32_t nu_post) {
+  VK_CHECK(ready(ctx));
+  if (!b || !x || b == x) return fail(ctx, VK_ERR_ARG, "b and x must be distinct non-null vectors");
+  if (nu_pre < 0 || nu_post < 0) return fail(ctx, VK_ERR_ARG, "negative sweep count");
+  return vcycle_level(ctx, ctx->n_levels - 1, b, x, nu_pre, nu_post);
+}
+
+vk_status gmres_solve(vk_ctx* ctx, const double* b, double* x, int32_t restart, int32_t max_iter, double rtol,
+                      double atol, int32_t nu_pre, int32_t nu_post, int32_t* iters, double* true_rel_res,
+                      double* history) {
+  VK_CHECK(ready(ctx));
+  if (!b || !x || b == x) return fail(ctx, VK_ERR_ARG, "b and x must be distinct non-null vectors");
+  if (restart < 1 || restart > ctx->restart) return fail(ctx, VK_ERR_ARG, "restart exceeds the workspace's value");
+  if (max_iter < 0 || nu_pre < 0 || nu_post < 0 || !(rtol >= 0.0) || !(atol >= 0.0))
+    return fail(ctx, VK_ERR_ARG, "negative iteration count, sweep count or tolerance");
+  if (iters) *iters = 0;
+  if (true_rel_res) *true_rel_res = 0.0;
+  hipStream_t s = ctx->stream;
+  const int L = ctx->n_levels - 1;
+  vk_level& F = ctx->lv[L];
+  const int64_t n = F.J.n_rows, ldv = ctx->n_pad;
+  const int32_t ldh = restart + 1;
+  double* sc = ctx->scal;
+  double hb[2];
+  VK_TRY(launch_dot(s, n, b, b, ctx->partial, ctx->n_partial, sc + 0, true));
+  VK_CHECK(read_scalars(ctx, sc + 0, 1, hb));
+  const double bnorm = hb[0];
+  if (!std::isfinite(bnorm)) return fail(ctx, VK_ERR_ARG, "right-hand side is not finite");
+  if (bnorm == 0.0) {
+    VK_TRY(launch_fill(s, n, 0.0, x));
+    VK_TRY(hipStreamSynchronize(s));
+    if (history) history[0] = 0.0;
+    return VK_OK;
+  }
+  const double tol = std::fmax(rtol * bnorm, atol);
+  int32_t its = 0;
+  bool first = true;
+  bool converged = false;
+  double beta = 0.0;
+  for (;;) {
+    double* V0 = ctx->V;
+    VK_TRY(launch_spmv(s, F.J, F.lpr_J, -1.0, x, 1.0, b, V0));
+    VK_TRY(launch_dot(s, n, V0, V0, ctx->partial, ctx->n_partial, sc + 1, true));
+    VK_CHECK(read_scalars(ctx, sc + 1, 1, hb));
+    beta = hb[0];
+    if (!std::isfinite(beta)) return fail(ctx, VK_ERR_BREAKDOWN, "residual is not finite");
+    if (first) {
+      if (history) history[0] = beta;
+      first = false;
+    }
+    if (beta <= tol) {
+      converged = true;
+      break;
+    }
+    if (its >= max_iter) break;
+    VK_TRY(launch_scale_by_inv(s, n, V0, sc + 1, V0));
+    VK_TRY(launch_gmres_init(s, restart, ctx->H, ctx->g, sc + 1));
+    int32_t jn = 0;
+    for (int32_t j = 0; j < restart; ++j) {
+      double* Vj = ctx->V + (int64_t)j * ldv;
+      double* Vn = ctx->V + (int64_t)(j + 1) * ldv;
+      double* Zj = ctx->Z + (int64_t)j * ldv;
+      double* Hc = ctx->H + (int64_t)j * ldh;
+      VK_CHECK(vcycle_level(ctx, L, Vj, Zj, nu_pre, nu_post));
+      VK_TRY(launch_spmv(s, F.J, F.lpr_J, 1.0, Zj, 0.0, nullptr, Vn));
+      // classical Gram-Schmidt, applied twice
+      VK_TRY(launch_mdot(s, n, ctx->V, ldv, j + 1, Vn, ctx->partial, ctx->n_partial, Hc));
+      VK_TRY(launch_maxpy(s, n, ctx->V, ldv, j + 1, Hc, -1.0, Vn));
+      VK_TRY(launch_mdot(s, n, ctx->V, ldv, j + 1, Vn, ctx->partial, ctx->n_partial, ctx->h2));
+      VK_TRY(launch_maxpy(s, n, ctx->V, ldv, j + 1, ctx->h2, -1.0, Vn));
+      VK_TRY(launch_dot(s, n, Vn, Vn, ctx->partial, ctx->n_partial, Hc + j + 1, true));
+      VK_TRY(launch_givens(s, j, ldh, ctx->H, ctx->h2, ctx->cs, ctx->sn, ctx->g, sc + 2));
+      VK_TRY(launch_scale_by_inv(s, n, Vn, sc + 3, Vn));
+      VK_CHECK(read_scalars(ctx, sc + 2, 2, hb));
+      ++its;
+      jn = j + 1;
+      if (history) history[its] = hb[0];
+      if (!std::isfinite(hb[0]) || !std::isfinite(hb[1]))
+        return fail(ctx, VK_ERR_BREAKDOWN, "non-finite value in the Arnoldi process");
+      if (hb[0] <= tol || hb[1] == 0.0 || its >= max_iter) break;
+    }
+    VK_TRY(launch_trisolve(s, jn, ldh, ctx->H, ctx->g, ctx->y));
+    VK_TRY(launch_maxpy(s, n, ctx->Z, ldv, jn, ctx->y, 1.0, x));
+  }
+  if (iters) *iters = its;
+  if (true_rel_res) *true_rel_res = beta / bnorm;
+  if (!converged) {
+    char buf[160];
+    snprintf(buf, sizeof(buf), "GMRES reached %d iterations with relative residual %.3e", its, beta / bnorm);
+    return fail(ctx, VK_ERR_NOCONV, buf);
+  }
+  return VK_OK;
+}
+
+vk_status vk_spmv(vk_ctx* ctx, int32_t l, double alpha, const double* x, double beta, const double* z, double* y) {
+  if (!ctx) return VK_ERR_ARG;
+  if (l < 0 || l >= ctx->n_levels || !ctx->lv[l].set) return fail(ctx, VK_ERR_ARG, "level not set");
+  if (!x || !y || (beta != 0.0 && !z)) return fail(ctx, VK_ERR_ARG, "null vector");
+  if (x == y) return fail(ctx, VK_ERR_ARG, "x must not alias y");
+  const vk_level& L = ctx->lv[l];
+  VK_TRY(launch_spmv(ctx->stream, L.J, L.lpr_J, alpha, x, beta, z, y));
+  return VK_OK;
+}
+
+vk_status vk_get_patch_inverses(vk_ctx* ctx, int32_t l, int32_t cell0, int32_t n, double* out) {
+  VK_CHECK(ready(ctx));
+  if (l < 1 || l >= ctx->n_levels) return fail(ctx, VK_ERR_ARG, "patch inverses exist on levels >= 1");
+  const vk_level& L = ctx->lv[l];
+  if (cell0 < 0 || n < 0 || (int64_t)cell0 + n > L.n_cells || !out) return fail(ctx, VK_ERR_ARG, "cell range");
+  VK_TRY(launch_patch_export(ctx->stream, L, ctx->prec, cell0, n, out));
+  return VK_OK;
+}
+
+vk_status vk_get_coarse_inverse(vk_ctx* ctx, double* out) {
+  VK_CHECK(ready(ctx));
+  if (!out) return fail(ctx, VK_ERR_ARG, "null output");
+  const int64_t n0 = ctx->lv[0].J.n_rows;
+  VK_TRY(hipMemcpyAsync(out, ctx->c_inv, (size_t)(n0 * n0) * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  return VK_OK;
+}
+
+vk_status vk_set_patch_tile(vk_ctx* ctx, int32_t l, int32_t cells_per_block) {
+  if (!ctx) return VK_ERR_ARG;
+  if (l < 1 || l >= ctx->n_levels || !ctx->lv[l].set) return fail(ctx, VK_ERR_ARG, "level not set");
+  if (!(cells_per_block == 0 || cells_per_block == 1 || cells_per_block == 2 || cells_per_block == 4 ||
+        cells_per_block == 8))
+    return fail(ctx, VK_ERR_ARG, "cells_per_block must be 0, 1, 2, 4 or 8");
+  vk_level& L = ctx->lv[l];
+  if (ctx->ws_ready && cells_per_block > 0 && VK_NT / cells_per_block < L.ld / vk_prec_vw(ctx->prec))
+    return fail(ctx, VK_ERR_ARG, "tile leaves fewer threads per cell than 16-byte vectors per column");
+  L.cpb_override = cells_per_block;
+  return VK_OK;
+}
+
+vk_status vk_patch_layout(const vk_ctx* ctx, int32_t l, int64_t* bytes_per_cell, int32_t* ld) {
+  if (!ctx || l < 1 || l >= ctx->n_levels || !ctx->ws_ready) return VK_ERR_ARG;
+  const vk_level& L = ctx->lv[l];
+  if (bytes_per_cell) *bytes_per_cell = L.cell_stride * vk_prec_bytes(ctx->prec);
+  if (ld) *ld = L.ld;
+  return VK_OK;
+}
+
+vk_status vk_timing_enable(vk_ctx* ctx, int32_t enable, int32_t level) {
+  if (!ctx) return VK_ERR_ARG;
+  if (enable) {
+    if (ctx->ev.empty()) {
+      ctx->ev.resize(2 * kTimingPool);
+      for (auto& e : ctx->ev) VK_TRY(hipEventCreate(&e));
+    }
+    VK_TRY(hipStreamSynchronize(ctx->stream));
+    ctx->recs.clear();
+  }
+  ctx->timing = enable != 0;
+  ctx->timing_level = level;
+  return VK_OK;
+}
+
+vk_status vk_timing_read(vk_ctx* ctx, int32_t kind, int32_t l, int64_t* launches, double* total_ms) {
+  if (!ctx || !launches || !total_ms) return VK_ERR_ARG;
+  VK_TRY(hipStreamSynchronize(ctx->stream));
+  int64_t cnt = 0;
+  double tot = 0.0;
+  for (const vk_timing_rec& r : ctx->recs) {
+    if (r.kind != kind || (l >= 0 && r.level != l)) continue;
+    float ms = 0.f;
+    VK_TRY(hipEventElapsedTime(&ms, ctx->ev[2 * r.slot], ctx->ev[2 * r.slot + 1]));
+    ++cnt;
+    tot += ms;
+  }
+  *launches = cnt;
+  *total_ms = tot;
+  return VK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,468 @@
+// Vanka patch kernels (Sec. 3, Eq. 3.4 and 3.5):
+//   setup : gather J_K = J restricted to dof(K,.) x dof(K,.) and invert it in
+//           FP64 (Gauss-Jordan, partial pivoting), store A_K = J_K^{-1};
+//   apply : per colour, y_K = A_K r_K (r_K gathered from the defect, or a
+//           per-cell defect buffer) and d[dof(K,i)] += omega * s_i * y_K[i]
+//           with s = 1/p (averaged additive form) or 1 (multiplicative form);
+//   residual : per colour, the local defects (b - J d)[dof(K,.)] of the
+//           multiplicative form.
+//
+// Storage of A_K: column by column, leading dimension ld >= n_K padded so a
+// column is a whole number of 16-byte vectors; element (i, j) at j*ld + i.
+// A thread owns VW consecutive rows of a column (one 16-byte load) and walks
+// the columns of its column group, so consecutive threads read consecutive
+// addresses of the same column.
+#include "vk_internal.h"
+
+namespace {
+
+template <int P> struct PT;
+template <> struct PT<VK_F64> { using S = double;   using A = double; static constexpr int VW = 2; };
+template <> struct PT<VK_F32> { using S = float;    using A = float;  static constexpr int VW = 4; };
+template <> struct PT<VK_BF16> { using S = uint16_t; using A = float;  static constexpr int VW = 8; };
+
+__device__ inline float bf16_lo(uint32_t u) { return __uint_as_float(u << 16); }
+__device__ inline float bf16_hi(uint32_t u) { return __uint_as_float(u & 0xffff0000u); }
+
+__device__ inline uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+template <int P> __device__ inline void load_vec(const typename PT<P>::S* p, typename PT<P>::A* a);
+template <> __device__ inline void load_vec<VK_F64>(const double* p, double* a) {
+  const double2 v = *reinterpret_cast<const double2*>(p);
+  a[0] = v.x; a[1] = v.y;
+}
+template <> __device__ inline void load_vec<VK_F32>(const float* p, float* a) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
+}
+template <> __device__ inline void load_vec<VK_BF16>(const uint16_t* p, float* a) {
+  const uint4 v = *reinterpret_cast<const uint4*>(p);
+  a[0] = bf16_lo(v.x); a[1] = bf16_hi(v.x); a[2] = bf16_lo(v.y); a[3] = bf16_hi(v.y);
+  a[4] = bf16_lo(v.z); a[5] = bf16_hi(v.z); a[6] = bf16_lo(v.w); a[7] = bf16_hi(v.w);
+}
+
+template <int P> __device__ inline typename PT<P>::S store_cvt(double v);
+template <> __device__ inline double store_cvt<VK_F64>(double v) { return v; }
+template <> __device__ inline float store_cvt<VK_F32>(double v) { return (float)v; }
+template <> __device__ inline uint16_t store_cvt<VK_BF16>(double v) { return f32_to_bf16_rne((float)v); }
+
+template <int P> __device__ inline double load_cvt(const typename PT<P>::S* p);
+template <> __device__ inline double load_cvt<VK_F64>(const double* p) { return *p; }
+template <> __device__ inline double load_cvt<VK_F32>(const float* p) { return (double)*p; }
+template <> __device__ inline double load_cvt<VK_BF16>(const uint16_t* p) { return (double)bf16_lo(*p); }
+
+// Small per-block arrays of the setup kernels (in LDS).
+struct SetupSmem {
+  double* fcol;
+  double* prow;
+  double* pval;
+  int* skey;
+  int* sloc;
+  int* sdof;
+  int* perm;
+  int* piv;
+};
+
+__device__ inline SetupSmem carve_setup_smem(char* base, int n) {
+  SetupSmem s;
+  s.fcol = reinterpret_cast<double*>(base);
+  s.prow = s.fcol + n;
+  s.pval = s.prow + n;
+  s.skey = reinterpret_cast<int*>(s.pval + 2);
+  s.sloc = s.skey + n;
+  s.sdof = s.sloc + n;
+  s.perm = s.sdof + n;
+  s.piv = s.perm + n;
+  return s;
+}
+
+__host__ __device__ inline size_t setup_small_bytes(int n) { return (size_t)n * (2 * 8 + 4 * 4) + 32; }
+
+// J_K[i][j] = J[dof_i][dof_j] (0 where J stores nothing), row-major in M.
+__device__ void gather_patch(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                             const double* __restrict__ val, const int32_t* __restrict__ dofs, int n, double* M,
+                             SetupSmem& s) {
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n; i += blockDim.x) {
+    s.sdof[i] = dofs[i];
+    s.skey[i] = 0x7fffffff;
+    s.sloc[i] = 0;
+  }
+  for (int e = tid; e < n * n; e += blockDim.x) M[e] = 0.0;
+  __syncthreads();
+  // sorted copy of the cell's DoFs (they are distinct): rank sort
+  for (int i = tid; i < n; i += blockDim.x) {
+    const int v = s.sdof[i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) rank += (s.sdof[j] < v) ? 1 : 0;
+    s.skey[rank] = v;
+    s.sloc[rank] = i;
+  }
+  __syncthreads();
+  const int lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+  for (int i = wave; i < n; i += nwave) {
+    const int64_t row = s.sdof[i];
+    const int64_t e1 = row_ptr[row + 1];
+    for (int64_t e = row_ptr[row] + lane; e < e1; e += 64) {
+      const int c = col[e];
+      int lo = 0, hi = n;  // first key >= c
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (s.skey[mid] < c) lo = mid + 1; else hi = mid;
+      }
+      if (lo < n && s.skey[lo] == c) M[i * n + s.sloc[lo]] = val[e];
+    }
+  }
+  __syncthreads();
+}
+
+// In-place Gauss-Jordan inversion with partial (row) pivoting of the n x n
+// row-major M, by the whole workgroup.  Pivot = first row of maximal |value|
+// in the current column (the pivot sequence of LU with partial pivoting).
+// Returns false on a zero or non-finite pivot (M is then meaningless).
+__device__ bool gauss_jordan_inverse(double* M, int n, SetupSmem& s) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nt = blockDim.x;
+  for (int k = 0; k < n; ++k) {
+    if (wave == 0) {
+      double best = -1.0;
+      int bi = n;
+      for (int i = k + lane; i < n; i += 64) {
+        const double a = fabs(M[i * n + k]);
+        if (a > best) { best = a; bi = i; }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (lane == 0) {
+        s.piv[0] = bi;
+        s.perm[k] = bi;
+        s.pval[0] = bi < n ? M[bi * n + k] : 0.0;
+      }
+    }
+    __syncthreads();
+    // pivot index and value come from LDS: the row swap below rewrites M[p][k]
+    const int p = s.piv[0];
+    const double pv = s.pval[0];
+    if (p >= n || pv == 0.0 || !isfinite(pv)) return false;
+    if (p != k) {
+      for (int j = tid; j < n; j += nt) {
+        const double t = M[k * n + j];
+        M[k * n + j] = M[p * n + j];
+        M[p * n + j] = t;
+      }
+    }
+    __syncthreads();
+    const double inv = 1.0 / pv;
+    for (int i = tid; i < n; i += nt) s.fcol[i] = M[i * n + k];
+    for (int j = tid; j < n; j += nt) s.prow[j] = (j == k ? 1.0 : M[k * n + j]) * inv;
+    __syncthreads();
+    for (int e = tid; e < n * n; e += nt) {
+      const int i = e / n, j = e - i * n;
+      M[e] = (i == k) ? s.prow[j] : ((j == k ? 0.0 : M[e]) - s.fcol[i] * s.prow[j]);
+    }
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const int p = s.perm[k];
+    if (p != k) {
+      for (int i = tid; i < n; i += nt) {
+        const double t = M[i * n + k];
+        M[i * n + k] = M[i * n + p];
+        M[i * n + p] = t;
+      }
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+template <int P>
+__device__ void write_inverse(const double* M, int n, typename PT<P>::S* out, int ld) {
+  for (int o = threadIdx.x; o < n * ld; o += blockDim.x) {
+    const int j = o / ld, i = o - j * ld;
+    out[o] = store_cvt<P>(i < n ? M[i * n + j] : 0.0);
+  }
+}
+
+// One workgroup per cell; M in LDS (n_K <= VK_LDS_SETUP_MAX_NK) or in global
+// scratch (one n_K x n_K slab per workgroup of the current chunk).
+template <int P, bool GLOBAL>
+__global__ __launch_bounds__(VK_NT) void patch_setup_kernel(const int64_t* __restrict__ row_ptr,
+                                                            const int32_t* __restrict__ col,
+                                                            const double* __restrict__ val,
+                                                            const int32_t* __restrict__ cell_dofs, int32_t cell0,
+                                                            int32_t n, void* inv_out, int32_t ld,
+                                                            int64_t cell_stride, double* scratch, int32_t* status) {
+  extern __shared__ __align__(16) char smem[];
+  const int K = cell0 + blockIdx.x;
+  double* M;
+  SetupSmem s;
+  if (GLOBAL) {
+    M = scratch + (int64_t)blockIdx.x * n * n;
+    s = carve_setup_smem(smem, n);
+  } else {
+    M = reinterpret_cast<double*>(smem);
+    s = carve_setup_smem(smem + (size_t)n * n * 8, n);
+  }
+  gather_patch(row_ptr, col, val, cell_dofs + (int64_t)K * n, n, M, s);
+  const bool ok = gauss_jordan_inverse(M, n, s);
+  if (!ok && threadIdx.x == 0) atomicMin(&status[0], K);
+  using S = typename PT<P>::S;
+  write_inverse<P>(M, n, reinterpret_cast<S*>(inv_out) + (int64_t)K * cell_stride, ld);
+}
+
+template <int P, bool FROM_BUF>
+__global__ __launch_bounds__(VK_NT) void patch_apply_kernel(const void* __restrict__ inv_, int32_t ld,
+                                                            int64_t cell_stride, int32_t n_K,
+                                                            const int32_t* __restrict__ cells, int32_t n_launch,
+                                                            const int32_t* __restrict__ cell_dofs,
+                                                            const double* __restrict__ r,
+                                                            const double* __restrict__ rK, double* d,
+                                                            const double* __restrict__ inv_p, double omega,
+                                                            int32_t cpb) {
+  using S = typename PT<P>::S;
+  using A = typename PT<P>::A;
+  constexpr int VW = PT<P>::VW;
+  extern __shared__ __align__(16) char smem[];
+  int* sdof = reinterpret_cast<int*>(smem);
+  A* srk = reinterpret_cast<A*>(smem + (((size_t)cpb * n_K * 4 + 15) & ~(size_t)15));
+  A* part = srk + cpb * n_K;
+  const int tpc = VK_NT / cpb;
+  const int slot = threadIdx.x / tpc, t = threadIdx.x - slot * tpc;
+  const int64_t idx = (int64_t)blockIdx.x * cpb + slot;
+  const bool valid = idx < n_launch;
+  const int K = valid ? cells[idx] : 0;
+  for (int j = t; j < n_K; j += tpc) {
+    const int dof = valid ? cell_dofs[(int64_t)K * n_K + j] : 0;
+    sdof[slot * n_K + j] = dof;
+    double rv = 0.0;
+    if (valid) rv = FROM_BUF ? rK[idx * n_K + j] : r[dof];
+    srk[slot * n_K + j] = (A)rv;
+  }
+  __syncthreads();
+  const int vpc = ld / VW;
+  const int G = tpc / vpc;
+  const int g = t / vpc, v = t - g * vpc;
+  A acc[VW];
+#pragma unroll
+  for (int e = 0; e < VW; ++e) acc[e] = (A)0;
+  if (valid && g < G) {
+    const S* base = reinterpret_cast<const S*>(inv_) + (int64_t)K * cell_stride + v * VW;
+    const A* rk = srk + slot * n_K;
+#pragma unroll 4
+    for (int j = g; j < n_K; j += G) {
+      A a[VW];
+      load_vec<P>(base + (int64_t)j * ld, a);
+      const A rj = rk[j];
+#pragma unroll
+      for (int e = 0; e < VW; ++e) acc[e] = fma(a[e], rj, acc[e]);
+    }
+  }
+  A* mypart = part + slot * tpc * VW;
+  if (g < G) {
+#pragma unroll
+    for (int e = 0; e < VW; ++e) mypart[g * ld + v * VW + e] = acc[e];
+  }
+  __syncthreads();
+  if (valid) {
+    for (int i = t; i < n_K; i += tpc) {
+      A y = (A)0;
+      for (int gg = 0; gg < G; ++gg) y += mypart[gg * ld + i];
+      const int dof = sdof[slot * n_K + i];
+      const double sc = inv_p ? inv_p[dof] : 1.0;
+      d[dof] += omega * sc * (double)y;
+    }
+  }
+}
+
+template <int LPR>
+__global__ __launch_bounds__(256) void patch_residual_kernel(const int64_t* __restrict__ row_ptr,
+                                                             const int32_t* __restrict__ col,
+                                                             const double* __restrict__ val,
+                                                             const int32_t* __restrict__ cells, int32_t n_launch,
+                                                             const int32_t* __restrict__ cell_dofs, int32_t n_K,
+                                                             const double* __restrict__ b,
+                                                             const double* __restrict__ d, double* rK) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t item = gid / LPR;
+  const int lane = threadIdx.x & (LPR - 1);
+  const bool ok = item < (int64_t)n_launch * n_K;
+  double sum = 0.0;
+  int dof = 0;
+  if (ok) {
+    const int64_t idx = item / n_K;
+    const int i = (int)(item - idx * n_K);
+    dof = cell_dofs[(int64_t)cells[idx] * n_K + i];
+    const int64_t e1 = row_ptr[dof + 1];
+    for (int64_t e = row_ptr[dof] + lane; e < e1; e += LPR) sum += val[e] * d[col[e]];
+  }
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, LPR);
+  if (ok && lane == 0) rK[item] = b[dof] - sum;
+}
+
+__global__ void count_kernel(int64_t total, const int32_t* __restrict__ cell_dofs, int32_t* count) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&count[cell_dofs[e]], 1);
+}
+
+__global__ void inv_count_kernel(int64_t n, const int32_t* __restrict__ count, double* inv_p) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    inv_p[i] = count[i] > 0 ? 1.0 / (double)count[i] : 0.0;
+}
+
+template <int P>
+__global__ void export_kernel(const void* __restrict__ inv_, int32_t ld, int64_t cell_stride, int32_t n_K,
+                              int32_t cell0, int32_t n, double* out) {
+  using S = typename PT<P>::S;
+  const int64_t total = (int64_t)n * n_K * n_K;
+  for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < total; o += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = o / ((int64_t)n_K * n_K);
+    const int rem = (int)(o - c * n_K * n_K);
+    const int i = rem / n_K, j = rem - i * n_K;
+    out[o] = load_cvt<P>(reinterpret_cast<const S*>(inv_) + (cell0 + c) * cell_stride + (int64_t)j * ld + i);
+  }
+}
+
+inline unsigned capped_grid(int64_t work, int per_block, unsigned cap) {
+  int64_t g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+template <int P>
+hipError_t setup_prec(hipStream_t s, const vk_level& L, double* big, int32_t chunk, int32_t* status) {
+  const int n = L.n_K;
+  if (n <= VK_LDS_SETUP_MAX_NK) {
+    const size_t lds = (size_t)n * n * 8 + setup_small_bytes(n);
+    patch_setup_kernel<P, false><<<L.n_cells, VK_NT, lds, s>>>(L.J.row_ptr, L.J.col, L.J.val, L.cell_dofs, 0, n,
+                                                               L.inv, L.ld, L.cell_stride, nullptr, status);
+    return hipGetLastError();
+  }
+  const size_t lds = setup_small_bytes(n);
+  for (int32_t c0 = 0; c0 < L.n_cells; c0 += chunk) {
+    const int32_t cnt = (L.n_cells - c0) < chunk ? (L.n_cells - c0) : chunk;
+    patch_setup_kernel<P, true><<<cnt, VK_NT, lds, s>>>(L.J.row_ptr, L.J.col, L.J.val, L.cell_dofs, c0, n, L.inv,
+                                                        L.ld, L.cell_stride, big, status);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <int P>
+hipError_t apply_prec(hipStream_t s, const vk_level& L, int cpb, int32_t colour, const double* r,
+                      const double* rK, double* d, double omega, bool average) {
+  const int32_t c0 = L.colour_ptr[colour], c1 = L.colour_ptr[colour + 1];
+  const int32_t n_launch = c1 - c0;
+  if (n_launch <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)((n_launch + cpb - 1) / cpb);
+  constexpr int VW = PT<P>::VW;
+  using A = typename PT<P>::A;
+  const size_t lds = (((size_t)cpb * L.n_K * 4 + 15) & ~(size_t)15) + (size_t)cpb * L.n_K * sizeof(A) +
+                     (size_t)VK_NT * VW * sizeof(A);
+  const double* ip = average ? L.inv_p : nullptr;
+  if (rK)
+    patch_apply_kernel<P, true><<<grid, VK_NT, lds, s>>>(L.inv, L.ld, L.cell_stride, L.n_K, L.colour_cells + c0,
+                                                         n_launch, L.cell_dofs, r, rK, d, ip, omega, cpb);
+  else
+    patch_apply_kernel<P, false><<<grid, VK_NT, lds, s>>>(L.inv, L.ld, L.cell_stride, L.n_K, L.colour_cells + c0,
+                                                          n_launch, L.cell_dofs, r, rK, d, ip, omega, cpb);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int vk_prec_vw(vk_prec p) { return p == VK_F64 ? 2 : (p == VK_F32 ? 4 : 8); }
+int vk_prec_bytes(vk_prec p) { return p == VK_F64 ? 8 : (p == VK_F32 ? 4 : 2); }
+
+// Cells per 256-thread workgroup: the largest of 8, 4, 2, 1 whose per-cell
+// thread count covers a column (tpc >= ld / VW) with at most 1/8 of the
+// threads idle; otherwise the one with the fewest idle threads.
+int vk_default_cpb(int32_t n_K, int32_t ld, vk_prec prec) {
+  (void)n_K;
+  const int vpc = ld / vk_prec_vw(prec);
+  int best = 0;
+  double best_idle = 2.0;
+  for (int cpb : {8, 4, 2, 1}) {
+    const int tpc = VK_NT / cpb;
+    if (tpc < vpc) continue;
+    const int G = tpc / vpc;
+    const double idle = 1.0 - (double)(G * vpc) / tpc;
+    if (idle <= 0.125) return cpb;
+    if (idle < best_idle) { best_idle = idle; best = cpb; }
+  }
+  return best;
+}
+
+hipError_t launch_multiplicity(hipStream_t s, int32_t n_cells, int32_t n_K, const int32_t* cell_dofs, int64_t n,
+                               int32_t* count, double* inv_p) {
+  hipError_t e = launch_fill_i32(s, n, 0, count);
+  if (e != hipSuccess) return e;
+  const int64_t total = (int64_t)n_cells * n_K;
+  count_kernel<<<capped_grid(total, 256, 4096), 256, 0, s>>>(total, cell_dofs, count);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  inv_count_kernel<<<capped_grid(n, 256, 4096), 256, 0, s>>>(n, count, inv_p);
+  return hipGetLastError();
+}
+
+hipError_t launch_patch_setup(hipStream_t s, const vk_level& L, vk_prec prec, double* big, int32_t chunk,
+                              int32_t* status) {
+  if (L.n_cells == 0) return hipSuccess;
+  switch (prec) {
+    case VK_F64: return setup_prec<VK_F64>(s, L, big, chunk, status);
+    case VK_F32: return setup_prec<VK_F32>(s, L, big, chunk, status);
+    default: return setup_prec<VK_BF16>(s, L, big, chunk, status);
+  }
+}
+
+hipError_t launch_patch_apply(hipStream_t s, const vk_level& L, vk_prec prec, int32_t colour, const double* r,
+                              const double* rK, double* d, double omega, bool average) {
+  const int cpb = L.cpb_override > 0 ? L.cpb_override : vk_default_cpb(L.n_K, L.ld, prec);
+  switch (prec) {
+    case VK_F64: return apply_prec<VK_F64>(s, L, cpb, colour, r, rK, d, omega, average);
+    case VK_F32: return apply_prec<VK_F32>(s, L, cpb, colour, r, rK, d, omega, average);
+    default: return apply_prec<VK_BF16>(s, L, cpb, colour, r, rK, d, omega, average);
+  }
+}
+
+hipError_t launch_patch_residual(hipStream_t s, const vk_level& L, int32_t colour, const double* b,
+                                 const double* d, double* rK) {
+  const int32_t c0 = L.colour_ptr[colour], c1 = L.colour_ptr[colour + 1];
+  const int32_t n_launch = c1 - c0;
+  if (n_launch <= 0) return hipSuccess;
+  const int64_t items = (int64_t)n_launch * L.n_K;
+  const int lpr = L.lpr_J;
+  const unsigned grid = capped_grid(items * lpr, 256, 0x7fffffff);
+  switch (lpr) {
+    case 4: patch_residual_kernel<4><<<grid, 256, 0, s>>>(L.J.row_ptr, L.J.col, L.J.val, L.colour_cells + c0, n_launch, L.cell_dofs, L.n_K, b, d, rK); break;
+    case 8: patch_residual_kernel<8><<<grid, 256, 0, s>>>(L.J.row_ptr, L.J.col, L.J.val, L.colour_cells + c0, n_launch, L.cell_dofs, L.n_K, b, d, rK); break;
+    case 16: patch_residual_kernel<16><<<grid, 256, 0, s>>>(L.J.row_ptr, L.J.col, L.J.val, L.colour_cells + c0, n_launch, L.cell_dofs, L.n_K, b, d, rK); break;
+    case 32: patch_residual_kernel<32><<<grid, 256, 0, s>>>(L.J.row_ptr, L.J.col, L.J.val, L.colour_cells + c0, n_launch, L.cell_dofs, L.n_K, b, d, rK); break;
+    default: patch_residual_kernel<64><<<grid, 256, 0, s>>>(L.J.row_ptr, L.J.col, L.J.val, L.colour_cells + c0, n_launch, L.cell_dofs, L.n_K, b, d, rK); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_patch_export(hipStream_t s, const vk_level& L, vk_prec prec, int32_t cell0, int32_t n,
+                               double* out) {
+  const int64_t total = (int64_t)n * L.n_K * L.n_K;
+  if (total == 0) return hipSuccess;
+  const unsigned g = capped_grid(total, 256, 8192);
+  switch (prec) {
+    case VK_F64: export_kernel<VK_F64><<<g, 256, 0, s>>>(L.inv, L.ld, L.cell_stride, L.n_K, cell0, n, out); break;
+    case VK_F32: export_kernel<VK_F32><<<g, 256, 0, s>>>(L.inv, L.ld, L.cell_stride, L.n_K, cell0, n, out); break;
+    default: export_kernel<VK_BF16><<<g, 256, 0, s>>>(L.inv, L.ld, L.cell_stride, L.n_K, cell0, n, out); break;
+  }
+  return hipGetLastError();
+}

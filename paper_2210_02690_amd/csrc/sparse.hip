@@ -1,0 +1,137 @@
+// CSR kernels: y = alpha A x + beta z (defects r = b - J d, restriction R r,
+// prolongation d += P e), structural validation and fills.
+#include "vk_internal.h"
+
+namespace {
+
+// LPR lanes cooperate on one row; LPR divides the 64-wide wavefront.
+template <int LPR>
+__global__ __launch_bounds__(256) void spmv_kernel(int64_t n_rows, const int64_t* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ col,
+                                                   const double* __restrict__ val,
+                                                   const double* __restrict__ x, double alpha, double beta,
+                                                   const double* z, double* y) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t row = gid / LPR;
+  const int lane = threadIdx.x & (LPR - 1);
+  double sum = 0.0;
+  if (row < n_rows) {
+    const int64_t e0 = row_ptr[row], e1 = row_ptr[row + 1];
+    for (int64_t e = e0 + lane; e < e1; e += LPR) sum += val[e] * x[col[e]];
+  }
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, LPR);
+  if (row < n_rows && lane == 0) {
+    double v = alpha * sum;
+    if (beta != 0.0) v += beta * z[row];
+    y[row] = v;
+  }
+}
+
+__global__ void validate_csr_kernel(int64_t n_rows, int64_t n_cols, int64_t nnz,
+                                    const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                    int32_t* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0 && (row_ptr[0] != 0 || row_ptr[n_rows] != nnz)) atomicOr(flag, 1);
+  if (i >= n_rows) return;
+  const int64_t e0 = row_ptr[i], e1 = row_ptr[i + 1];
+  if (e0 < 0 || e1 > nnz || e0 > e1) {
+    atomicOr(flag, 2);
+    return;
+  }
+  int64_t prev = -1;
+  for (int64_t e = e0; e < e1; ++e) {
+    const int64_t c = col[e];
+    if (c < 0 || c >= n_cols) {
+      atomicOr(flag, 4);
+      return;
+    }
+    if (c <= prev) {
+      atomicOr(flag, 8);
+      return;
+    }
+    prev = c;
+  }
+}
+
+__global__ void validate_cells_kernel(int32_t n_cells, int32_t n_K, const int32_t* __restrict__ cell_dofs,
+                                      int64_t n, const int32_t* __restrict__ colour_cells, int32_t* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < (int64_t)n_cells * n_K) {
+    const int32_t v = cell_dofs[i];
+    if (v < 0 || v >= n) atomicOr(flag, 16);
+  }
+  if (i < n_cells) {
+    const int32_t c = colour_cells[i];
+    if (c < 0 || c >= n_cells) atomicOr(flag, 32);
+  }
+}
+
+__global__ void fill_kernel(int64_t n, double v, double* x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+__global__ void fill_i32_kernel(int64_t n, int32_t v, int32_t* x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+inline unsigned grid_for(int64_t work, int per_block) {
+  int64_t g = (work + per_block - 1) / per_block;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+int vk_pick_lpr(int64_t n_rows, int64_t nnz) {
+  const double avg = n_rows > 0 ? (double)nnz / (double)n_rows : 0.0;
+  if (avg >= 96) return 64;
+  if (avg >= 40) return 32;
+  if (avg >= 20) return 16;
+  if (avg >= 10) return 8;
+  return 4;
+}
+
+hipError_t launch_spmv(hipStream_t s, const vk_csr& A, int lpr, double alpha, const double* x, double beta,
+                       const double* z, double* y) {
+  if (A.n_rows == 0) return hipSuccess;
+  const unsigned grid = grid_for(A.n_rows * lpr, 256);
+  switch (lpr) {
+    case 4: spmv_kernel<4><<<grid, 256, 0, s>>>(A.n_rows, A.row_ptr, A.col, A.val, x, alpha, beta, z, y); break;
+    case 8: spmv_kernel<8><<<grid, 256, 0, s>>>(A.n_rows, A.row_ptr, A.col, A.val, x, alpha, beta, z, y); break;
+    case 16: spmv_kernel<16><<<grid, 256, 0, s>>>(A.n_rows, A.row_ptr, A.col, A.val, x, alpha, beta, z, y); break;
+    case 32: spmv_kernel<32><<<grid, 256, 0, s>>>(A.n_rows, A.row_ptr, A.col, A.val, x, alpha, beta, z, y); break;
+    default: spmv_kernel<64><<<grid, 256, 0, s>>>(A.n_rows, A.row_ptr, A.col, A.val, x, alpha, beta, z, y); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_validate_csr(hipStream_t s, const vk_csr& A, int32_t* flag) {
+  validate_csr_kernel<<<grid_for(A.n_rows + 1, 256), 256, 0, s>>>(A.n_rows, A.n_cols, A.nnz, A.row_ptr, A.col,
+                                                                    flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate_cells(hipStream_t s, int32_t n_cells, int32_t n_K, const int32_t* cell_dofs, int64_t n,
+                                 const int32_t* colour_cells, int32_t* flag) {
+  validate_cells_kernel<<<grid_for((int64_t)n_cells * n_K, 256), 256, 0, s>>>(n_cells, n_K, cell_dofs, n,
+                                                                              colour_cells, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(hipStream_t s, int64_t n, double v, double* x) {
+  if (n == 0) return hipSuccess;
+  unsigned g = grid_for(n, 256);
+  if (g > 4096) g = 4096;
+  fill_kernel<<<g, 256, 0, s>>>(n, v, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(hipStream_t s, int64_t n, int32_t v, int32_t* x) {
+  if (n == 0) return hipSuccess;
+  unsigned g = grid_for(n, 256);
+  if (g > 4096) g = 4096;
+  fill_i32_kernel<<<g, 256, 0, s>>>(n, v, x);
+  return hipGetLastError();
+}

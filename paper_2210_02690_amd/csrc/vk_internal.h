@@ -1,0 +1,130 @@
+// Internal declarations shared by the HIP translation units of libvk.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "vk.h"
+
+#define VK_NT 256  // threads per workgroup for the patch kernels
+
+// Largest patch width kept entirely in LDS during setup (FP64 n_K x n_K plus
+// small vectors must fit the 64 KiB a workgroup may always allocate).
+#define VK_LDS_SETUP_MAX_NK 88
+#define VK_MAX_NK 512
+#define VK_MAX_RESTART 64
+
+struct vk_level {
+  bool set = false;
+  vk_csr J{}, P{}, R{};
+  bool has_transfer = false;
+  int32_t n_cells = 0, n_K = 0;
+  const int32_t* cell_dofs = nullptr;
+  const int32_t* colour_cells = nullptr;
+  std::vector<int32_t> colour_ptr;  // host copy
+  int32_t n_colours = 0;
+  int32_t max_colour_cells = 0;
+  int32_t cpb_override = 0;
+  int lpr_J = 4, lpr_P = 4, lpr_R = 4;
+  // carved from the workspace
+  void* inv = nullptr;        // stored patch inverses
+  int32_t ld = 0;             // leading dimension (rows, padded)
+  int64_t cell_stride = 0;    // elements per cell
+  double* inv_p = nullptr;    // 1 / multiplicity
+  double* b = nullptr;        // V-cycle right-hand side (levels < L)
+  double* d = nullptr;        // V-cycle iterate (levels < L)
+  double* r = nullptr;        // defect scratch
+};
+
+struct vk_timing_rec {
+  int32_t kind, level, slot;
+};
+
+struct vk_ctx {
+  // per-launch event timing
+  bool timing = false;
+  int32_t timing_level = -1;
+  std::vector<hipEvent_t> ev;           // 2 * pool size, created on first enable
+  std::vector<vk_timing_rec> recs;
+  int32_t n_levels = 0;
+  hipStream_t stream = nullptr;
+  std::vector<vk_level> lv;
+  std::string err;
+  int32_t* status = nullptr;   // device status block (4 KiB)
+  double* host_buf = nullptr;  // pinned host readback buffer (4 KiB)
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_ready = false;
+  vk_prec prec = VK_F64;
+  int32_t restart = 0;
+  bool setup_done = false;
+  double omega = 0.7;
+  vk_mode mode = VK_ADDITIVE;
+  // coarse direct solve
+  double* c_inv = nullptr;   // FP64 inverse of J_0 (row-major)
+  double* c_tmp = nullptr;   // Gauss-Jordan ping-pong buffer
+  int32_t* c_perm = nullptr;
+  // setup scratch for patches too wide for LDS
+  double* big_scratch = nullptr;
+  int32_t big_chunk = 0;
+  // multiplicative sweep: per-cell local defects of one colour
+  double* rK = nullptr;
+  // Krylov
+  int64_t n_pad = 0;
+  double* V = nullptr;   // (restart + 1) vectors
+  double* Z = nullptr;   // restart vectors
+  double* H = nullptr;   // (restart + 1) x restart, column-major
+  double* h2 = nullptr;  // second CGS pass coefficients
+  double* cs = nullptr;
+  double* sn = nullptr;
+  double* g = nullptr;
+  double* y = nullptr;
+  double* partial = nullptr;  // block partial sums
+  double* scal = nullptr;     // device scalars
+  int32_t n_partial = 0;
+};
+
+// ---- launchers (defined in the .hip files) --------------------------------
+// sparse
+int vk_pick_lpr(int64_t n_rows, int64_t nnz);
+hipError_t launch_spmv(hipStream_t s, const vk_csr& A, int lpr, double alpha, const double* x,
+                       double beta, const double* z, double* y);
+hipError_t launch_validate_csr(hipStream_t s, const vk_csr& A, int32_t* flag);
+hipError_t launch_validate_cells(hipStream_t s, int32_t n_cells, int32_t n_K, const int32_t* cell_dofs,
+                                 int64_t n, const int32_t* colour_cells, int32_t* flag);
+hipError_t launch_fill(hipStream_t s, int64_t n, double v, double* x);
+hipError_t launch_fill_i32(hipStream_t s, int64_t n, int32_t v, int32_t* x);
+// patches
+hipError_t launch_multiplicity(hipStream_t s, int32_t n_cells, int32_t n_K, const int32_t* cell_dofs,
+                               int64_t n, int32_t* count, double* inv_p);
+hipError_t launch_patch_setup(hipStream_t s, const vk_level& L, vk_prec prec, double* big_scratch,
+                              int32_t big_chunk, int32_t* status);
+hipError_t launch_patch_apply(hipStream_t s, const vk_level& L, vk_prec prec, int32_t colour,
+                              const double* r, const double* rK, double* d, double omega, bool average);
+hipError_t launch_patch_residual(hipStream_t s, const vk_level& L, int32_t colour, const double* b,
+                                 const double* d, double* rK);
+hipError_t launch_patch_export(hipStream_t s, const vk_level& L, vk_prec prec, int32_t cell0, int32_t n,
+                               double* out);
+int vk_default_cpb(int32_t n_K, int32_t ld, vk_prec prec);
+int vk_prec_vw(vk_prec prec);
+int vk_prec_bytes(vk_prec prec);
+// coarse
+hipError_t launch_coarse_invert(hipStream_t s, const vk_csr& J0, double* inv, double* tmp, int32_t* perm,
+                                int32_t* status);
+hipError_t launch_dense_gemv(hipStream_t s, int64_t n, const double* A, const double* x, double* y);
+// Krylov
+hipError_t launch_dot(hipStream_t s, int64_t n, const double* x, const double* y, double* partial,
+                      int32_t n_partial, double* out, bool sqrt_out);
+hipError_t launch_mdot(hipStream_t s, int64_t n, const double* V, int64_t ldv, int32_t m, const double* w,
+                       double* partial, int32_t n_partial, double* out);
+hipError_t launch_maxpy(hipStream_t s, int64_t n, const double* V, int64_t ldv, int32_t m, const double* h,
+                        double sign, double* w);
+hipError_t launch_scale_by_inv(hipStream_t s, int64_t n, const double* x, const double* den, double* y);
+hipError_t launch_givens(hipStream_t s, int32_t j, int32_t ldh, double* H, const double* h2, double* cs,
+                         double* sn, double* g, double* out);
+hipError_t launch_gmres_init(hipStream_t s, int32_t m, double* H, double* g, const double* beta);
+hipError_t launch_trisolve(hipStream_t s, int32_t jn, int32_t ldh, const double* H, const double* g, double* y);

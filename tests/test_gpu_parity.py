@@ -1,0 +1,327 @@
+"""GPU parity of libvk against the FP64 CPU oracle, through the C ABI.
+
+Tolerances: FP64 paths 1e-10 relative (max-norm); patch inverses and the coarse
+inverse relative to their conditioning; FP32/BF16 patch storage 2e-5 against
+the oracle with identically rounded inverses (FP32 accumulation over n_K <= 84
+terms: n_K * 2^-24 ~ 5e-6, times a safety factor of 4); GMRES counts within
++-1 of the oracle and a true relative residual <= 1e-8.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from synth import build_problem  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def vk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2210_02690_amd as m
+    return m
+
+
+DEV = "cuda:0"
+
+CASES = {
+    # name: (config, overrides)
+    "cfg0": ("channel2d_44x8_k1", {}),
+    "ragged_k2": ("channel2d_44x8_k1", dict(shape=(10, 6), levels=2, k=2)),
+    "k3": ("channel2d_44x8_k1", dict(shape=(12, 4), levels=2, k=3)),
+}
+
+_cache = {}
+
+
+def problem(name):
+    if name not in _cache:
+        cfg, over = CASES[name] if name in CASES else (name, {})
+        P = build_problem(cfg, **over)
+        _cache[name] = (P, oracle.OracleHierarchy(P.levels))
+    return _cache[name]
+
+
+def make_solver(vk, P, prec="f64", mode="additive", restart=30):
+    S = vk.Solver([vk.upload_level(L, DEV) for L in P.levels])
+    S.vk_set_workspace(prec, restart, device=DEV)
+    S.vanka_setup(0.7, mode)
+    return S
+
+
+def t(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(DEV)
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_spmv(vk, case):
+    P, _ = problem(case)
+    S = make_solver(vk, P)
+    rng = np.random.default_rng(1)
+    for l, L in enumerate(P.levels):
+        x = rng.standard_normal(L.n)
+        y = torch.empty(L.n, dtype=torch.float64, device=DEV)
+        S.vk_spmv(l, t(x), y)
+        assert rel(y.cpu().numpy(), L.J @ x) <= 1e-13
+        z = rng.standard_normal(L.n)
+        S.vk_spmv(l, t(x), y, alpha=-1.0, beta=1.0, z=t(z))
+        assert rel(y.cpu().numpy(), z - L.J @ x) <= 1e-13
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_patch_inverses(vk, case):
+    P, H = problem(case)
+    S = make_solver(vk, P)
+    for l in range(1, len(P.levels)):
+        nc, nK = P.levels[l].mesh.n_cells, P.levels[l].mesh.n_K
+        out = torch.empty((nc, nK, nK), dtype=torch.float64, device=DEV)
+        S.vk_get_patch_inverses(l, 0, nc, out)
+        got = out.cpu().numpy()
+        err = np.abs(got - H.A[l]).max(axis=(1, 2)) / np.abs(H.A[l]).max(axis=(1, 2))
+        assert err.max() <= 1e-10, (l, err.max())
+
+
+@pytest.mark.parametrize("case", ["cfg0"])
+def test_coarse_inverse(vk, case):
+    P, _ = problem(case)
+    S = make_solver(vk, P)
+    J0 = P.levels[0].J.toarray()
+    n0 = J0.shape[0]
+    out = torch.empty((n0, n0), dtype=torch.float64, device=DEV)
+    S.vk_get_coarse_inverse(out)
+    ref = np.linalg.inv(J0)
+    kappa = np.linalg.cond(J0)
+    assert rel(out.cpu().numpy(), ref) <= 100 * kappa * np.finfo(float).eps
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("zero", [False, True])
+def test_smooth_additive(vk, case, zero):
+    P, H = problem(case)
+    S = make_solver(vk, P)
+    rng = np.random.default_rng(2)
+    for l in range(1, len(P.levels)):
+        L = P.levels[l]
+        b = rng.standard_normal(L.n)
+        d0 = np.zeros(L.n) if zero else rng.standard_normal(L.n)
+        d = t(d0)
+        _say(f"smooth additive {case} level {l} zero={zero}")
+        S.vanka_smooth(l, t(b), d, 2, d_is_zero=zero)
+        ref = H.smooth(l, b, d0, 2)
+        assert rel(d.cpu().numpy(), ref) <= 1e-10, (l, rel(d.cpu().numpy(), ref))
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_smooth_multiplicative(vk, case):
+    P, _ = problem(case)
+    Hm = oracle.OracleHierarchy(P.levels, mode="multiplicative", order="coloured")
+    S = make_solver(vk, P, mode="multiplicative")
+    rng = np.random.default_rng(3)
+    for l in range(1, len(P.levels)):
+        L = P.levels[l]
+        b = rng.standard_normal(L.n)
+        d0 = rng.standard_normal(L.n)
+        d = t(d0)
+        _say(f"smooth multiplicative {case} level {l}")
+        S.vanka_smooth(l, t(b), d, 2)
+        ref = Hm.smooth(l, b, d0, 2)
+        assert rel(d.cpu().numpy(), ref) <= 1e-10
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("nu", [(2, 2), (1, 0), (0, 1)])
+def test_vcycle(vk, case, nu):
+    P, H = problem(case)
+    S = make_solver(vk, P)
+    b = np.random.default_rng(4).standard_normal(P.finest.n)
+    x = torch.empty(P.finest.n, dtype=torch.float64, device=DEV)
+    _say(f"vcycle {case} nu={nu}")
+    S.vcycle(t(b), x, *nu)
+    ref = oracle.vcycle(H, b, *nu)
+    assert rel(x.cpu().numpy(), ref) <= 1e-10
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_gmres(vk, case):
+    P, H = problem(case)
+    S = make_solver(vk, P)
+    b = P.b
+    x = torch.zeros(P.finest.n, dtype=torch.float64, device=DEV)
+    _say(f"gmres {case}")
+    its, relres, hist, ok = S.gmres_solve(t(b), x, restart=30, max_iter=200, rtol=1e-8)
+    xo, its_o, hist_o, ok_o, rel_o = oracle.gmres(P.finest.J, b, lambda v: oracle.vcycle(H, v, 2, 2))
+    xg = x.cpu().numpy()
+    true_rel = np.linalg.norm(b - P.finest.J @ xg) / np.linalg.norm(b)
+    assert ok and ok_o
+    assert abs(its - its_o) <= 1, (its, its_o)
+    assert true_rel <= 1e-8 and abs(true_rel - relres) <= 1e-12
+    assert np.all(np.diff(hist) <= 0)
+    np.testing.assert_allclose(hist[: min(len(hist), len(hist_o)) - 1],
+                               hist_o[: min(len(hist), len(hist_o)) - 1], rtol=1e-6)
+
+
+@pytest.mark.parametrize("prec,store,tol_rounded,tol_f64", [("f32", oracle.round_f32, 2e-5, 1e-5),
+                                                           ("bf16", oracle.round_bf16, 2e-5, 2e-2)])
+def test_mixed_precision_sweep(vk, prec, store, tol_rounded, tol_f64):
+    P, H = problem("cfg0")
+    Hr = oracle.OracleHierarchy(P.levels, patch_store=store)
+    S = make_solver(vk, P, prec=prec)
+    rng = np.random.default_rng(5)
+    for l in range(1, len(P.levels)):
+        L = P.levels[l]
+        nc, nK = L.mesh.n_cells, L.mesh.n_K
+        out = torch.empty((nc, nK, nK), dtype=torch.float64, device=DEV)
+        S.vk_get_patch_inverses(l, 0, nc, out)
+        ulp = 2.0 ** -24 if prec == "f32" else 2.0 ** -8
+        a = np.abs(out.cpu().numpy() - Hr.A[l])
+        assert np.all(a <= 2 * ulp * np.abs(H.A[l]) + 1e-300), l
+        b = rng.standard_normal(L.n)
+        d0 = rng.standard_normal(L.n)
+        d = t(d0)
+        S.vanka_smooth(l, t(b), d, 1)
+        got = d.cpu().numpy()
+        assert rel(got, Hr.smooth(l, b, d0, 1)) <= tol_rounded
+        assert rel(got, H.smooth(l, b, d0, 1)) <= tol_f64
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_mixed_precision_gmres(vk, prec):
+    P, H = problem("cfg0")
+    S = make_solver(vk, P, prec=prec)
+    x = torch.zeros(P.finest.n, dtype=torch.float64, device=DEV)
+    its, relres, hist, ok = S.gmres_solve(t(P.b), x, restart=30, max_iter=200, rtol=1e-8)
+    true_rel = np.linalg.norm(P.b - P.finest.J @ x.cpu().numpy()) / np.linalg.norm(P.b)
+    _say(f"gmres {prec}: {its} its, true rel {true_rel:.2e}")
+    assert ok and true_rel <= 1e-8
+
+
+def test_error_paths(vk):
+    P, _ = problem("cfg0")
+    S = make_solver(vk, P)
+    b = t(P.b)
+    x = torch.zeros_like(b)
+    # b = 0 -> x = 0, zero iterations
+    x.fill_(1.0)
+    its, relres, hist, ok = S.gmres_solve(torch.zeros_like(b), x)
+    assert ok and its == 0 and float(x.abs().max()) == 0.0
+    # max_iter = 1 -> no convergence, reported
+    x.zero_()
+    its, relres, hist, ok = S.gmres_solve(b, x, max_iter=1, raise_on_noconv=False)
+    assert not ok and its == 1 and relres > 1e-8
+    with pytest.raises(vk.VkError) as e:
+        S.gmres_solve(b, x, max_iter=1)
+    assert e.value.status == vk.VK_ERR_NOCONV
+    # level 0 is solved directly, not smoothed
+    with pytest.raises(vk.VkError) as e:
+        S.vanka_smooth(0, b[:P.levels[0].n], x[:P.levels[0].n], 1)
+    assert e.value.status == vk.VK_ERR_ARG
+    # restart larger than the workspace's
+    with pytest.raises(vk.VkError):
+        S.gmres_solve(b, x, restart=40)
+
+
+def test_state_and_workspace_errors(vk):
+    P, _ = problem("cfg0")
+    S = vk.Solver([vk.upload_level(L, DEV) for L in P.levels])
+    b = t(P.b)
+    x = torch.zeros_like(b)
+    with pytest.raises(vk.VkError) as e:
+        S.vcycle(b, x)
+    assert e.value.status == vk.VK_ERR_WORKSPACE
+    need = S.vk_workspace_bytes("f64", 30)
+    ws = torch.empty(need, dtype=torch.uint8, device=DEV)
+    import ctypes
+    st = vk.lib().vk_set_workspace(S.ctx, ctypes.c_void_p(ws.data_ptr()), need - 4096, vk.VK_F64, 30)
+    assert st == vk.VK_ERR_WORKSPACE
+    S.vk_set_workspace("f64", 30, device=DEV)
+    with pytest.raises(vk.VkError) as e:
+        S.vcycle(b, x)
+    assert e.value.status == vk.VK_ERR_STATE
+
+
+def test_singular_patch_reported(vk):
+    P = build_problem("channel2d_44x8_k1", shape=(8, 4), levels=2)
+    L = P.finest
+    J = L.J.tolil()
+    cell = 5
+    pdof = int(L.cell_dofs[cell][18])   # a pressure DoF: it belongs to this cell only
+    J[pdof, :] = 0.0
+    J = J.tocsr()
+    J.eliminate_zeros()
+    J.sort_indices()
+    L.J = J
+    S = vk.Solver([vk.upload_level(Lv, DEV) for Lv in P.levels])
+    S.vk_set_workspace("f64", 30, device=DEV)
+    with pytest.raises(vk.VkError) as e:
+        S.vanka_setup(0.7)
+    assert e.value.status == vk.VK_ERR_SINGULAR
+    assert e.value.bad_level == 1 and e.value.bad_cell == cell
+
+
+def test_malformed_csr_rejected(vk):
+    P = build_problem("channel2d_44x8_k1", shape=(8, 4), levels=2)
+    lv = [vk.upload_level(L, DEV) for L in P.levels]
+    col = lv[1]["J"]["col"].clone()
+    col[3], col[4] = lv[1]["J"]["col"][4], lv[1]["J"]["col"][3]     # unsorted row
+    bad = dict(lv[1])
+    bad["J"] = dict(lv[1]["J"], col=col)
+    with pytest.raises(vk.VkError) as e:
+        vk.Solver([lv[0], bad])
+    assert e.value.status == vk.VK_ERR_ARG
+    col2 = lv[1]["J"]["col"].clone()
+    col2[7] = P.finest.n + 5                                           # out of range
+    bad["J"] = dict(lv[1]["J"], col=col2)
+    with pytest.raises(vk.VkError) as e:
+        vk.Solver([lv[0], bad])
+    assert e.value.status == vk.VK_ERR_ARG
+    cd = lv[1]["cell_dofs"].clone()
+    cd[0, 0] = -1
+    bad = dict(lv[1], cell_dofs=cd)
+    with pytest.raises(vk.VkError) as e:
+        vk.Solver([lv[0], bad])
+    assert e.value.status == vk.VK_ERR_ARG
+
+
+def test_timing_counts(vk):
+    P, _ = problem("cfg0")
+    S = make_solver(vk, P)
+    S.vk_timing_enable(True)
+    L = P.finest
+    d = torch.zeros(L.n, dtype=torch.float64, device=DEV)
+    S.vanka_smooth(len(P.levels) - 1, t(P.b), d, 3, d_is_zero=True)
+    n, ms = S.vk_timing_read("patch_apply", len(P.levels) - 1)
+    assert n == 3 * 4 and ms > 0
+    n, ms = S.vk_timing_read("spmv", len(P.levels) - 1)
+    assert n == 2
+    S.vk_timing_enable(False)
+
+
+@pytest.mark.parametrize("tile", [1, 2, 4, 8])
+def test_patch_tiles_agree(vk, tile):
+    P, H = problem("ragged_k2")
+    S = make_solver(vk, P)
+    l = len(P.levels) - 1
+    try:
+        S.vk_set_patch_tile(l, tile)
+    except vk.VkError:
+        pytest.skip("tile too narrow for this patch")
+    rng = np.random.default_rng(6)
+    b = rng.standard_normal(P.finest.n)
+    d0 = rng.standard_normal(P.finest.n)
+    d = t(d0)
+    S.vanka_smooth(l, t(b), d, 1)
+    assert rel(d.cpu().numpy(), H.smooth(l, b, d0, 1)) <= 1e-10
