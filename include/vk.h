@@ -76,6 +76,8 @@ typedef struct vk_ctx vk_ctx;
  * stream).  Allocates the 4 KiB device status block. */
 vk_status vk_create(vk_ctx** ctx, int32_t n_levels, void* hip_stream);
 void vk_destroy(vk_ctx* ctx);
+/* Message of the last failure on ctx; with ctx == NULL, of the last failed
+ * vk_create in the process. */
 const char* vk_last_error(const vk_ctx* ctx);
 
 /* Describe level l.

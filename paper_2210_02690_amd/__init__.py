@@ -11,6 +11,10 @@ import os
 import re
 
 import numpy as np
+# torch ships its own HIP runtime (libamdhip64.so.7).  It must be the one that
+# satisfies libvk.so's dependency: loading libvk.so first would map the system
+# runtime as well, and two HIP runtimes in one process do not share devices.
+import torch  # noqa: F401
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libvk.so")
@@ -137,7 +141,7 @@ class Solver:
         ctx = _P()
         st = _lib.vk_create(ctypes.byref(ctx), len(levels), _stream_handle(stream))
         if st != VK_OK:
-            raise VkError(st, "vk_create failed")
+            raise VkError(st, "vk_create failed: " + _lib.vk_last_error(None).decode())
         self.ctx = ctx
         for l, lv in enumerate(levels):
             J = csr_struct(lv["J"])

@@ -207,10 +207,16 @@ vk_status vcycle_level(vk_ctx* ctx, int l, const double* b, double* x, int32_t n
 }
 
 vk_status read_scalars(vk_ctx* ctx, const double* dev, int count, double* out) {
-  VK_TRY(hipMemcpyAsync(ctx->host_buf, dev, sizeof(double) * count, hipMemcpyDeviceToHost, ctx->stream));
+  VK_TRY(hipMemcpyAsync(out, dev, sizeof(double) * count, hipMemcpyDeviceToHost, ctx->stream));
   VK_TRY(hipStreamSynchronize(ctx->stream));
-  for (int i = 0; i < count; ++i) out[i] = ctx->host_buf[i];
   return VK_OK;
+}
+
+char g_create_err[256] = "";
+
+vk_status create_fail(vk_status st, const char* msg) {
+  snprintf(g_create_err, sizeof(g_create_err), "%s", msg);
+  return st;
 }
 
 vk_status ready(vk_ctx* ctx) {
@@ -225,22 +231,21 @@ vk_status ready(vk_ctx* ctx) {
 extern "C" {
 
 vk_status vk_create(vk_ctx** out, int32_t n_levels, void* hip_stream) {
-  if (!out) return VK_ERR_ARG;
+  if (!out) return create_fail(VK_ERR_ARG, "null output pointer");
   *out = nullptr;
-  if (n_levels < 1 || n_levels > 32) return VK_ERR_ARG;
+  if (n_levels < 1 || n_levels > 32) return create_fail(VK_ERR_ARG, "n_levels must be in [1, 32]");
   vk_ctx* ctx = new (std::nothrow) vk_ctx;
-  if (!ctx) return VK_ERR_ARG;
+  if (!ctx) return create_fail(VK_ERR_ARG, "host allocation failed");
   ctx->n_levels = n_levels;
   ctx->lv.resize(n_levels);
   ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  if (hipMalloc(&ctx->status, 4096) != hipSuccess) {
+  const hipError_t e = hipMalloc(&ctx->status, 4096);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();  // do not leave the error for the caller's next check
     delete ctx;
-    return VK_ERR_HIP;
-  }
-  if (hipHostMalloc(reinterpret_cast<void**>(&ctx->host_buf), 4096, hipHostMallocDefault) != hipSuccess) {
-    (void)hipFree(ctx->status);
-    delete ctx;
-    return VK_ERR_HIP;
+    char buf[256];
+    snprintf(buf, sizeof(buf), "hipMalloc of the status block failed: %s", hipGetErrorString(e));
+    return create_fail(VK_ERR_HIP, buf);
   }
   *out = ctx;
   return VK_OK;
@@ -252,11 +257,10 @@ void vk_destroy(vk_ctx* ctx) {
   else (void)hipDeviceSynchronize();
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
   if (ctx->status) (void)hipFree(ctx->status);
-  if (ctx->host_buf) (void)hipHostFree(ctx->host_buf);
   delete ctx;
 }
 
-const char* vk_last_error(const vk_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char* vk_last_error(const vk_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_err; }
 
 vk_status vk_set_level(vk_ctx* ctx, int32_t l, const vk_csr* J, const vk_csr* P, const vk_csr* R, int32_t n_cells,
                        int32_t n_K, const int32_t* cell_dofs, const int32_t* colour_cells,
@@ -388,9 +392,8 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
   }
   VK_TRY(launch_coarse_invert(s, ctx->lv[0].J, ctx->c_inv, ctx->c_tmp, ctx->c_perm, ctx->status));
   int32_t st[64];
-  VK_TRY(hipMemcpyAsync(ctx->host_buf, ctx->status, sizeof(int32_t) * 64, hipMemcpyDeviceToHost, s));
+  VK_TRY(hipMemcpyAsync(st, ctx->status, sizeof(int32_t) * 64, hipMemcpyDeviceToHost, s));
   VK_TRY(hipStreamSynchronize(s));
-  memcpy(st, ctx->host_buf, sizeof(st));
   if (st[0] != INT_MAX) {
     if (bad_level) *bad_level = 0;
     if (bad_cell) *bad_cell = -1;

@@ -54,7 +54,6 @@ struct vk_ctx {
   std::vector<vk_level> lv;
   std::string err;
   int32_t* status = nullptr;   // device status block (4 KiB)
-  double* host_buf = nullptr;  // pinned host readback buffer (4 KiB)
   // workspace
   char* ws = nullptr;
   size_t ws_bytes = 0;

@@ -187,8 +187,12 @@ def test_mixed_precision_sweep(vk, prec, store, tol_rounded, tol_f64):
         out = torch.empty((nc, nK, nK), dtype=torch.float64, device=DEV)
         S.vk_get_patch_inverses(l, 0, nc, out)
         ulp = 2.0 ** -24 if prec == "f32" else 2.0 ** -8
+        # both sides round an FP64 inverse; the two FP64 inverses agree to 1e-10 of the
+        # cell's largest entry (see test_patch_inverses), so the stored values agree to
+        # one rounding step plus that
         a = np.abs(out.cpu().numpy() - Hr.A[l])
-        assert np.all(a <= 2 * ulp * np.abs(H.A[l]) + 1e-300), l
+        cell_max = np.abs(H.A[l]).max(axis=(1, 2), keepdims=True)
+        assert np.all(a <= 2 * ulp * np.abs(H.A[l]) + 1e-10 * cell_max), l
         b = rng.standard_normal(L.n)
         d0 = rng.standard_normal(L.n)
         d = t(d0)
