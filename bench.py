@@ -37,12 +37,14 @@ def cells_sweeps_per_vcycle(P, nu1, nu2):
     return sum(L.mesh.n_cells for L in P.levels[1:]) * (nu1 + nu2)
 
 
-def patch_apply_bytes(L, prec, cells):
-    """Algorithmic bytes of one additive patch-apply launch over `cells` cells:
-    A_K (n_K^2 entries), the cell's DoF list (int32), the gathered defect, the
-    read and write of d, and 1/p, all per DoF of the cell; plus the cell id."""
+def patch_gemv_bytes(L, prec):
+    """Algorithmic bytes of one patch-GEMV launch (all cells of level L):
+    per cell the n_K^2 stored entries of A_K, the cell's DoF list (int32), the
+    gathered defect entries (FP64) and the written products y_K (FP64 for FP64
+    storage, FP32 otherwise)."""
     nK = L.mesh.n_K
-    return cells * (nK * nK * PREC_BYTES[prec] + nK * (4 + 8 + 8 + 8 + 8) + 4)
+    y_bytes = 8 if prec == "f64" else 4
+    return L.mesh.n_cells * (nK * nK * PREC_BYTES[prec] + nK * (4 + 8 + y_bytes))
 
 
 def run_step(S, b, x, nu, restart, max_iter):
@@ -161,15 +163,16 @@ def main():
         total_its += its
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    n_apply, ms_apply = S.vk_timing_read("patch_apply", l_fine)
+    n_apply, ms_apply = S.vk_timing_read("patch_gemv", l_fine)
+    n_gather, ms_gather = S.vk_timing_read("dof_gather", l_fine)
+    n_spmv, ms_spmv = S.vk_timing_read("spmv", l_fine)
     S.vk_timing_enable(False)
     log(f"[bench] timed {args.steps} steps in {dt:.3f} s, {total_its} GMRES its")
     value = total_its * cs_per_vc / dt
     ms_per_step = dt / args.steps * 1e3
 
-    # roofline of the dominant kernel: finest-level patch apply, one colour per launch
-    cells_per_launch = fine.mesh.n_cells / fine.mesh.n_colours
-    bytes_launch = patch_apply_bytes(fine, args.prec, cells_per_launch)
+    # roofline of the dominant kernel: the finest-level patch GEMV (all cells)
+    bytes_launch = patch_gemv_bytes(fine, args.prec)
     avg_ms = ms_apply / max(n_apply, 1)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
 
@@ -189,8 +192,10 @@ def main():
         "gmres_ms_to_1e-8": gmres_ms, "setup_ms": setup_ms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "patch_apply (finest level, one colour per launch)",
+                     "kernel": "patch_gemv (finest level, all cells per launch)",
                      "bytes_per_launch": bytes_launch, "avg_launch_ms": avg_ms, "launches": n_apply},
+        "finest_level_kernels_avg_ms": {"patch_gemv": avg_ms, "dof_gather": ms_gather / max(n_gather, 1),
+                                        "spmv": ms_spmv / max(n_spmv, 1)},
     }
     try:
         out["finest_sweep_rate"] = {args.prec: sweep_rate(torch, S, P, P.b)}

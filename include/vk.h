@@ -170,6 +170,22 @@ vk_status vk_set_patch_tile(vk_ctx* ctx, int32_t l, int32_t cells_per_block);
  * leading dimension used (the inverse is stored column by column). */
 vk_status vk_patch_layout(const vk_ctx* ctx, int32_t l, int64_t* bytes_per_cell, int32_t* ld);
 
+/* Implementation of the averaged additive sweep (both compute Eq. 3.5):
+ * VK_SWEEP_DOF_GATHER (default): one launch computes y_K = A_K R_K r for all
+ *   cells, a second forms z_mu = sum over the cells containing mu of their y
+ *   entry (ascending cell order) and d_mu += omega z_mu / p_mu.  Deterministic;
+ *   needs no colouring.
+ * VK_SWEEP_COLOURED_SCATTER: one launch per colour, each cell adding
+ *   omega y_K / p to its DoFs directly (cells of a colour share no DoF). */
+typedef enum { VK_SWEEP_DOF_GATHER = 0, VK_SWEEP_COLOURED_SCATTER = 1 } vk_sweep_variant;
+vk_status vk_set_sweep_variant(vk_ctx* ctx, int32_t variant);
+
+/* Patch inversion kernel used by vanka_setup: 0 (default) keeps one patch row
+ * per lane in registers where a kernel for the patch width is compiled
+ * (n_K = 42, 63, 84), 1 always uses the LDS / global-memory kernel.  Both
+ * compute the same Gauss-Jordan inverse; setup must run again after a change. */
+vk_status vk_set_setup_variant(vk_ctx* ctx, int32_t variant);
+
 /* ---- per-launch timing (benchmarks) --------------------------------------
  * With timing enabled, the library brackets every launch of the kernel classes
  * below with a pair of HIP events on the context's stream (a pool of 16384
@@ -182,7 +198,9 @@ typedef enum {
   VK_KERNEL_PATCH_APPLY = 0,    /* gather - patch GEMV - scatter, one colour */
   VK_KERNEL_SPMV = 1,           /* level defect b - J d */
   VK_KERNEL_PATCH_SETUP = 2,    /* patch gather + Gauss-Jordan inverse */
-  VK_KERNEL_PATCH_RESIDUAL = 3  /* multiplicative mode local defects */
+  VK_KERNEL_PATCH_RESIDUAL = 3, /* multiplicative mode local defects */
+  VK_KERNEL_PATCH_GEMV = 4,     /* y_K = A_K r_K for all cells (additive, DoF gather) */
+  VK_KERNEL_DOF_GATHER = 5      /* d += omega z / p from the y_K (additive, DoF gather) */
 } vk_kernel_kind;
 vk_status vk_timing_enable(vk_ctx* ctx, int32_t enable, int32_t level);
 vk_status vk_timing_read(vk_ctx* ctx, int32_t kind, int32_t l, int64_t* launches, double* total_ms);

@@ -60,9 +60,13 @@ _SIGS = {
     "vk_set_patch_tile": (ctypes.c_int, [_P, _I32, _I32]),
     "vk_patch_layout": (ctypes.c_int, [_P, _I32, _PI64, _PI32]),
     "vk_timing_enable": (ctypes.c_int, [_P, _I32, _I32]),
+    "vk_set_sweep_variant": (ctypes.c_int, [_P, _I32]),
+    "vk_set_setup_variant": (ctypes.c_int, [_P, _I32]),
     "vk_timing_read": (ctypes.c_int, [_P, _I32, _I32, _PI64, _PD]),
 }
-KERNEL_KINDS = {"patch_apply": 0, "spmv": 1, "patch_setup": 2, "patch_residual": 3}
+KERNEL_KINDS = {"patch_apply": 0, "spmv": 1, "patch_setup": 2, "patch_residual": 3, "patch_gemv": 4,
+                "dof_gather": 5}
+SWEEP_VARIANTS = {"dof_gather": 0, "coloured_scatter": 1}
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
     _f.restype = _res
@@ -228,6 +232,12 @@ class Solver:
 
     def vk_set_patch_tile(self, l, cells_per_block):
         self._check(_lib.vk_set_patch_tile(self.ctx, l, cells_per_block))
+
+    def vk_set_sweep_variant(self, variant):
+        self._check(_lib.vk_set_sweep_variant(self.ctx, SWEEP_VARIANTS[variant]))
+
+    def vk_set_setup_variant(self, variant):
+        self._check(_lib.vk_set_setup_variant(self.ctx, variant))
 
     def vk_timing_enable(self, enable=True, level=-1):
         self._check(_lib.vk_timing_enable(self.ctx, 1 if enable else 0, level))

@@ -20,6 +20,8 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
+    # the register-resident elimination loops are unrolled completely (k indexes registers)
+    "-mllvm", "-pragma-unroll-threshold=2000000",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 

@@ -84,7 +84,7 @@ size_t plan_workspace(vk_ctx* ctx, vk_prec prec, int32_t restart, char* base) {
   const int nl = ctx->n_levels;
   const int vw = vk_prec_vw(prec), sb = vk_prec_bytes(prec);
   int32_t big_nk = 0, big_cells = 0;
-  int64_t rk = 0;
+  int64_t rk = 0, ycount = 0;
   for (int l = 0; l < nl; ++l) {
     vk_level& L = ctx->lv[l];
     const int64_t n = L.J.n_rows;
@@ -96,6 +96,9 @@ size_t plan_workspace(vk_ctx* ctx, vk_prec prec, int32_t restart, char* base) {
     L.cell_stride = (int64_t)L.n_K * L.ld;
     L.inv = cv.take<char>((int64_t)L.n_cells * L.cell_stride * sb);
     L.inv_p = cv.take<double>(n);
+    L.dof_off = cv.take<int32_t>(n + 1);
+    L.dof_list = cv.take<int32_t>((int64_t)L.n_cells * L.n_K);
+    if ((int64_t)L.n_cells * L.n_K > ycount) ycount = (int64_t)L.n_cells * L.n_K;
     if (L.n_K > VK_LDS_SETUP_MAX_NK) {
       if (L.n_K > big_nk) big_nk = L.n_K;
       if (L.n_cells > big_cells) big_cells = L.n_cells;
@@ -119,6 +122,7 @@ size_t plan_workspace(vk_ctx* ctx, vk_prec prec, int32_t restart, char* base) {
     ctx->big_scratch = nullptr;
   }
   ctx->rK = cv.take<double>(rk > 0 ? rk : 1);
+  ctx->Y = cv.take<double>(ycount > 0 ? ycount : 1);
   const int64_t nL = ctx->lv[nl - 1].J.n_rows;
   ctx->n_pad = round_up(nL, 32);
   const int32_t m = restart;
@@ -166,9 +170,18 @@ vk_status smooth(vk_ctx* ctx, int l, const double* b, double* d, int32_t sweeps,
         VK_TRY(launch_spmv(s, L.J, L.lpr_J, -1.0, d, 1.0, b, L.r));
         r = L.r;
       }
-      for (int c = 0; c < L.n_colours; ++c) {
-        Timed t(ctx, VK_KERNEL_PATCH_APPLY, l);
-        VK_TRY(launch_patch_apply(s, L, ctx->prec, c, r, nullptr, d, ctx->omega, true));
+      if (ctx->sweep_variant == 0) {
+        {
+          Timed t(ctx, VK_KERNEL_PATCH_GEMV, l);
+          VK_TRY(launch_patch_gemv(s, L, ctx->prec, r, ctx->Y));
+        }
+        Timed t(ctx, VK_KERNEL_DOF_GATHER, l);
+        VK_TRY(launch_dof_gather(s, L, ctx->prec, ctx->Y, ctx->omega, d));
+      } else {
+        for (int c = 0; c < L.n_colours; ++c) {
+          Timed t(ctx, VK_KERNEL_PATCH_APPLY, l);
+          VK_TRY(launch_patch_apply(s, L, ctx->prec, c, r, nullptr, d, ctx->omega, true));
+        }
       }
     } else {
       for (int c = 0; c < L.n_colours; ++c) {
@@ -187,7 +200,7 @@ vk_status smooth(vk_ctx* ctx, int l, const double* b, double* d, int32_t sweeps,
 vk_status vcycle_level(vk_ctx* ctx, int l, const double* b, double* x, int32_t nu1, int32_t nu2) {
   hipStream_t s = ctx->stream;
   if (l == 0) {
-    VK_TRY(launch_dense_gemv(s, ctx->lv[0].J.n_rows, ctx->c_inv, b, x));
+    VK_TRY(launch_coarse_apply(s, ctx->lv[0].J.n_rows, ctx->c_W, ctx->c_perm, b, x));
     return VK_OK;
   }
   vk_level& L = ctx->lv[l];
@@ -270,6 +283,8 @@ vk_status vk_set_level(vk_ctx* ctx, int32_t l, const vk_csr* J, const vk_csr* P,
   if (!csr_ok(J) || J->n_rows != J->n_cols || J->n_rows == 0)
     return fail(ctx, VK_ERR_ARG, "J must be a non-empty square CSR matrix with valid pointers");
   if (J->n_rows > INT32_MAX) return fail(ctx, VK_ERR_ARG, "J too large for int32 columns");
+  if (l == 0 && J->n_rows > vk_coarse_max_n())
+    return fail(ctx, VK_ERR_ARG, "the coarsest level exceeds the dense direct solver's limit of 15360 unknowns");
   vk_level L;
   L.J = *J;
   if (l > 0) {
@@ -387,10 +402,13 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
     vk_level& L = ctx->lv[l];
     VK_TRY(launch_multiplicity(s, L.n_cells, L.n_K, L.cell_dofs, L.J.n_rows, reinterpret_cast<int32_t*>(L.r),
                                L.inv_p));
+    VK_TRY(launch_dof_map(s, L, reinterpret_cast<int32_t*>(L.r), L.dof_off, L.dof_list));
     Timed t(ctx, VK_KERNEL_PATCH_SETUP, l);
-    VK_TRY(launch_patch_setup(s, L, ctx->prec, ctx->big_scratch, ctx->big_chunk, ctx->status + l));
+    bool handled = false;
+    if (ctx->fast_setup) VK_TRY(launch_patch_setup_fast(s, L, ctx->prec, ctx->status + l, &handled));
+    if (!handled) VK_TRY(launch_patch_setup(s, L, ctx->prec, ctx->big_scratch, ctx->big_chunk, ctx->status + l));
   }
-  VK_TRY(launch_coarse_invert(s, ctx->lv[0].J, ctx->c_inv, ctx->c_tmp, ctx->c_perm, ctx->status));
+  VK_TRY(launch_coarse_invert(s, ctx->lv[0].J, ctx->c_inv, ctx->c_tmp, ctx->c_perm, ctx->status, &ctx->c_W));
   int32_t st[64];
   VK_TRY(hipMemcpyAsync(st, ctx->status, sizeof(int32_t) * 64, hipMemcpyDeviceToHost, s));
   VK_TRY(hipStreamSynchronize(s));
@@ -543,7 +561,7 @@ vk_status vk_get_coarse_inverse(vk_ctx* ctx, double* out) {
   VK_CHECK(ready(ctx));
   if (!out) return fail(ctx, VK_ERR_ARG, "null output");
   const int64_t n0 = ctx->lv[0].J.n_rows;
-  VK_TRY(hipMemcpyAsync(out, ctx->c_inv, (size_t)(n0 * n0) * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  VK_TRY(launch_coarse_export(ctx->stream, n0, ctx->c_W, ctx->c_perm, out));
   return VK_OK;
 }
 
@@ -565,6 +583,22 @@ vk_status vk_patch_layout(const vk_ctx* ctx, int32_t l, int64_t* bytes_per_cell,
   const vk_level& L = ctx->lv[l];
   if (bytes_per_cell) *bytes_per_cell = L.cell_stride * vk_prec_bytes(ctx->prec);
   if (ld) *ld = L.ld;
+  return VK_OK;
+}
+
+vk_status vk_set_sweep_variant(vk_ctx* ctx, int32_t variant) {
+  if (!ctx) return VK_ERR_ARG;
+  if (variant != VK_SWEEP_DOF_GATHER && variant != VK_SWEEP_COLOURED_SCATTER)
+    return fail(ctx, VK_ERR_ARG, "unknown sweep variant");
+  ctx->sweep_variant = variant;
+  return VK_OK;
+}
+
+vk_status vk_set_setup_variant(vk_ctx* ctx, int32_t variant) {
+  if (!ctx) return VK_ERR_ARG;
+  if (variant != 0 && variant != 1) return fail(ctx, VK_ERR_ARG, "unknown setup variant");
+  ctx->fast_setup = variant == 0;
+  ctx->setup_done = false;
   return VK_OK;
 }
 

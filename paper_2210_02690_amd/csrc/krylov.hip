@@ -63,12 +63,15 @@ __global__ __launch_bounds__(RB) void mdot_partial_kernel(int64_t n, const doubl
   }
 }
 
-__global__ void mreduce_kernel(int32_t nb, int32_t m, const double* __restrict__ partial, double* out) {
-  const int i = threadIdx.x;
-  if (i >= m) return;
+// out[i] = sum_b partial[b * m + i]; one workgroup per coefficient i
+__global__ __launch_bounds__(RB) void mreduce_kernel(int32_t nb, int32_t m, const double* __restrict__ partial,
+                                                     double* out) {
+  __shared__ double sh[RB / 64];
+  const int i = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += partial[(int64_t)b * m + i];
-  out[i] = s;
+  for (int b = threadIdx.x; b < nb; b += RB) s += partial[(int64_t)b * m + i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[i] = s;
 }
 
 // w += sign * sum_i h_i V_i
@@ -151,7 +154,10 @@ inline unsigned grid_n(int64_t n, int cap) {
 
 hipError_t launch_dot(hipStream_t s, int64_t n, const double* x, const double* y, double* partial,
                       int32_t n_partial, double* out, bool sqrt_out) {
-  const unsigned g = grid_n(n, n_partial);
+  unsigned g = (unsigned)((n + RB * 4 - 1) / (RB * 4));
+  if (g < 1) g = 1;
+  if (g > 1024) g = 1024;
+  if (g > (unsigned)n_partial) g = (unsigned)n_partial;
   dot_partial_kernel<<<g, RB, 0, s>>>(n, x, y, partial);
   reduce_kernel<<<1, RB, 0, s>>>((int32_t)g, partial, out, sqrt_out ? 1 : 0);
   return hipGetLastError();
@@ -161,12 +167,15 @@ hipError_t launch_mdot(hipStream_t s, int64_t n, const double* V, int64_t ldv, i
                        double* partial, int32_t n_partial, double* out) {
   int cap = n_partial / (m > 0 ? m : 1);
   if (cap < 1) cap = 1;
-  const unsigned g = grid_n(n, cap < 1024 ? cap : 1024);
+  if (cap > 256) cap = 256;
+  unsigned g = (unsigned)((n + RB * 4 - 1) / (RB * 4));
+  if (g < 1) g = 1;
+  if (g > (unsigned)cap) g = (unsigned)cap;
   if (m <= 8) mdot_partial_kernel<8><<<g, RB, 0, s>>>(n, V, ldv, m, w, partial);
   else if (m <= 16) mdot_partial_kernel<16><<<g, RB, 0, s>>>(n, V, ldv, m, w, partial);
   else if (m <= 32) mdot_partial_kernel<32><<<g, RB, 0, s>>>(n, V, ldv, m, w, partial);
   else mdot_partial_kernel<VK_MAX_RESTART + 1><<<g, RB, 0, s>>>(n, V, ldv, m, w, partial);
-  mreduce_kernel<<<1, 128, 0, s>>>((int32_t)g, m, partial, out);
+  mreduce_kernel<<<(unsigned)m, RB, 0, s>>>((int32_t)g, m, partial, out);
   return hipGetLastError();
 }
 

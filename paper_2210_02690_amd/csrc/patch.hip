@@ -466,3 +466,335 @@ hipError_t launch_patch_export(hipStream_t s, const vk_level& L, vk_prec prec, i
   }
   return hipGetLastError();
 }
+
+// ===========================================================================
+// Setup with one lane per patch row, rows held in registers (n_K = N known at
+// compile time).  Gauss-Jordan elimination with implicit partial pivoting: at
+// step k the pivot is the not-yet-used row with the largest |value| in column
+// k (first such row on ties); rows never move.  With q_k the pivot row of
+// step k, the stored rows W satisfy J_K^{-1}[k][q_j] = W[q_k][j].
+// The patch rows are staged through LDS in chunks of CH rows (the gather
+// scatters CSR entries by column, which registers cannot be indexed by).
+// ===========================================================================
+namespace {
+
+template <int N> struct RowCfg {
+  static constexpr int W = (N + 63) / 64;          // wavefronts per cell
+  static constexpr int CH = 16;                    // staged rows per chunk (<= 11 KiB of LDS)
+};
+
+template <int P, int N>
+__global__ __launch_bounds__(64 * RowCfg<N>::W) void patch_setup_rows_kernel(
+    const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const double* __restrict__ val,
+    const int32_t* __restrict__ cell_dofs, void* inv_out, int32_t ld, int64_t cell_stride, int32_t* status) {
+  constexpr int W = RowCfg<N>::W, CH = RowCfg<N>::CH, NT = 64 * W;
+  __shared__ int sdof[N], skey[N], sloc[N], qs[N];
+  __shared__ double stage[CH * N];
+  __shared__ double prow_s[N];
+  __shared__ double red_abs[W];
+  __shared__ int red_idx[W];
+  __shared__ int s_p;
+  const int K = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < N; i += NT) {
+    sdof[i] = cell_dofs[(int64_t)K * N + i];
+    skey[i] = 0x7fffffff;
+    sloc[i] = 0;
+  }
+  __syncthreads();
+  for (int i = tid; i < N; i += NT) {
+    const int v = sdof[i];
+    int rank = 0;
+    for (int j = 0; j < N; ++j) rank += (sdof[j] < v) ? 1 : 0;
+    skey[rank] = v;
+    sloc[rank] = i;
+  }
+  double row[N];
+#pragma unroll
+  for (int c = 0; c < N; ++c) row[c] = 0.0;
+#pragma unroll
+  for (int r0 = 0; r0 < N; r0 += CH) {
+    __syncthreads();
+    for (int e = tid; e < CH * N; e += NT) stage[e] = 0.0;
+    __syncthreads();
+    for (int rr = wave; rr < CH && r0 + rr < N; rr += W) {
+      const int64_t grow = sdof[r0 + rr];
+      const int64_t e1 = row_ptr[grow + 1];
+      for (int64_t e = row_ptr[grow] + lane; e < e1; e += 64) {
+        const int c = col[e];
+        int lo = 0, hi = N;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (skey[mid] < c) lo = mid + 1; else hi = mid;
+        }
+        if (lo < N && skey[lo] == c) stage[rr * N + sloc[lo]] = val[e];
+      }
+    }
+    __syncthreads();
+    if (tid >= r0 && tid < r0 + CH && tid < N) {
+#pragma unroll
+      for (int c = 0; c < N; ++c) row[c] = stage[(tid - r0) * N + c];
+    }
+  }
+  const bool mine = tid < N;
+  bool used = !mine;
+  bool singular = false;
+  int my_step = 0;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    double a = used ? -1.0 : fabs(row[k]);
+    int ai = used ? 0x7fffffff : tid;
+    for (int o = 32; o > 0; o >>= 1) {
+      const double oa = __shfl_xor(a, o, 64);
+      const int oi = __shfl_xor(ai, o, 64);
+      if (oa > a || (oa == a && oi < ai)) { a = oa; ai = oi; }
+    }
+    if (W > 1) {
+      if (lane == 0) { red_abs[wave] = a; red_idx[wave] = ai; }
+      __syncthreads();
+      a = red_abs[0];
+      ai = red_idx[0];
+#pragma unroll
+      for (int w = 1; w < W; ++w) {
+        const double oa = red_abs[w];
+        const int oi = red_idx[w];
+        if (oa > a || (oa == a && oi < ai)) { a = oa; ai = oi; }
+      }
+    }
+    const int p = ai;  // uniform across the workgroup
+    const bool piv = (tid == p);
+    if (piv) {
+#pragma unroll
+      for (int c = 0; c < N; ++c) prow_s[c] = row[c];
+      qs[k] = p;
+      used = true;
+      my_step = k;
+    }
+    __syncthreads();
+    double pv = prow_s[k];
+    if (!(pv != 0.0) || !isfinite(pv) || p >= N) {
+      singular = true;
+      pv = 1.0;
+    }
+    const double inv = 1.0 / pv;
+    if (mine) {
+      const double f = row[k];
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        const double pr = (c == k ? 1.0 : prow_s[c]) * inv;
+        row[c] = piv ? pr : ((c == k ? 0.0 : row[c]) - f * pr);
+      }
+    }
+    __syncthreads();
+  }
+  if (singular && tid == 0) atomicMin(status, K);
+  using S = typename PT<P>::S;
+  S* out = reinterpret_cast<S*>(inv_out) + (int64_t)K * cell_stride;
+  if (mine) {
+    // J_K^{-1}[my_step][q_j] = row[j]
+#pragma unroll
+    for (int j = 0; j < N; ++j) out[(int64_t)qs[j] * ld + my_step] = store_cvt<P>(row[j]);
+  }
+  for (int e = tid; e < N * (ld - N); e += NT) {
+    const int c = e / (ld - N), i = N + (e - c * (ld - N));
+    out[(int64_t)c * ld + i] = store_cvt<P>(0.0);
+  }
+}
+
+template <int P>
+hipError_t setup_rows(hipStream_t s, const vk_level& L, int32_t* status, bool* handled) {
+  *handled = true;
+  switch (L.n_K) {
+#define VK_ROWS_CASE(NN)                                                                                \
+  case NN:                                                                                              \
+    patch_setup_rows_kernel<P, NN><<<L.n_cells, 64 * RowCfg<NN>::W, 0, s>>>(                            \
+        L.J.row_ptr, L.J.col, L.J.val, L.cell_dofs, L.inv, L.ld, L.cell_stride, status);               \
+    return hipGetLastError();
+    VK_ROWS_CASE(42)
+    VK_ROWS_CASE(63)
+    VK_ROWS_CASE(84)
+#undef VK_ROWS_CASE
+    default:
+      *handled = false;
+      return hipSuccess;
+  }
+}
+
+// ===========================================================================
+// Averaged additive sweep in two passes (Eq. 3.5):
+//   patch_gemv : y_K = A_K r_K for every cell (natural order), stored in Y;
+//   dof_gather : z_mu = sum of the entries of Y that belong to DoF mu (the
+//                E_K y_K accumulation of Eq. 3.5b, in ascending cell order),
+//                d_mu += omega z_mu / p_mu.
+// The DoF -> (cell, local index) lists are built at setup.
+// ===========================================================================
+
+template <int P>
+__global__ __launch_bounds__(VK_NT) void patch_gemv_kernel(const void* __restrict__ inv_, int32_t ld,
+                                                           int64_t cell_stride, int32_t n_K, int32_t n_cells,
+                                                           const int32_t* __restrict__ cell_dofs,
+                                                           const double* __restrict__ r,
+                                                           typename PT<P>::A* __restrict__ Y, int32_t cpb) {
+  using S = typename PT<P>::S;
+  using A = typename PT<P>::A;
+  constexpr int VW = PT<P>::VW;
+  extern __shared__ __align__(16) char smem[];
+  A* srk = reinterpret_cast<A*>(smem);
+  A* part = srk + cpb * n_K;
+  const int tpc = VK_NT / cpb;
+  const int slot = threadIdx.x / tpc, t = threadIdx.x - slot * tpc;
+  const int64_t K = (int64_t)blockIdx.x * cpb + slot;
+  const bool valid = K < n_cells;
+  for (int j = t; j < n_K; j += tpc) srk[slot * n_K + j] = valid ? (A)r[cell_dofs[K * n_K + j]] : (A)0;
+  __syncthreads();
+  const int vpc = ld / VW;
+  const int G = tpc / vpc;
+  const int g = t / vpc, v = t - g * vpc;
+  A acc[VW];
+#pragma unroll
+  for (int e = 0; e < VW; ++e) acc[e] = (A)0;
+  if (valid && g < G) {
+    const S* base = reinterpret_cast<const S*>(inv_) + K * cell_stride + v * VW;
+    const A* rk = srk + slot * n_K;
+#pragma unroll 4
+    for (int j = g; j < n_K; j += G) {
+      A a[VW];
+      load_vec<P>(base + (int64_t)j * ld, a);
+      const A rj = rk[j];
+#pragma unroll
+      for (int e = 0; e < VW; ++e) acc[e] = fma(a[e], rj, acc[e]);
+    }
+  }
+  A* mypart = part + slot * tpc * VW;
+  if (g < G) {
+#pragma unroll
+    for (int e = 0; e < VW; ++e) mypart[g * ld + v * VW + e] = acc[e];
+  }
+  __syncthreads();
+  if (valid) {
+    for (int i = t; i < n_K; i += tpc) {
+      A y = (A)0;
+      for (int gg = 0; gg < G; ++gg) y += mypart[gg * ld + i];
+      Y[K * n_K + i] = y;
+    }
+  }
+}
+
+template <typename TY>
+__global__ __launch_bounds__(256) void dof_gather_kernel(int64_t n, const int32_t* __restrict__ off,
+                                                         const int32_t* __restrict__ list,
+                                                         const TY* __restrict__ Y, double omega, double* d) {
+  const int64_t mu = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (mu >= n) return;
+  const int32_t e0 = off[mu], e1 = off[mu + 1];
+  double z = 0.0;
+  for (int32_t e = e0; e < e1; ++e) z += (double)Y[list[e]];
+  if (e1 > e0) d[mu] += omega * z / (double)(e1 - e0);
+}
+
+// exclusive prefix sum of count[0..n) into off[0..n] by one workgroup
+__global__ __launch_bounds__(1024) void scan_kernel(int64_t n, const int32_t* __restrict__ count, int32_t* off) {
+  __shared__ int64_t part[1024];
+  const int tid = threadIdx.x;
+  const int64_t chunk = (n + 1023) / 1024;
+  const int64_t b = tid * chunk, e = (b + chunk < n) ? b + chunk : n;
+  int64_t s = 0;
+  for (int64_t i = b; i < e; ++i) s += count[i];
+  part[tid] = s;
+  __syncthreads();
+  if (tid == 0) {
+    int64_t run = 0;
+    for (int i = 0; i < 1024; ++i) {
+      const int64_t v = part[i];
+      part[i] = run;
+      run += v;
+    }
+    off[n] = (int32_t)run;
+  }
+  __syncthreads();
+  int64_t run = part[tid];
+  for (int64_t i = b; i < e; ++i) {
+    off[i] = (int32_t)run;
+    run += count[i];
+  }
+}
+
+__global__ void dof_fill_kernel(int64_t total, const int32_t* __restrict__ cell_dofs,
+                                const int32_t* __restrict__ off, int32_t* cursor, int32_t* list) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t mu = cell_dofs[e];
+    const int32_t pos = off[mu] + atomicAdd(&cursor[mu], 1);
+    list[pos] = (int32_t)e;
+  }
+}
+
+// ascending order inside each DoF's list (deterministic accumulation order)
+__global__ void dof_sort_kernel(int64_t n, const int32_t* __restrict__ off, int32_t* list) {
+  for (int64_t mu = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; mu < n; mu += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t e0 = off[mu], e1 = off[mu + 1];
+    for (int32_t i = e0 + 1; i < e1; ++i) {
+      const int32_t v = list[i];
+      int32_t j = i - 1;
+      while (j >= e0 && list[j] > v) {
+        list[j + 1] = list[j];
+        --j;
+      }
+      list[j + 1] = v;
+    }
+  }
+}
+
+template <int P>
+hipError_t gemv_prec(hipStream_t s, const vk_level& L, int cpb, const double* r, void* Y) {
+  using A = typename PT<P>::A;
+  constexpr int VW = PT<P>::VW;
+  const unsigned grid = (unsigned)((L.n_cells + cpb - 1) / cpb);
+  const size_t lds = (size_t)cpb * L.n_K * sizeof(A) + (size_t)VK_NT * VW * sizeof(A);
+  patch_gemv_kernel<P><<<grid, VK_NT, lds, s>>>(L.inv, L.ld, L.cell_stride, L.n_K, L.n_cells, L.cell_dofs, r,
+                                                reinterpret_cast<A*>(Y), cpb);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_patch_setup_fast(hipStream_t s, const vk_level& L, vk_prec prec, int32_t* status, bool* handled) {
+  switch (prec) {
+    case VK_F64: return setup_rows<VK_F64>(s, L, status, handled);
+    case VK_F32: return setup_rows<VK_F32>(s, L, status, handled);
+    default: return setup_rows<VK_BF16>(s, L, status, handled);
+  }
+}
+
+hipError_t launch_dof_map(hipStream_t s, const vk_level& L, int32_t* count, int32_t* off, int32_t* list) {
+  const int64_t n = L.J.n_rows;
+  const int64_t total = (int64_t)L.n_cells * L.n_K;
+  hipError_t e = launch_fill_i32(s, n, 0, count);
+  if (e != hipSuccess) return e;
+  count_kernel<<<capped_grid(total, 256, 4096), 256, 0, s>>>(total, L.cell_dofs, count);
+  scan_kernel<<<1, 1024, 0, s>>>(n, count, off);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = launch_fill_i32(s, n, 0, count)) != hipSuccess) return e;
+  dof_fill_kernel<<<capped_grid(total, 256, 4096), 256, 0, s>>>(total, L.cell_dofs, off, count, list);
+  dof_sort_kernel<<<capped_grid(n, 256, 4096), 256, 0, s>>>(n, off, list);
+  return hipGetLastError();
+}
+
+hipError_t launch_patch_gemv(hipStream_t s, const vk_level& L, vk_prec prec, const double* r, void* Y) {
+  const int cpb = L.cpb_override > 0 ? L.cpb_override : vk_default_cpb(L.n_K, L.ld, prec);
+  switch (prec) {
+    case VK_F64: return gemv_prec<VK_F64>(s, L, cpb, r, Y);
+    case VK_F32: return gemv_prec<VK_F32>(s, L, cpb, r, Y);
+    default: return gemv_prec<VK_BF16>(s, L, cpb, r, Y);
+  }
+}
+
+hipError_t launch_dof_gather(hipStream_t s, const vk_level& L, vk_prec prec, const void* Y, double omega,
+                             double* d) {
+  const int64_t n = L.J.n_rows;
+  const unsigned g = (unsigned)((n + 255) / 256);
+  if (prec == VK_F64)
+    dof_gather_kernel<double><<<g, 256, 0, s>>>(n, L.dof_off, L.dof_list, reinterpret_cast<const double*>(Y), omega, d);
+  else
+    dof_gather_kernel<float><<<g, 256, 0, s>>>(n, L.dof_off, L.dof_list, reinterpret_cast<const float*>(Y), omega, d);
+  return hipGetLastError();
+}

@@ -34,6 +34,8 @@ struct vk_level {
   int32_t ld = 0;             // leading dimension (rows, padded)
   int64_t cell_stride = 0;    // elements per cell
   double* inv_p = nullptr;    // 1 / multiplicity
+  int32_t* dof_off = nullptr;   // DoF -> (cell, local) lists: offsets (n + 1)
+  int32_t* dof_list = nullptr;  // flat indices K * n_K + i, ascending per DoF
   double* b = nullptr;        // V-cycle right-hand side (levels < L)
   double* d = nullptr;        // V-cycle iterate (levels < L)
   double* r = nullptr;        // defect scratch
@@ -63,10 +65,14 @@ struct vk_ctx {
   bool setup_done = false;
   double omega = 0.7;
   vk_mode mode = VK_ADDITIVE;
+  int32_t sweep_variant = 0;  // additive sweep: 0 DoF gather, 1 coloured scatter
+  bool fast_setup = true;     // register-resident patch inversion where compiled
+  void* Y = nullptr;          // per-cell products y_K of the additive sweep
   // coarse direct solve
-  double* c_inv = nullptr;   // FP64 inverse of J_0 (row-major)
-  double* c_tmp = nullptr;   // Gauss-Jordan ping-pong buffer
-  int32_t* c_perm = nullptr;
+  double* c_inv = nullptr;   // Gauss-Jordan buffers (two, alternating)
+  double* c_tmp = nullptr;
+  double* c_W = nullptr;     // the one holding the eliminated matrix
+  int32_t* c_perm = nullptr; // rowmap (n_0) + panel interchanges (n_0)
   // setup scratch for patches too wide for LDS
   double* big_scratch = nullptr;
   int32_t big_chunk = 0;
@@ -112,9 +118,17 @@ int vk_default_cpb(int32_t n_K, int32_t ld, vk_prec prec);
 int vk_prec_vw(vk_prec prec);
 int vk_prec_bytes(vk_prec prec);
 // coarse
-hipError_t launch_coarse_invert(hipStream_t s, const vk_csr& J0, double* inv, double* tmp, int32_t* perm,
-                                int32_t* status);
-hipError_t launch_dense_gemv(hipStream_t s, int64_t n, const double* A, const double* x, double* y);
+int64_t vk_coarse_max_n();
+hipError_t launch_coarse_invert(hipStream_t s, const vk_csr& J0, double* buf0, double* buf1, int32_t* perm,
+                                int32_t* status, double** result);
+hipError_t launch_coarse_apply(hipStream_t s, int64_t n, const double* W, const int32_t* rowmap, const double* x,
+                               double* y);
+hipError_t launch_coarse_export(hipStream_t s, int64_t n, const double* W, const int32_t* rowmap, double* out);
+hipError_t launch_patch_setup_fast(hipStream_t s, const vk_level& L, vk_prec prec, int32_t* status, bool* handled);
+hipError_t launch_dof_map(hipStream_t s, const vk_level& L, int32_t* count, int32_t* off, int32_t* list);
+hipError_t launch_patch_gemv(hipStream_t s, const vk_level& L, vk_prec prec, const double* r, void* Y);
+hipError_t launch_dof_gather(hipStream_t s, const vk_level& L, vk_prec prec, const void* Y, double omega,
+                             double* d);
 // Krylov
 hipError_t launch_dot(hipStream_t s, int64_t n, const double* x, const double* y, double* partial,
                       int32_t n_partial, double* out, bool sqrt_out);

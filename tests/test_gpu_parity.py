@@ -307,8 +307,10 @@ def test_timing_counts(vk):
     L = P.finest
     d = torch.zeros(L.n, dtype=torch.float64, device=DEV)
     S.vanka_smooth(len(P.levels) - 1, t(P.b), d, 3, d_is_zero=True)
-    n, ms = S.vk_timing_read("patch_apply", len(P.levels) - 1)
-    assert n == 3 * 4 and ms > 0
+    n, ms = S.vk_timing_read("patch_gemv", len(P.levels) - 1)
+    assert n == 3 and ms > 0
+    n, ms = S.vk_timing_read("dof_gather", len(P.levels) - 1)
+    assert n == 3 and ms > 0
     n, ms = S.vk_timing_read("spmv", len(P.levels) - 1)
     assert n == 2
     S.vk_timing_enable(False)
@@ -329,3 +331,54 @@ def test_patch_tiles_agree(vk, tile):
     d = t(d0)
     S.vanka_smooth(l, t(b), d, 1)
     assert rel(d.cpu().numpy(), H.smooth(l, b, d0, 1)) <= 1e-10
+
+
+@pytest.mark.parametrize("variant", ["dof_gather", "coloured_scatter"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_sweep_variants(vk, variant, prec):
+    """Both implementations of the averaged additive sweep equal the oracle's Eq. 3.5."""
+    P, H = problem("ragged_k2")
+    S = make_solver(vk, P, prec=prec)
+    S.vk_set_sweep_variant(variant)
+    Href = H if prec == "f64" else oracle.OracleHierarchy(P.levels, patch_store=oracle.round_f32)
+    tol = 1e-10 if prec == "f64" else 2e-5
+    rng = np.random.default_rng(7)
+    for l in range(1, len(P.levels)):
+        L = P.levels[l]
+        b = rng.standard_normal(L.n)
+        d0 = rng.standard_normal(L.n)
+        d = t(d0)
+        S.vanka_smooth(l, t(b), d, 2)
+        assert rel(d.cpu().numpy(), Href.smooth(l, b, d0, 2)) <= tol
+
+
+@pytest.mark.parametrize("case", ["cfg0", "ragged_k2", "k3"])
+def test_setup_variants_agree(vk, case):
+    """The register-resident and the LDS Gauss-Jordan kernels give the same inverses."""
+    P, H = problem(case)
+    outs = []
+    for variant in (0, 1):
+        S = vk.Solver([vk.upload_level(L, DEV) for L in P.levels])
+        S.vk_set_workspace("f64", 30, device=DEV)
+        S.vk_set_setup_variant(variant)
+        S.vanka_setup(0.7)
+        l = len(P.levels) - 1
+        nc, nK = P.finest.mesh.n_cells, P.finest.mesh.n_K
+        out = torch.empty((nc, nK, nK), dtype=torch.float64, device=DEV)
+        S.vk_get_patch_inverses(l, 0, nc, out)
+        outs.append(out.cpu().numpy())
+        err = np.abs(outs[-1] - H.A[l]).max(axis=(1, 2)) / np.abs(H.A[l]).max(axis=(1, 2))
+        assert err.max() <= 1e-10, (variant, err.max())
+
+
+def test_coarse_inverse_cfg1_size(vk):
+    """The blocked coarse inverse at the 11x2 dG(2) coarse level (888 unknowns, several panels)."""
+    P = build_problem("channel2d_176x32_k2", shape=(22, 4), levels=2)
+    S = make_solver(vk, P)
+    J0 = P.levels[0].J.toarray()
+    n0 = J0.shape[0]
+    out = torch.empty((n0, n0), dtype=torch.float64, device=DEV)
+    S.vk_get_coarse_inverse(out)
+    ref = np.linalg.inv(J0)
+    kappa = np.linalg.cond(J0)
+    assert rel(out.cpu().numpy(), ref) <= 100 * kappa * np.finfo(float).eps
