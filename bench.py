@@ -150,6 +150,8 @@ def main():
         return S
 
     S = make(args.prec)
+    S.vanka_setup(0.7, "additive")
+    S.vk_autotune(10)
     for w in range(args.warmup):
         its, rel = run_step(S, b, x, nu, restart, max_iter)
         log(f"[bench] warmup {w}: {its} its, rel {rel:.2e}")
@@ -206,6 +208,8 @@ def main():
     if not args.no_compare:
         for prec in [p for p in ("f64", "bf16") if p != args.prec]:
             S2 = make(prec)
+            S2.vanka_setup(0.7, "additive")
+            S2.vk_autotune(10)
             run_step(S2, b, x, nu, restart, max_iter)
             torch.cuda.synchronize()
             t0 = time.perf_counter()

@@ -186,6 +186,14 @@ vk_status vk_set_sweep_variant(vk_ctx* ctx, int32_t variant);
  * compute the same Gauss-Jordan inverse; setup must run again after a change. */
 vk_status vk_set_setup_variant(vk_ctx* ctx, int32_t variant);
 
+/* Autotuner: after vanka_setup, times each level's SpMV kernels (J, P, R)
+ * with 4, 8, 16, 32 and 64 lanes per row and the patch GEMV with 1, 2, 4 and
+ * 8 cells per workgroup (`reps` launches each, HIP events) and keeps the
+ * fastest for the context.  Results change only in floating-point summation
+ * order.  Overwrites the level scratch vectors; synchronises the stream.
+ * A later vk_set_workspace resets the choices (vk_set_patch_tile overrides). */
+vk_status vk_autotune(vk_ctx* ctx, int32_t reps);
+
 /* ---- per-launch timing (benchmarks) --------------------------------------
  * With timing enabled, the library brackets every launch of the kernel classes
  * below with a pair of HIP events on the context's stream (a pool of 16384

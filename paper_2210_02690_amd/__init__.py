@@ -62,6 +62,7 @@ _SIGS = {
     "vk_timing_enable": (ctypes.c_int, [_P, _I32, _I32]),
     "vk_set_sweep_variant": (ctypes.c_int, [_P, _I32]),
     "vk_set_setup_variant": (ctypes.c_int, [_P, _I32]),
+    "vk_autotune": (ctypes.c_int, [_P, _I32]),
     "vk_timing_read": (ctypes.c_int, [_P, _I32, _I32, _PI64, _PD]),
 }
 KERNEL_KINDS = {"patch_apply": 0, "spmv": 1, "patch_setup": 2, "patch_residual": 3, "patch_gemv": 4,
@@ -238,6 +239,9 @@ class Solver:
 
     def vk_set_setup_variant(self, variant):
         self._check(_lib.vk_set_setup_variant(self.ctx, variant))
+
+    def vk_autotune(self, reps=10):
+        self._check(_lib.vk_autotune(self.ctx, reps))
 
     def vk_timing_enable(self, enable=True, level=-1):
         self._check(_lib.vk_timing_enable(self.ctx, 1 if enable else 0, level))

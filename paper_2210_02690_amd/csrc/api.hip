@@ -252,12 +252,19 @@ vk_status vk_create(vk_ctx** out, int32_t n_levels, void* hip_stream) {
   ctx->n_levels = n_levels;
   ctx->lv.resize(n_levels);
   ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  const hipError_t e = hipMalloc(&ctx->status, 4096);
+  hipError_t e = hipMalloc(&ctx->status, 4096);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming);
   if (e != hipSuccess) {
     (void)hipGetLastError();  // do not leave the error for the caller's next check
+    if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
+    if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
+    if (ctx->status) (void)hipFree(ctx->status);
     delete ctx;
     char buf[256];
-    snprintf(buf, sizeof(buf), "hipMalloc of the status block failed: %s", hipGetErrorString(e));
+    snprintf(buf, sizeof(buf), "vk_create: HIP resource allocation failed: %s", hipGetErrorString(e));
     return create_fail(VK_ERR_HIP, buf);
   }
   *out = ctx;
@@ -269,6 +276,10 @@ void vk_destroy(vk_ctx* ctx) {
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   else (void)hipDeviceSynchronize();
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+  if (ctx->side) (void)hipStreamSynchronize(ctx->side);
+  if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
+  if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+  if (ctx->side) (void)hipStreamDestroy(ctx->side);
   if (ctx->status) (void)hipFree(ctx->status);
   delete ctx;
 }
@@ -284,7 +295,7 @@ vk_status vk_set_level(vk_ctx* ctx, int32_t l, const vk_csr* J, const vk_csr* P,
     return fail(ctx, VK_ERR_ARG, "J must be a non-empty square CSR matrix with valid pointers");
   if (J->n_rows > INT32_MAX) return fail(ctx, VK_ERR_ARG, "J too large for int32 columns");
   if (l == 0 && J->n_rows > vk_coarse_max_n())
-    return fail(ctx, VK_ERR_ARG, "the coarsest level exceeds the dense direct solver's limit of 15360 unknowns");
+    return fail(ctx, VK_ERR_ARG, "the coarsest level exceeds the dense direct solver limit of 4096 unknowns");
   vk_level L;
   L.J = *J;
   if (l > 0) {
@@ -383,6 +394,8 @@ vk_status vk_set_workspace(vk_ctx* ctx, void* dev, size_t bytes, vk_prec prec, i
   plan_workspace(ctx, prec, restart, ctx->ws);
   ctx->ws_ready = true;
   ctx->setup_done = false;
+  ctx->maps_ready = false;
+  for (int l = 0; l < ctx->n_levels; ++l) ctx->lv[l].cpb_tuned = 0;
   return VK_OK;
 }
 
@@ -398,17 +411,30 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
   ctx->mode = mode;
   hipStream_t s = ctx->stream;
   VK_TRY(launch_fill_i32(s, 64, INT_MAX, ctx->status));
+  // the coarse inversion occupies one workgroup at a time: run it on the side
+  // stream while the patch inversions fill the rest of the GPU
+  VK_TRY(hipEventRecord(ctx->fork_ev, s));
+  VK_TRY(hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0));
+  VK_TRY(launch_coarse_invert(ctx->side, ctx->lv[0].J, ctx->c_inv, ctx->c_tmp, ctx->c_perm, ctx->status,
+                              &ctx->c_W));
+  VK_TRY(hipEventRecord(ctx->join_ev, ctx->side));
+  if (!ctx->maps_ready) {
+    // multiplicities and DoF -> (cell, local) lists depend on the mesh only
+    for (int l = 1; l < ctx->n_levels; ++l) {
+      vk_level& L = ctx->lv[l];
+      VK_TRY(launch_multiplicity(s, L.n_cells, L.n_K, L.cell_dofs, L.J.n_rows, reinterpret_cast<int32_t*>(L.r),
+                                 L.inv_p));
+      VK_TRY(launch_dof_map(s, L, reinterpret_cast<int32_t*>(L.r), L.dof_off, L.dof_list));
+    }
+  }
   for (int l = 1; l < ctx->n_levels; ++l) {
     vk_level& L = ctx->lv[l];
-    VK_TRY(launch_multiplicity(s, L.n_cells, L.n_K, L.cell_dofs, L.J.n_rows, reinterpret_cast<int32_t*>(L.r),
-                               L.inv_p));
-    VK_TRY(launch_dof_map(s, L, reinterpret_cast<int32_t*>(L.r), L.dof_off, L.dof_list));
     Timed t(ctx, VK_KERNEL_PATCH_SETUP, l);
     bool handled = false;
     if (ctx->fast_setup) VK_TRY(launch_patch_setup_fast(s, L, ctx->prec, ctx->status + l, &handled));
     if (!handled) VK_TRY(launch_patch_setup(s, L, ctx->prec, ctx->big_scratch, ctx->big_chunk, ctx->status + l));
   }
-  VK_TRY(launch_coarse_invert(s, ctx->lv[0].J, ctx->c_inv, ctx->c_tmp, ctx->c_perm, ctx->status, &ctx->c_W));
+  VK_TRY(hipStreamWaitEvent(s, ctx->join_ev, 0));
   int32_t st[64];
   VK_TRY(hipMemcpyAsync(st, ctx->status, sizeof(int32_t) * 64, hipMemcpyDeviceToHost, s));
   VK_TRY(hipStreamSynchronize(s));
@@ -427,6 +453,7 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
     }
   }
   ctx->setup_done = true;
+  ctx->maps_ready = true;
   return VK_OK;
 }
 
@@ -583,6 +610,57 @@ vk_status vk_patch_layout(const vk_ctx* ctx, int32_t l, int64_t* bytes_per_cell,
   const vk_level& L = ctx->lv[l];
   if (bytes_per_cell) *bytes_per_cell = L.cell_stride * vk_prec_bytes(ctx->prec);
   if (ld) *ld = L.ld;
+  return VK_OK;
+}
+
+vk_status vk_autotune(vk_ctx* ctx, int32_t reps) {
+  VK_CHECK(ready(ctx));
+  if (reps < 1) reps = 1;
+  hipStream_t s = ctx->stream;
+  hipEvent_t e0, e1;
+  VK_TRY(hipEventCreate(&e0));
+  VK_TRY(hipEventCreate(&e1));
+  auto time_ms = [&](auto&& launch) -> float {
+    if (launch() != hipSuccess) return 1e30f;  // warm-up
+    (void)hipEventRecord(e0, s);
+    for (int i = 0; i < reps; ++i)
+      if (launch() != hipSuccess) return 1e30f;
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    float ms = 1e30f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    return ms;
+  };
+  const int lprs[5] = {4, 8, 16, 32, 64};
+  for (int l = 0; l < ctx->n_levels; ++l) {
+    vk_level& L = ctx->lv[l];
+    VK_TRY(launch_fill(s, L.J.n_rows, 1.0, L.b));
+    auto tune_csr = [&](const vk_csr& A, double* x, double* y) -> int {
+      int best = 4;
+      float tb = 1e30f;
+      for (int lpr : lprs) {
+        const float t = time_ms([&] { return launch_spmv(s, A, lpr, 1.0, x, 0.0, nullptr, y); });
+        if (t < tb) { tb = t; best = lpr; }
+      }
+      return best;
+    };
+    L.lpr_J = tune_csr(L.J, L.b, L.r);
+    if (l == 0) continue;
+    vk_level& C = ctx->lv[l - 1];
+    VK_TRY(launch_fill(s, C.J.n_rows, 1.0, C.b));
+    L.lpr_P = tune_csr(L.P, C.b, L.r);
+    L.lpr_R = tune_csr(L.R, L.b, C.r);
+    int best = 0;
+    float tb = 1e30f;
+    for (int cpb : {1, 2, 4, 8}) {
+      if (VK_NT / cpb < L.ld / vk_prec_vw(ctx->prec)) continue;
+      const float t = time_ms([&] { return launch_patch_gemv(s, L, ctx->prec, L.b, ctx->Y, cpb); });
+      if (t < tb) { tb = t; best = cpb; }
+    }
+    L.cpb_tuned = best;
+  }
+  VK_TRY(hipEventDestroy(e0));
+  VK_TRY(hipEventDestroy(e1));
   return VK_OK;
 }
 

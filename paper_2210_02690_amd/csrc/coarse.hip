@@ -1,239 +1,210 @@
 // Coarsest-level direct solve (Sec. 3: a direct solver for J_0 d_0 = b_0 on T_0).
 //
 // Setup inverts the dense FP64 J_0 by blocked Gauss-Jordan elimination with
-// partial pivoting (first row of maximal |value| among the rows not yet used).
+// implicit partial pivoting: the pivot of column k is the not-yet-used row
+// q_k with the largest |value| (the first such row on ties); rows never move.
 // For each panel of NB columns:
-//   panel kernel  (one workgroup, rows of the panel in registers): the NB
-//                 elimination steps restricted to the panel columns; it
-//                 records the row interchanges;
-//   update kernel (whole GPU): the same transformation applied to every other
+//   panel kernel  (one 256-thread workgroup, the panel rows in registers):
+//                 the NB elimination steps restricted to the panel columns;
+//   update kernel (whole GPU): the same transformation on every other
 //                 column, as the rank-NB update
-//                   out[i, c] = (i in panel rows ? 0 : in[src(i), c])
-//                               + sum_j X[i, j] in[src(k0 + j), c],
-//                 X the eliminated panel, src the panel's row interchanges.
-// Two buffers alternate so no workgroup reads what another writes.  The row
-// interchanges are not undone on the columns: with rowmap the composition of
-// all interchanges, J_0^{-1} b = W b[rowmap], which the V-cycle applies.
+//                   out[i, c] = (i a pivot row of the panel ? 0 : in[i, c])
+//                               + sum_j X[i, j] in[q_j, c],
+//                 X the eliminated panel.
+// Two buffers alternate so no workgroup reads what another writes.  The
+// stored matrix W then satisfies J_0^{-1}[k][q_j] = W[q_k][j], so the coarse
+// solve is y[k] = sum_j W[q_k][j] b[q_j].
 #include <climits>
 
 #include "vk_internal.h"
 
 namespace {
 
-constexpr int PT = 1024;  // panel kernel threads
-
+// one wavefront per row
 __global__ void csr_to_dense_kernel(int64_t n, const int64_t* __restrict__ row_ptr,
                                     const int32_t* __restrict__ col, const double* __restrict__ val, double* M) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
   if (i >= n) return;
-  for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) M[i * n + col[e]] = val[e];
+  for (int64_t e = row_ptr[i] + lane; e < row_ptr[i + 1]; e += 64) M[i * n + col[e]] = val[e];
 }
 
-__global__ void iota_kernel(int64_t n, int32_t* x) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    x[i] = (int32_t)i;
-}
+constexpr int CT = 256;  // panel kernel threads
 
 template <int R, int NB>
-__global__ __launch_bounds__(PT) void coarse_panel_kernel(int64_t n, int64_t k0, int nb,
+__global__ __launch_bounds__(CT) void coarse_panel_kernel(int64_t n, int64_t k0, int nb,
                                                           const double* __restrict__ Min, double* __restrict__ Mout,
-                                                          int32_t* __restrict__ src_g, int32_t* rowmap,
+                                                          int32_t* __restrict__ q_g, int32_t* __restrict__ used_g,
                                                           int32_t* status) {
-  extern __shared__ int src_l[];  // n entries
-  __shared__ double red_abs[PT / 64], red_val[PT / 64];
-  __shared__ int red_idx[PT / 64];
-  __shared__ double prow[NB], xk[NB], xp[NB];
-  __shared__ int s_p, s_piv[NB];
-  __shared__ double s_pv;
+  __shared__ double w_abs[CT / 64];
+  __shared__ int w_idx[CT / 64];
+  __shared__ double prow[NB];
+  __shared__ int s_q[NB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // P[r][.]: panel row tid + r * CT; the column loop is unrolled completely
   double P[R][NB];
+  uint32_t used = 0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int64_t i = tid + (int64_t)r * PT;
+    const int64_t i = tid + (int64_t)r * CT;
+    const bool ok = i < n;
 #pragma unroll
-    for (int c = 0; c < NB; ++c) P[r][c] = (i < n && c < nb) ? Min[i * n + k0 + c] : 0.0;
+    for (int c = 0; c < NB; ++c) P[r][c] = (ok && c < nb) ? Min[i * n + k0 + c] : 0.0;
+    if (!ok || used_g[i]) used |= 1u << r;
   }
-  for (int64_t i = tid; i < n; i += PT) src_l[i] = (int)i;
-  __syncthreads();
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    if (j < nb) {  // uniform: every thread sees the same nb
-    const int64_t k = k0 + j;
-    double babs = -1.0, bval = 0.0;
-    int bidx = INT_MAX;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int64_t i = tid + (int64_t)r * PT;
-      if (i >= k && i < n) {
-        const double a = fabs(P[r][j]);
-        if (a > babs) { babs = a; bval = P[r][j]; bidx = (int)i; }
-      }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ob = __shfl_xor(babs, o, 64), ov = __shfl_xor(bval, o, 64);
-      const int oi = __shfl_xor(bidx, o, 64);
-      if (ob > babs || (ob == babs && oi < bidx)) { babs = ob; bval = ov; bidx = oi; }
-    }
-    if (lane == 0) { red_abs[wave] = babs; red_val[wave] = bval; red_idx[wave] = bidx; }
-    __syncthreads();
-    if (wave == 0) {
-      babs = lane < PT / 64 ? red_abs[lane] : -1.0;
-      bval = lane < PT / 64 ? red_val[lane] : 0.0;
-      bidx = lane < PT / 64 ? red_idx[lane] : INT_MAX;
-      for (int o = 8; o > 0; o >>= 1) {
-        const double ob = __shfl_xor(babs, o, 64), ov = __shfl_xor(bval, o, 64);
-        const int oi = __shfl_xor(bidx, o, 64);
-        if (ob > babs || (ob == babs && oi < bidx)) { babs = ob; bval = ov; bidx = oi; }
-      }
-      if (lane == 0) {
-        const bool bad = bidx >= n || !(babs > 0.0) || !isfinite(babs);
-        if (bad) atomicMin(&status[0], -1);
-        s_p = bad ? (int)k : bidx;
-        s_pv = bad ? 1.0 : bval;
-      }
-    }
-    __syncthreads();
-    const int64_t p = s_p;
-    const double pv = s_pv;
-    const int tk = (int)(k % PT), rk = (int)(k / PT);
-    const int tp = (int)(p % PT), rp = (int)(p / PT);
-    if (p != k) {
+    if (j < nb) {  // uniform
+      double ba = -1.0;
+      int bi = INT_MAX;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        if (tid == tk && r == rk)
-#pragma unroll
-          for (int c = 0; c < NB; ++c) xk[c] = P[r][c];
-        if (tid == tp && r == rp)
-#pragma unroll
-          for (int c = 0; c < NB; ++c) xp[c] = P[r][c];
+        const double av = fabs(P[r][j]);
+        if (!((used >> r) & 1u) && av > ba) { ba = av; bi = tid + r * CT; }
       }
-      if (tid == 0) {
-        const int t = src_l[k];
-        src_l[k] = src_l[p];
-        src_l[p] = t;
+      const double m = wave_max(ba);
+      const int wi = wave_min((ba == m && bi != INT_MAX) ? bi : INT_MAX);
+      if (lane == 0) { w_abs[wave] = m; w_idx[wave] = wi; }
+      __syncthreads();
+      double pm = w_abs[0];
+      int p = w_idx[0];
+#pragma unroll
+      for (int w = 1; w < CT / 64; ++w) {
+        const double om = w_abs[w];
+        const int oi = w_idx[w];
+        if (om > pm || (om == pm && oi < p)) { pm = om; p = oi; }
+      }
+      const bool bad = p == INT_MAX || !(pm > 0.0) || !isfinite(pm);
+      const int owner = bad ? -1 : p % CT, slot = bad ? -1 : p / CT;
+      if (tid == owner) {
+        double v[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          v[c] = P[0][c];
+#pragma unroll
+          for (int r = 1; r < R; ++r) v[c] = (slot == r) ? P[r][c] : v[c];
+        }
+        const double inv = 1.0 / v[j];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) prow[c] = (c == j ? 1.0 : v[c]) * inv;
+        used |= 1u << slot;
+        s_q[j] = p;
+      }
+      if (bad && tid == 0) {
+        atomicMin(&status[0], -1);  // failure path only
+        s_q[j] = 0;
       }
       __syncthreads();
+      if (!bad) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if (tid == tk && r == rk)
+        for (int r = 0; r < R; ++r) {
+          const bool piv = (tid == owner) && (r == slot);
+          const double f = piv ? -1.0 : P[r][j];
+          const double keep = piv ? 0.0 : 1.0;
 #pragma unroll
-          for (int c = 0; c < NB; ++c) P[r][c] = xp[c];
-        if (tid == tp && r == rp)
-#pragma unroll
-          for (int c = 0; c < NB; ++c) P[r][c] = xk[c];
-      }
-    }
-    if (tid == 0) s_piv[j] = (int)p;
-    const double inv = 1.0 / pv;
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-      if (tid == tk && r == rk)
-#pragma unroll
-        for (int c = 0; c < NB; ++c) prow[c] = (c == j ? 1.0 : P[r][c]) * inv;
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int64_t i = tid + (int64_t)r * PT;
-      if (i < n) {
-        if (i == k) {
-#pragma unroll
-          for (int c = 0; c < NB; ++c) P[r][c] = prow[c];
-        } else {
-          const double f = P[r][j];
-#pragma unroll
-          for (int c = 0; c < NB; ++c) P[r][c] = (c == j ? 0.0 : P[r][c]) - f * prow[c];
+          for (int c = 0; c < NB; ++c) {
+            const double pc = prow[c];
+            P[r][c] = (c == j) ? -f * pc : fma(-f, pc, keep * P[r][c]);
+          }
         }
       }
-    }
-    __syncthreads();
+      __syncthreads();
     }
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int64_t i = tid + (int64_t)r * PT;
-    if (i < n)
+    const int64_t i = tid + (int64_t)r * CT;
+    if (i < n) {
 #pragma unroll
       for (int c = 0; c < NB; ++c)
         if (c < nb) Mout[i * n + k0 + c] = P[r][c];
-  }
-  for (int64_t i = tid; i < n; i += PT) src_g[i] = src_l[i];
-  if (tid == 0) {
-    for (int j = 0; j < nb; ++j) {
-      const int64_t k = k0 + j, p = s_piv[j];
-      const int32_t t = rowmap[k];
-      rowmap[k] = rowmap[p];
-      rowmap[p] = t;
+      used_g[i] = (used >> r) & 1u;
     }
   }
+  if (tid < nb) q_g[k0 + tid] = s_q[tid];
 }
 
 // Rank-NB update of the columns outside the panel; tiles of 32 rows x 64 columns.
 template <int NB>
 __global__ __launch_bounds__(256) void coarse_update_kernel(int64_t n, int64_t k0, int nb,
                                                             const double* __restrict__ Min, double* Mout,
-                                                            const int32_t* __restrict__ src) {
+                                                            const int32_t* __restrict__ q_g) {
   __shared__ double Rt[NB][64];
   __shared__ double Xt[32][NB + 1];
+  __shared__ int qs[NB];
   const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 64;
   const int tid = threadIdx.x;
+  if (tid < NB) qs[tid] = tid < nb ? q_g[k0 + tid] : -1;
+  __syncthreads();
   for (int e = tid; e < NB * 64; e += 256) {
     const int j = e >> 6, cc = e & 63;
     const int64_t c = c0 + cc;
-    Rt[j][cc] = (j < nb && c < n) ? Min[(int64_t)src[k0 + j] * n + c] : 0.0;
+    Rt[j][cc] = (j < nb && c < n) ? Min[(int64_t)qs[j] * n + c] : 0.0;
   }
   for (int e = tid; e < 32 * NB; e += 256) {
     const int rr = e / NB, j = e - rr * NB;
     const int64_t i = r0 + rr;
     Xt[rr][j] = (i < n && j < nb) ? Mout[i * n + k0 + j] : 0.0;
   }
-  __syncthreads();
   const int tx = tid & 63, ty = tid >> 6;
   const int64_t c = c0 + tx;
-  if (c >= n || (c >= k0 && c < k0 + nb)) return;
+  const bool col_ok = c < n && !(c >= k0 && c < k0 + nb);
+  double base[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int64_t i = r0 + ty + 4 * s;
+    base[s] = (col_ok && i < n) ? Min[i * n + c] : 0.0;  // issued before the barrier
+  }
+  __syncthreads();
+  if (!col_ok) return;
+#pragma unroll
   for (int s = 0; s < 8; ++s) {
     const int rr = ty + 4 * s;
     const int64_t i = r0 + rr;
-    if (i >= n) break;
-    double acc = (i >= k0 && i < k0 + nb) ? 0.0 : Min[(int64_t)src[i] * n + c];
+    if (i < n) {
+      bool pivot_row = false;
 #pragma unroll
-    for (int j = 0; j < NB; ++j) acc = fma(Xt[rr][j], Rt[j][tx], acc);
-    Mout[i * n + c] = acc;
+      for (int j = 0; j < NB; ++j) pivot_row |= (qs[j] == i);
+      double acc = pivot_row ? 0.0 : base[s];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) acc = fma(Xt[rr][j], Rt[j][tx], acc);
+      Mout[i * n + c] = acc;
+    }
   }
 }
 
-// y = W x[rowmap], W dense row-major n x n, one wavefront per row.
+// y[k] = sum_j W[q_k][j] x[q_j], one wavefront per output entry.
 __global__ __launch_bounds__(256) void coarse_apply_kernel(int64_t n, const double* __restrict__ W,
-                                                           const int32_t* __restrict__ rowmap,
+                                                           const int32_t* __restrict__ q,
                                                            const double* __restrict__ x, double* __restrict__ y) {
-  const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
-  if (row >= n) return;
-  const double* w = W + row * n;
+  if (k >= n) return;
+  const double* w = W + (int64_t)q[k] * n;
   double s = 0.0;
-  for (int64_t j = lane; j < n; j += 64) s = fma(w[j], x[rowmap[j]], s);
+  for (int64_t j = lane; j < n; j += 64) s = fma(w[j], x[q[j]], s);
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-  if (lane == 0) y[row] = s;
+  if (lane == 0) y[k] = s;
 }
 
-// out[r, rowmap[i]] = W[r, i]: the inverse with the interchanges undone
-__global__ void coarse_export_kernel(int64_t n, const double* __restrict__ W, const int32_t* __restrict__ rowmap,
+// out[k][q_j] = W[q_k][j]: the inverse in natural order
+__global__ void coarse_export_kernel(int64_t n, const double* __restrict__ W, const int32_t* __restrict__ q,
                                      double* out) {
   const int64_t total = n * n;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = e / n, i = e - r * n;
-    out[r * n + rowmap[i]] = W[e];
+    const int64_t k = e / n, j = e - k * n;
+    out[k * n + q[j]] = W[(int64_t)q[k] * n + j];
   }
 }
 
 template <int R, int NB>
-hipError_t run_blocked(hipStream_t s, int64_t n, double** a, double** b, int32_t* src, int32_t* rowmap,
+hipError_t run_blocked(hipStream_t s, int64_t n, double** a, double** b, int32_t* q, int32_t* used,
                        int32_t* status) {
-  const size_t lds = (size_t)n * sizeof(int);
   const dim3 ugrid((unsigned)((n + 63) / 64), (unsigned)((n + 31) / 32));
   for (int64_t k0 = 0; k0 < n; k0 += NB) {
     const int nb = (int)((n - k0) < NB ? (n - k0) : NB);
-    coarse_panel_kernel<R, NB><<<1, PT, lds, s>>>(n, k0, nb, *a, *b, src, rowmap, status);
-    coarse_update_kernel<NB><<<ugrid, 256, 0, s>>>(n, k0, nb, *a, *b, src);
+    coarse_panel_kernel<R, NB><<<1, CT, 0, s>>>(n, k0, nb, *a, *b, q, used, status);
+    coarse_update_kernel<NB><<<ugrid, 256, 0, s>>>(n, k0, nb, *a, *b, q);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     double* t = *a;
@@ -245,41 +216,38 @@ hipError_t run_blocked(hipStream_t s, int64_t n, double** a, double** b, int32_t
 
 }  // namespace
 
-int64_t vk_coarse_max_n() { return 15360; }
+int64_t vk_coarse_max_n() { return 4096; }
 
 hipError_t launch_coarse_invert(hipStream_t s, const vk_csr& J0, double* buf0, double* buf1, int32_t* perm,
                                 int32_t* status, double** result) {
   const int64_t n = J0.n_rows;
   hipError_t e = launch_fill(s, n * n, 0.0, buf0);
   if (e != hipSuccess) return e;
-  csr_to_dense_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, J0.row_ptr, J0.col, J0.val, buf0);
-  int32_t* rowmap = perm;
-  int32_t* src = perm + n;
-  iota_kernel<<<(unsigned)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096), 256, 0, s>>>(n, rowmap);
+  csr_to_dense_kernel<<<(unsigned)((n * 64 + 255) / 256), 256, 0, s>>>(n, J0.row_ptr, J0.col, J0.val, buf0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  int32_t* q = perm;
+  int32_t* used = perm + n;
+  if ((e = launch_fill_i32(s, n, 0, used)) != hipSuccess) return e;
   double* a = buf0;
   double* b = buf1;
-  const int64_t R = (n + PT - 1) / PT;
-  // R rows x NB panel columns per thread, R * NB <= 32 doubles (the register
-  // budget of a 1024-thread workgroup)
-  if (R <= 1) e = run_blocked<1, 32>(s, n, &a, &b, src, rowmap, status);
-  else if (R <= 2) e = run_blocked<2, 16>(s, n, &a, &b, src, rowmap, status);
-  else if (R <= 4) e = run_blocked<4, 8>(s, n, &a, &b, src, rowmap, status);
-  else if (R <= 8) e = run_blocked<8, 4>(s, n, &a, &b, src, rowmap, status);
-  else e = run_blocked<16, 2>(s, n, &a, &b, src, rowmap, status);
+  // R rows x NB panel columns per thread: R * NB <= 64 doubles
+  const int64_t R = (n + CT - 1) / CT;
+  if (R <= 4) e = run_blocked<4, 16>(s, n, &a, &b, q, used, status);
+  else if (R <= 8) e = run_blocked<8, 8>(s, n, &a, &b, q, used, status);
+  else e = run_blocked<16, 4>(s, n, &a, &b, q, used, status);
   *result = a;
   return e;
 }
 
-hipError_t launch_coarse_apply(hipStream_t s, int64_t n, const double* W, const int32_t* rowmap, const double* x,
+hipError_t launch_coarse_apply(hipStream_t s, int64_t n, const double* W, const int32_t* q, const double* x,
                                double* y) {
-  coarse_apply_kernel<<<(unsigned)((n * 64 + 255) / 256), 256, 0, s>>>(n, W, rowmap, x, y);
+  coarse_apply_kernel<<<(unsigned)((n * 64 + 255) / 256), 256, 0, s>>>(n, W, q, x, y);
   return hipGetLastError();
 }
 
-hipError_t launch_coarse_export(hipStream_t s, int64_t n, const double* W, const int32_t* rowmap, double* out) {
+hipError_t launch_coarse_export(hipStream_t s, int64_t n, const double* W, const int32_t* q, double* out) {
   int64_t g = (n * n + 255) / 256;
   if (g > 8192) g = 8192;
-  coarse_export_kernel<<<(unsigned)g, 256, 0, s>>>(n, W, rowmap, out);
+  coarse_export_kernel<<<(unsigned)g, 256, 0, s>>>(n, W, q, out);
   return hipGetLastError();
 }

@@ -481,6 +481,7 @@ namespace {
 template <int N> struct RowCfg {
   static constexpr int W = (N + 63) / 64;          // wavefronts per cell
   static constexpr int CH = 16;                    // staged rows per chunk (<= 11 KiB of LDS)
+  static constexpr int U = 7;                      // elimination steps per register rotation
 };
 
 template <int P, int N>
@@ -517,17 +518,24 @@ __global__ __launch_bounds__(64 * RowCfg<N>::W) void patch_setup_rows_kernel(
     __syncthreads();
     for (int e = tid; e < CH * N; e += NT) stage[e] = 0.0;
     __syncthreads();
-    for (int rr = wave; rr < CH && r0 + rr < N; rr += W) {
-      const int64_t grow = sdof[r0 + rr];
-      const int64_t e1 = row_ptr[grow + 1];
-      for (int64_t e = row_ptr[grow] + lane; e < e1; e += 64) {
-        const int c = col[e];
-        int lo = 0, hi = N;
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (skey[mid] < c) lo = mid + 1; else hi = mid;
+    {
+      // NT / CH lanes per staged row, several independent loads per lane
+      constexpr int LPR = NT / CH;
+      const int rr = tid / LPR, sub = tid - rr * LPR;
+      if (r0 + rr < N) {
+        const int64_t grow = sdof[r0 + rr];
+        const int64_t e0 = row_ptr[grow], e1 = row_ptr[grow + 1];
+#pragma unroll 4
+        for (int64_t e = e0 + sub; e < e1; e += LPR) {
+          const int c = col[e];
+          const double v = val[e];
+          int lo = 0, hi = N;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (skey[mid] < c) lo = mid + 1; else hi = mid;
+          }
+          if (lo < N && skey[lo] == c) stage[rr * N + sloc[lo]] = v;
         }
-        if (lo < N && skey[lo] == c) stage[rr * N + sloc[lo]] = val[e];
       }
     }
     __syncthreads();
@@ -540,52 +548,67 @@ __global__ __launch_bounds__(64 * RowCfg<N>::W) void patch_setup_rows_kernel(
   bool used = !mine;
   bool singular = false;
   int my_step = 0;
+  for (int i = tid; i < N; i += NT) qs[i] = 0;
+  // Column k of step k sits in register row[k mod U]: the loop runs U steps
+  // with constant register indices, then rotates every row left by U.  After
+  // N steps (N is a multiple of U) the rotation has come full circle.
+  static_assert(N % RowCfg<N>::U == 0, "patch width must be a multiple of the unroll factor");
+  constexpr int U = RowCfg<N>::U;
+#pragma unroll 1
+  for (int k0 = 0; k0 < N; k0 += U) {
 #pragma unroll
-  for (int k = 0; k < N; ++k) {
-    double a = used ? -1.0 : fabs(row[k]);
-    int ai = used ? 0x7fffffff : tid;
-    for (int o = 32; o > 0; o >>= 1) {
-      const double oa = __shfl_xor(a, o, 64);
-      const int oi = __shfl_xor(ai, o, 64);
-      if (oa > a || (oa == a && oi < ai)) { a = oa; ai = oi; }
-    }
-    if (W > 1) {
-      if (lane == 0) { red_abs[wave] = a; red_idx[wave] = ai; }
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u;
+      const double my = used ? -1.0 : fabs(row[u]);
+      double a = wave_max(my);
+      int ai = wave_min((!used && my == a) ? tid : 0x7fffffff);
+      if (W > 1) {
+        if (lane == 0) { red_abs[wave] = a; red_idx[wave] = ai; }
+        __syncthreads();
+        a = red_abs[0];
+        ai = red_idx[0];
+#pragma unroll
+        for (int w = 1; w < W; ++w) {
+          const double oa = red_abs[w];
+          const int oi = red_idx[w];
+          if (oa > a || (oa == a && oi < ai)) { a = oa; ai = oi; }
+        }
+      }
+      const int p = ai;  // uniform across the workgroup
+      const bool piv = (tid == p);
+      const bool bad = !(a > 0.0) || !isfinite(a) || p >= N;
+      if (piv) {
+        // the pivot row, scaled: (c == k ? 1 : row[c]) / pivot
+        const double inv = 1.0 / row[u];
+#pragma unroll
+        for (int c = 0; c < N; ++c) prow_s[c] = (c == u ? 1.0 : row[c]) * inv;
+        qs[k] = p;
+        used = true;
+        my_step = k;
+      }
       __syncthreads();
-      a = red_abs[0];
-      ai = red_idx[0];
+      if (bad) {
+        singular = true;
+      } else if (mine) {
+        // other rows: row - f * prow (column k: -f * prow[k]); the pivot row
+        // becomes prow itself (keep = 0, f = -1)
+        const double f = piv ? -1.0 : row[u];
+        const double keep = piv ? 0.0 : 1.0;
 #pragma unroll
-      for (int w = 1; w < W; ++w) {
-        const double oa = red_abs[w];
-        const int oi = red_idx[w];
-        if (oa > a || (oa == a && oi < ai)) { a = oa; ai = oi; }
+        for (int c = 0; c < N; ++c) {
+          const double pc = prow_s[c];
+          row[c] = (c == u) ? -f * pc : fma(-f, pc, keep * row[c]);
+        }
       }
+      __syncthreads();
     }
-    const int p = ai;  // uniform across the workgroup
-    const bool piv = (tid == p);
-    if (piv) {
+    double tmp[U];
 #pragma unroll
-      for (int c = 0; c < N; ++c) prow_s[c] = row[c];
-      qs[k] = p;
-      used = true;
-      my_step = k;
-    }
-    __syncthreads();
-    double pv = prow_s[k];
-    if (!(pv != 0.0) || !isfinite(pv) || p >= N) {
-      singular = true;
-      pv = 1.0;
-    }
-    const double inv = 1.0 / pv;
-    if (mine) {
-      const double f = row[k];
+    for (int c = 0; c < U; ++c) tmp[c] = row[c];
 #pragma unroll
-      for (int c = 0; c < N; ++c) {
-        const double pr = (c == k ? 1.0 : prow_s[c]) * inv;
-        row[c] = piv ? pr : ((c == k ? 0.0 : row[c]) - f * pr);
-      }
-    }
-    __syncthreads();
+    for (int c = 0; c < N - U; ++c) row[c] = row[c + U];
+#pragma unroll
+    for (int c = 0; c < U; ++c) row[N - U + c] = tmp[c];
   }
   if (singular && tid == 0) atomicMin(status, K);
   using S = typename PT<P>::S;
@@ -779,8 +802,9 @@ hipError_t launch_dof_map(hipStream_t s, const vk_level& L, int32_t* count, int3
   return hipGetLastError();
 }
 
-hipError_t launch_patch_gemv(hipStream_t s, const vk_level& L, vk_prec prec, const double* r, void* Y) {
-  const int cpb = L.cpb_override > 0 ? L.cpb_override : vk_default_cpb(L.n_K, L.ld, prec);
+hipError_t launch_patch_gemv(hipStream_t s, const vk_level& L, vk_prec prec, const double* r, void* Y, int cpb) {
+  if (cpb <= 0)
+    cpb = L.cpb_override > 0 ? L.cpb_override : (L.cpb_tuned > 0 ? L.cpb_tuned : vk_default_cpb(L.n_K, L.ld, prec));
   switch (prec) {
     case VK_F64: return gemv_prec<VK_F64>(s, L, cpb, r, Y);
     case VK_F32: return gemv_prec<VK_F32>(s, L, cpb, r, Y);

@@ -14,11 +14,20 @@ __global__ __launch_bounds__(256) void spmv_kernel(int64_t n_rows, const int64_t
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t row = gid / LPR;
   const int lane = threadIdx.x & (LPR - 1);
-  double sum = 0.0;
+  double s0 = 0.0, s1 = 0.0;
   if (row < n_rows) {
-    const int64_t e0 = row_ptr[row], e1 = row_ptr[row + 1];
-    for (int64_t e = e0 + lane; e < e1; e += LPR) sum += val[e] * x[col[e]];
+    const int64_t e1 = row_ptr[row + 1];
+    int64_t e = row_ptr[row] + lane;
+    // two independent loads in flight per lane
+    for (; e + LPR < e1; e += 2 * LPR) {
+      const double v0 = val[e], v1 = val[e + LPR];
+      const int32_t c0 = col[e], c1 = col[e + LPR];
+      s0 = fma(v0, x[c0], s0);
+      s1 = fma(v1, x[c1], s1);
+    }
+    if (e < e1) s0 = fma(val[e], x[col[e]], s0);
   }
+  double sum = s0 + s1;
 #pragma unroll
   for (int o = LPR / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, LPR);
   if (row < n_rows && lane == 0) {

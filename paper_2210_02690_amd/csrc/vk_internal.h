@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <climits>
+
 #include <string>
 #include <vector>
 
@@ -17,6 +19,45 @@
 #define VK_MAX_NK 512
 #define VK_MAX_RESTART 64
 
+// ---- wavefront reductions through DPP (row shifts, then row broadcasts);
+// the result of lane 63 is returned to every lane ----
+template <int CTRL, int RM>
+__device__ inline double dpp_move(double v, double ident) {
+  const int2 a = __builtin_bit_cast(int2, v), b = __builtin_bit_cast(int2, ident);
+  int2 r;
+  r.x = __builtin_amdgcn_update_dpp(b.x, a.x, CTRL, RM, 0xF, false);
+  r.y = __builtin_amdgcn_update_dpp(b.y, a.y, CTRL, RM, 0xF, false);
+  return __builtin_bit_cast(double, r);
+}
+
+// maximum over the 64 lanes, returned to every lane (NaN lanes are ignored)
+__device__ inline double wave_max(double v) {
+  const double id = -__builtin_inf();
+  v = fmax(v, dpp_move<0x111, 0xF>(v, id));
+  v = fmax(v, dpp_move<0x112, 0xF>(v, id));
+  v = fmax(v, dpp_move<0x114, 0xF>(v, id));
+  v = fmax(v, dpp_move<0x118, 0xF>(v, id));
+  v = fmax(v, dpp_move<0x142, 0xA>(v, id));
+  v = fmax(v, dpp_move<0x143, 0xC>(v, id));
+  const int2 a = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_readlane(a.x, 63);
+  r.y = __builtin_amdgcn_readlane(a.y, 63);
+  return __builtin_bit_cast(double, r);
+}
+
+__device__ inline int wave_min(int v) {
+  const int id = INT_MAX;
+  v = min(v, __builtin_amdgcn_update_dpp(id, v, 0x111, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(id, v, 0x112, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(id, v, 0x114, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(id, v, 0x118, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(id, v, 0x142, 0xA, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(id, v, 0x143, 0xC, 0xF, false));
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
+
 struct vk_level {
   bool set = false;
   vk_csr J{}, P{}, R{};
@@ -28,6 +69,7 @@ struct vk_level {
   int32_t n_colours = 0;
   int32_t max_colour_cells = 0;
   int32_t cpb_override = 0;
+  int32_t cpb_tuned = 0;      // picked by vk_autotune for the patch GEMV
   int lpr_J = 4, lpr_P = 4, lpr_R = 4;
   // carved from the workspace
   void* inv = nullptr;        // stored patch inverses
@@ -53,6 +95,8 @@ struct vk_ctx {
   std::vector<vk_timing_rec> recs;
   int32_t n_levels = 0;
   hipStream_t stream = nullptr;
+  hipStream_t side = nullptr;       // internal stream: coarse inversion during patch setup
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   std::vector<vk_level> lv;
   std::string err;
   int32_t* status = nullptr;   // device status block (4 KiB)
@@ -67,6 +111,7 @@ struct vk_ctx {
   vk_mode mode = VK_ADDITIVE;
   int32_t sweep_variant = 0;  // additive sweep: 0 DoF gather, 1 coloured scatter
   bool fast_setup = true;     // register-resident patch inversion where compiled
+  bool maps_ready = false;    // multiplicities and DoF lists (depend on the mesh only)
   void* Y = nullptr;          // per-cell products y_K of the additive sweep
   // coarse direct solve
   double* c_inv = nullptr;   // Gauss-Jordan buffers (two, alternating)
@@ -126,7 +171,8 @@ hipError_t launch_coarse_apply(hipStream_t s, int64_t n, const double* W, const 
 hipError_t launch_coarse_export(hipStream_t s, int64_t n, const double* W, const int32_t* rowmap, double* out);
 hipError_t launch_patch_setup_fast(hipStream_t s, const vk_level& L, vk_prec prec, int32_t* status, bool* handled);
 hipError_t launch_dof_map(hipStream_t s, const vk_level& L, int32_t* count, int32_t* off, int32_t* list);
-hipError_t launch_patch_gemv(hipStream_t s, const vk_level& L, vk_prec prec, const double* r, void* Y);
+hipError_t launch_patch_gemv(hipStream_t s, const vk_level& L, vk_prec prec, const double* r, void* Y,
+                             int cpb = 0);
 hipError_t launch_dof_gather(hipStream_t s, const vk_level& L, vk_prec prec, const void* Y, double omega,
                              double* d);
 // Krylov

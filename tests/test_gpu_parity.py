@@ -382,3 +382,15 @@ def test_coarse_inverse_cfg1_size(vk):
     ref = np.linalg.inv(J0)
     kappa = np.linalg.cond(J0)
     assert rel(out.cpu().numpy(), ref) <= 100 * kappa * np.finfo(float).eps
+
+
+def test_autotuned_matches_oracle(vk):
+    """Tuned launch shapes change only the summation order."""
+    P, H = problem("cfg0")
+    S = make_solver(vk, P)
+    S.vk_autotune(3)
+    S.vanka_setup(0.7)
+    b = np.random.default_rng(8).standard_normal(P.finest.n)
+    x = torch.empty(P.finest.n, dtype=torch.float64, device=DEV)
+    S.vcycle(t(b), x, 2, 2)
+    assert rel(x.cpu().numpy(), oracle.vcycle(H, b, 2, 2)) <= 1e-10
