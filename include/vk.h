@@ -99,6 +99,48 @@ vk_status vk_set_level(vk_ctx* ctx, int32_t l, const vk_csr* J, const vk_csr* P,
                        int32_t n_cells, int32_t n_K, const int32_t* cell_dofs,
                        const int32_t* colour_cells, const int32_t* colour_ptr, int32_t n_colours);
 
+/* ---- several independent systems in one context (batching) -------------
+ * A batch of independent systems is described level by level from the finest
+ * down: level L - d of the context holds, for every system s, its level
+ * L_s - d (block-diagonal concatenation).  Cells are given in groups of equal
+ * patch width (one group per k); systems whose coarsest level is reached at
+ * this depth are listed as diagonal blocks solved directly (their rows carry no
+ * cells); level 0 holds only blocks.  Every stage of the V-cycle then runs as
+ * one launch over all systems. */
+typedef struct {
+  int32_t n_cells;
+  int32_t n_K;
+  const int32_t* cell_dofs;     /* device, n_cells x n_K, level-global DoF numbers */
+  const int32_t* colour_cells;  /* device, n_cells, cells sorted by colour */
+  const int32_t* colour_ptr;    /* host, n_colours + 1 */
+  int32_t n_colours;
+} vk_cell_group;
+
+/* General form of vk_set_level: n_groups cell groups (levels >= 1) and
+ * n_blocks directly solved diagonal blocks, rows [block_rows[b],
+ * block_rows[b+1]) (host array, n_blocks + 1 entries, at most 4096 rows per
+ * block).  A block must not be coupled to rows outside it (checked at setup).
+ * vk_set_level(l = 0) is one block covering the level; vk_set_level(l >= 1) one
+ * group and no blocks. */
+vk_status vk_set_level_groups(vk_ctx* ctx, int32_t l, const vk_csr* J, const vk_csr* P, const vk_csr* R,
+                              int32_t n_groups, const vk_cell_group* groups, int32_t n_blocks,
+                              const int64_t* block_rows);
+
+/* Split the finest level into n_seg independent systems, rows
+ * [seg_rows[i], seg_rows[i+1]) (host array).  Call after setting the finest
+ * level and before vk_set_workspace; default: one segment. */
+vk_status vk_set_segments(vk_ctx* ctx, int32_t n_seg, const int64_t* seg_rows);
+
+/* GMRES for every segment at once (Sec. 3 method per system, each with its own
+ * Krylov space, Givens rotations and stopping test), Arnoldi steps in
+ * lockstep: one V-cycle over all systems per step, converged systems idle.
+ * Outputs (host, n_seg entries each): iters, true_rel_res; *all_converged
+ * (host, may be NULL).  Returns VK_ERR_NOCONV if a system missed the
+ * tolerance. */
+vk_status gmres_solve_batched(vk_ctx* ctx, const double* b, double* x, int32_t restart, int32_t max_iter,
+                              double rtol, double atol, int32_t nu_pre, int32_t nu_post, int32_t* iters,
+                              double* true_rel_res, int32_t* all_converged);
+
 /* Bytes of device workspace needed for patch inverses stored in `prec`, GMRES
  * restart length `restart` and the current levels.  Host-only query. */
 size_t vk_workspace_bytes(const vk_ctx* ctx, vk_prec prec, int32_t restart);

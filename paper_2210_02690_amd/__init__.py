@@ -38,6 +38,12 @@ class vk_csr(ctypes.Structure):
                 ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
 
 
+class vk_cell_group(ctypes.Structure):
+    _fields_ = [("n_cells", ctypes.c_int32), ("n_K", ctypes.c_int32), ("cell_dofs", ctypes.c_void_p),
+                ("colour_cells", ctypes.c_void_p), ("colour_ptr", ctypes.POINTER(ctypes.c_int32)),
+                ("n_colours", ctypes.c_int32)]
+
+
 _P = ctypes.c_void_p
 _I32, _I64, _D, _SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
 _PI32, _PI64, _PD = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
@@ -63,6 +69,11 @@ _SIGS = {
     "vk_set_sweep_variant": (ctypes.c_int, [_P, _I32]),
     "vk_set_setup_variant": (ctypes.c_int, [_P, _I32]),
     "vk_autotune": (ctypes.c_int, [_P, _I32]),
+    "vk_set_level_groups": (ctypes.c_int, [_P, _I32, ctypes.POINTER(vk_csr), ctypes.POINTER(vk_csr),
+                                           ctypes.POINTER(vk_csr), _I32, ctypes.POINTER(vk_cell_group), _I32,
+                                           _PI64]),
+    "vk_set_segments": (ctypes.c_int, [_P, _I32, _PI64]),
+    "gmres_solve_batched": (ctypes.c_int, [_P, _P, _P, _I32, _I32, _D, _D, _I32, _I32, _PI32, _PD, _PI32]),
     "vk_timing_read": (ctypes.c_int, [_P, _I32, _I32, _PI64, _PD]),
 }
 KERNEL_KINDS = {"patch_apply": 0, "spmv": 1, "patch_setup": 2, "patch_residual": 3, "patch_gemv": 4,
@@ -136,6 +147,30 @@ def upload_level(level, device):
     return out
 
 
+def _colour_order(colours):
+    colours = np.asarray(colours, dtype=np.int32)
+    order = np.argsort(colours, kind="stable").astype(np.int32)
+    n_col = int(colours.max()) + 1 if colours.size else 1
+    ptr = np.concatenate([[0], np.cumsum(np.bincount(colours, minlength=n_col))]).astype(np.int32)
+    return order, ptr, n_col
+
+
+def upload_packed_level(level, device):
+    """Device tensors of one packed batch level (synth.batch.PackedLevel)."""
+    import torch
+    out = {"J": upload_csr(level.J, device),
+           "P": upload_csr(level.P, device) if level.P is not None else None,
+           "R": upload_csr(level.R, device) if level.R is not None else None,
+           "groups": [], "blocks": np.asarray(level.blocks, dtype=np.int64)}
+    for g in level.groups:
+        order, ptr, n_col = _colour_order(g["colours"])
+        cd = np.ascontiguousarray(g["cell_dofs"], dtype=np.int32)
+        out["groups"].append(dict(n_cells=cd.shape[0], n_K=cd.shape[1], cell_dofs=torch.from_numpy(cd).to(device),
+                                  colour_cells=torch.from_numpy(order).to(device), colour_ptr=ptr,
+                                  n_colours=n_col))
+    return out
+
+
 class Solver:
     """Owns a vk_ctx and the device tensors it points to."""
 
@@ -152,6 +187,22 @@ class Solver:
             J = csr_struct(lv["J"])
             P = csr_struct(lv["P"]) if l > 0 else None
             R = csr_struct(lv["R"]) if l > 0 else None
+            if "groups" in lv:
+                gs = (vk_cell_group * max(1, len(lv["groups"])))()
+                for i, g in enumerate(lv["groups"]):
+                    ptr = np.ascontiguousarray(g["colour_ptr"], dtype=np.int32)
+                    self._keep.append(ptr)
+                    gs[i] = vk_cell_group(int(g["n_cells"]), int(g["n_K"]), g["cell_dofs"].data_ptr(),
+                                          g["colour_cells"].data_ptr(), ptr.ctypes.data_as(_PI32),
+                                          int(g["n_colours"]))
+                blocks = np.ascontiguousarray(lv["blocks"], dtype=np.int64)
+                self._keep += [gs, blocks]
+                nb = max(0, len(blocks) - 1)
+                self._check(_lib.vk_set_level_groups(
+                    self.ctx, l, ctypes.byref(J), ctypes.byref(P) if P is not None else None,
+                    ctypes.byref(R) if R is not None else None, len(lv["groups"]), gs, nb,
+                    blocks.ctypes.data_as(_PI64) if nb else None))
+                continue
             ptr = np.ascontiguousarray(lv["colour_ptr"], dtype=np.int32)
             self._keep.append(ptr)
             self._check(_lib.vk_set_level(
@@ -221,6 +272,24 @@ class Solver:
         if st != VK_OK and not (st == VK_ERR_NOCONV and not raise_on_noconv):
             raise VkError(st, _lib.vk_last_error(self.ctx).decode())
         return its.value, rel.value, np.array(hist[: its.value + 1]), st == VK_OK
+
+    def vk_set_segments(self, seg_rows):
+        seg = np.ascontiguousarray(seg_rows, dtype=np.int64)
+        self._keep.append(seg)
+        self._check(_lib.vk_set_segments(self.ctx, len(seg) - 1, seg.ctypes.data_as(_PI64)))
+        self.n_seg = len(seg) - 1
+
+    def gmres_solve_batched(self, b, x, restart=30, max_iter=300, rtol=1e-8, atol=0.0, nu_pre=2, nu_post=2,
+                            raise_on_noconv=True):
+        ns = getattr(self, "n_seg", 1)
+        its = (ctypes.c_int32 * ns)()
+        rel = (ctypes.c_double * ns)()
+        conv = _I32(0)
+        st = _lib.gmres_solve_batched(self.ctx, _ptr(b), _ptr(x), restart, max_iter, rtol, atol, nu_pre, nu_post,
+                                      its, rel, ctypes.byref(conv))
+        if st != VK_OK and not (st == VK_ERR_NOCONV and not raise_on_noconv):
+            raise VkError(st, _lib.vk_last_error(self.ctx).decode())
+        return np.array(its[:]), np.array(rel[:]), bool(conv.value)
 
     def vk_spmv(self, l, x, y, alpha=1.0, beta=0.0, z=None):
         self._check(_lib.vk_spmv(self.ctx, l, alpha, _ptr(x), beta, _ptr(z), _ptr(y)))

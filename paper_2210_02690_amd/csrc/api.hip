@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 
 #include "vk_internal.h"
@@ -91,25 +92,33 @@ size_t plan_workspace(vk_ctx* ctx, vk_prec prec, int32_t restart, char* base) {
     L.b = cv.take<double>(n);
     L.d = cv.take<double>(n);
     L.r = cv.take<double>(n);
-    if (l == 0) continue;
-    L.ld = (int32_t)round_up(L.n_K, vw);
-    L.cell_stride = (int64_t)L.n_K * L.ld;
-    L.inv = cv.take<char>((int64_t)L.n_cells * L.cell_stride * sb);
-    L.inv_p = cv.take<double>(n);
-    L.dof_off = cv.take<int32_t>(n + 1);
-    L.dof_list = cv.take<int32_t>((int64_t)L.n_cells * L.n_K);
-    if ((int64_t)L.n_cells * L.n_K > ycount) ycount = (int64_t)L.n_cells * L.n_K;
-    if (L.n_K > VK_LDS_SETUP_MAX_NK) {
-      if (L.n_K > big_nk) big_nk = L.n_K;
-      if (L.n_cells > big_cells) big_cells = L.n_cells;
+    if (!L.groups.empty()) {
+      L.inv_p = cv.take<double>(n);
+      L.dof_off = cv.take<int32_t>(n + 1);
+      L.dof_list = cv.take<int32_t>(L.n_items > 0 ? L.n_items : 1);
+      if (L.n_items > ycount) ycount = L.n_items;
     }
-    const int64_t r = (int64_t)L.max_colour_cells * L.n_K;
-    if (r > rk) rk = r;
+    for (vk_group& G : L.groups) {
+      G.ld = (int32_t)round_up(G.n_K, vw);
+      G.cell_stride = (int64_t)G.n_K * G.ld;
+      G.inv = cv.take<char>((int64_t)G.n_cells * G.cell_stride * sb);
+      if (G.n_K > VK_LDS_SETUP_MAX_NK) {
+        if (G.n_K > big_nk) big_nk = G.n_K;
+        if (G.n_cells > big_cells) big_cells = G.n_cells;
+      }
+      const int64_t r = (int64_t)G.max_colour_cells * G.n_K;
+      if (r > rk) rk = r;
+    }
+    const int nbk = (int)L.cb_rows.size() - 1;
+    if (nbk > 0) {
+      L.cb_a = cv.take<double>(L.cb_sq);
+      L.cb_b = cv.take<double>(L.cb_sq);
+      L.d_cb_rows = cv.take<int64_t>(nbk + 1);
+      L.d_cb_woff = cv.take<int64_t>(nbk);
+      L.cb_q = cv.take<int32_t>(n);
+      L.cb_used = cv.take<int32_t>(n);
+    }
   }
-  const int64_t n0 = ctx->lv[0].J.n_rows;
-  ctx->c_inv = cv.take<double>(n0 * n0);
-  ctx->c_tmp = cv.take<double>(n0 * n0);
-  ctx->c_perm = cv.take<int32_t>(2 * n0);
   if (big_nk > 0) {
     const int64_t per = (int64_t)big_nk * big_nk;
     int64_t chunk = (int64_t)(512ll << 20) / (per * 8);
@@ -126,18 +135,42 @@ size_t plan_workspace(vk_ctx* ctx, vk_prec prec, int32_t restart, char* base) {
   const int64_t nL = ctx->lv[nl - 1].J.n_rows;
   ctx->n_pad = round_up(nL, 32);
   const int32_t m = restart;
+  const int32_t ns = ctx->n_seg;
   ctx->V = cv.take<double>((int64_t)(m + 1) * ctx->n_pad);
   ctx->Z = cv.take<double>((int64_t)m * ctx->n_pad);
-  ctx->H = cv.take<double>((int64_t)(m + 1) * m);
-  ctx->h2 = cv.take<double>(m + 1);
-  ctx->cs = cv.take<double>(m);
-  ctx->sn = cv.take<double>(m);
-  ctx->g = cv.take<double>(m + 1);
-  ctx->y = cv.take<double>(m);
-  ctx->n_partial = 1024 * (m + 1);
+  ctx->H = cv.take<double>((int64_t)ns * (m + 1) * m);
+  ctx->h2 = cv.take<double>((int64_t)ns * (m + 1));
+  ctx->cs = cv.take<double>((int64_t)ns * m);
+  ctx->sn = cv.take<double>((int64_t)ns * m);
+  ctx->g = cv.take<double>((int64_t)ns * (m + 1));
+  ctx->y = cv.take<double>((int64_t)ns * m);
+  ctx->n_partial = (ns * 64 > 1024 ? ns * 64 : 1024) * (m + 1);
   ctx->partial = cv.take<double>(ctx->n_partial);
   ctx->scal = cv.take<double>(16);
+  ctx->d_seg = cv.take<int64_t>(ns + 1);
+  ctx->seg_scal = cv.take<double>(5 * (int64_t)ns);
+  ctx->seg_flags = cv.take<int32_t>(3 * (int64_t)ns);
   return cv.off;
+}
+
+// host tables that kernels read: block offsets, block storage offsets, segments
+vk_status upload_tables(vk_ctx* ctx) {
+  for (int l = 0; l < ctx->n_levels; ++l) {
+    vk_level& L = ctx->lv[l];
+    const int nbk = (int)L.cb_rows.size() - 1;
+    if (nbk <= 0) continue;
+    std::vector<int64_t> woff(nbk);
+    int64_t acc = 0;
+    for (int b = 0; b < nbk; ++b) {
+      woff[b] = acc;
+      const int64_t nb = L.cb_rows[b + 1] - L.cb_rows[b];
+      acc += nb * nb;
+    }
+    VK_TRY(hipMemcpy(L.d_cb_rows, L.cb_rows.data(), sizeof(int64_t) * (nbk + 1), hipMemcpyHostToDevice));
+    VK_TRY(hipMemcpy(L.d_cb_woff, woff.data(), sizeof(int64_t) * nbk, hipMemcpyHostToDevice));
+  }
+  VK_TRY(hipMemcpy(ctx->d_seg, ctx->seg_rows.data(), sizeof(int64_t) * (ctx->n_seg + 1), hipMemcpyHostToDevice));
+  return VK_OK;
 }
 
 constexpr int32_t kTimingPool = 16384;
@@ -171,26 +204,33 @@ vk_status smooth(vk_ctx* ctx, int l, const double* b, double* d, int32_t sweeps,
         r = L.r;
       }
       if (ctx->sweep_variant == 0) {
-        {
+        for (const vk_group& G : L.groups) {
           Timed t(ctx, VK_KERNEL_PATCH_GEMV, l);
-          VK_TRY(launch_patch_gemv(s, L, ctx->prec, r, ctx->Y));
+          VK_TRY(launch_patch_gemv(s, G, ctx->prec, r, ctx->Y));
         }
         Timed t(ctx, VK_KERNEL_DOF_GATHER, l);
         VK_TRY(launch_dof_gather(s, L, ctx->prec, ctx->Y, ctx->omega, d));
       } else {
-        for (int c = 0; c < L.n_colours; ++c) {
-          Timed t(ctx, VK_KERNEL_PATCH_APPLY, l);
-          VK_TRY(launch_patch_apply(s, L, ctx->prec, c, r, nullptr, d, ctx->omega, true));
-        }
+        for (const vk_group& G : L.groups)
+          for (int c = 0; c < G.n_colours; ++c) {
+            Timed t(ctx, VK_KERNEL_PATCH_APPLY, l);
+            VK_TRY(launch_patch_apply(s, G, ctx->prec, c, r, nullptr, d, L.inv_p, ctx->omega));
+          }
       }
     } else {
-      for (int c = 0; c < L.n_colours; ++c) {
-        {
-          Timed t(ctx, VK_KERNEL_PATCH_RESIDUAL, l);
-          VK_TRY(launch_patch_residual(s, L, c, b, d, ctx->rK));
+      // groups are independent systems: colour c of every group, then colour c + 1
+      int max_c = 0;
+      for (const vk_group& G : L.groups) max_c = G.n_colours > max_c ? G.n_colours : max_c;
+      for (int c = 0; c < max_c; ++c) {
+        for (const vk_group& G : L.groups) {
+          if (c >= G.n_colours) continue;
+          {
+            Timed t(ctx, VK_KERNEL_PATCH_RESIDUAL, l);
+            VK_TRY(launch_patch_residual(s, L.J, L.lpr_J, G, c, b, d, ctx->rK));
+          }
+          Timed t(ctx, VK_KERNEL_PATCH_APPLY, l);
+          VK_TRY(launch_patch_apply(s, G, ctx->prec, c, nullptr, ctx->rK, d, nullptr, ctx->omega));
         }
-        Timed t(ctx, VK_KERNEL_PATCH_APPLY, l);
-        VK_TRY(launch_patch_apply(s, L, ctx->prec, c, nullptr, ctx->rK, d, ctx->omega, false));
       }
     }
   }
@@ -199,20 +239,18 @@ vk_status smooth(vk_ctx* ctx, int l, const double* b, double* d, int32_t sweeps,
 
 vk_status vcycle_level(vk_ctx* ctx, int l, const double* b, double* x, int32_t nu1, int32_t nu2) {
   hipStream_t s = ctx->stream;
+  vk_level& L = ctx->lv[l];
   if (l == 0) {
-    VK_TRY(launch_coarse_apply(s, ctx->lv[0].J.n_rows, ctx->c_W, ctx->c_perm, b, x));
+    VK_TRY(launch_block_apply(s, L, b, x));
     return VK_OK;
   }
-  vk_level& L = ctx->lv[l];
   vk_level& C = ctx->lv[l - 1];
-  if (nu1 > 0) {
-    VK_CHECK(smooth(ctx, l, b, x, nu1, true));
-    VK_TRY(launch_spmv(s, L.J, L.lpr_J, -1.0, x, 1.0, b, L.r));
-    VK_TRY(launch_spmv(s, L.R, L.lpr_R, 1.0, L.r, 0.0, nullptr, C.b));
-  } else {
-    VK_TRY(launch_fill(s, L.J.n_rows, 0.0, x));
-    VK_TRY(launch_spmv(s, L.R, L.lpr_R, 1.0, b, 0.0, nullptr, C.b));
-  }
+  if (nu1 > 0) VK_CHECK(smooth(ctx, l, b, x, nu1, true));
+  else VK_TRY(launch_fill(s, L.J.n_rows, 0.0, x));
+  // systems whose coarsest level is this one are solved directly (their rows carry no cells)
+  VK_TRY(launch_block_apply(s, L, b, x));
+  VK_TRY(launch_spmv(s, L.J, L.lpr_J, -1.0, x, 1.0, b, L.r));
+  VK_TRY(launch_spmv(s, L.R, L.lpr_R, 1.0, L.r, 0.0, nullptr, C.b));
   VK_CHECK(vcycle_level(ctx, l - 1, C.b, C.d, nu1, nu2));
   VK_TRY(launch_spmv(s, L.P, L.lpr_P, 1.0, C.d, 1.0, x, x));
   if (nu2 > 0) VK_CHECK(smooth(ctx, l, b, x, nu2, false));
@@ -286,45 +324,70 @@ void vk_destroy(vk_ctx* ctx) {
 
 const char* vk_last_error(const vk_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_err; }
 
-vk_status vk_set_level(vk_ctx* ctx, int32_t l, const vk_csr* J, const vk_csr* P, const vk_csr* R, int32_t n_cells,
-                       int32_t n_K, const int32_t* cell_dofs, const int32_t* colour_cells,
-                       const int32_t* colour_ptr, int32_t n_colours) {
+vk_status vk_set_level_groups(vk_ctx* ctx, int32_t l, const vk_csr* J, const vk_csr* P, const vk_csr* R,
+                              int32_t n_groups, const vk_cell_group* groups, int32_t n_blocks,
+                              const int64_t* block_rows) {
   if (!ctx) return VK_ERR_ARG;
   if (l < 0 || l >= ctx->n_levels) return fail(ctx, VK_ERR_ARG, "level index out of range");
   if (!csr_ok(J) || J->n_rows != J->n_cols || J->n_rows == 0)
     return fail(ctx, VK_ERR_ARG, "J must be a non-empty square CSR matrix with valid pointers");
   if (J->n_rows > INT32_MAX) return fail(ctx, VK_ERR_ARG, "J too large for int32 columns");
-  if (l == 0 && J->n_rows > vk_coarse_max_n())
-    return fail(ctx, VK_ERR_ARG, "the coarsest level exceeds the dense direct solver limit of 4096 unknowns");
+  if (n_groups < 0 || n_groups > 64 || (n_groups > 0 && !groups))
+    return fail(ctx, VK_ERR_ARG, "0 <= n_groups <= 64 cell groups required");
+  if (n_blocks < 0 || (n_blocks > 0 && !block_rows)) return fail(ctx, VK_ERR_ARG, "invalid block table");
+  if (l == 0 && (n_groups != 0 || n_blocks < 1))
+    return fail(ctx, VK_ERR_ARG, "level 0 is solved directly: no cell groups, at least one block");
+  if (l > 0 && n_groups < 1) return fail(ctx, VK_ERR_ARG, "levels >= 1 need at least one cell group");
   vk_level L;
   L.J = *J;
+  // directly solved diagonal blocks
+  if (n_blocks > 0) {
+    L.cb_rows.assign(block_rows, block_rows + n_blocks + 1);
+    for (int b = 0; b < n_blocks; ++b) {
+      const int64_t nb = L.cb_rows[b + 1] - L.cb_rows[b];
+      if (nb <= 0 || L.cb_rows[b] < 0 || L.cb_rows[b + 1] > J->n_rows)
+        return fail(ctx, VK_ERR_ARG, "blocks must be non-empty, increasing and inside the level");
+      if (nb > vk_coarse_max_n())
+        return fail(ctx, VK_ERR_ARG, "a directly solved block exceeds the dense solver limit of 4096 unknowns");
+      if (nb > L.cb_max) L.cb_max = nb;
+      L.cb_sq += nb * nb;
+    }
+  }
   if (l > 0) {
     if (!csr_ok(P) || !csr_ok(R)) return fail(ctx, VK_ERR_ARG, "levels >= 1 need prolongation P and restriction R");
     if (P->n_rows != J->n_rows || R->n_cols != J->n_rows || P->n_cols != R->n_rows)
       return fail(ctx, VK_ERR_ARG, "P must be n_l x n_{l-1} and R n_{l-1} x n_l");
-    if (n_cells <= 0 || n_K <= 0 || n_K > VK_MAX_NK)
-      return fail(ctx, VK_ERR_ARG, "n_cells must be positive and 1 <= n_K <= 512");
-    if (n_K > J->n_rows) return fail(ctx, VK_ERR_ARG, "n_K exceeds the number of unknowns");
-    if (!cell_dofs || !colour_cells || !colour_ptr || n_colours <= 0 || n_colours > 64)
-      return fail(ctx, VK_ERR_ARG, "cell_dofs, colour_cells, colour_ptr and 1 <= n_colours <= 64 required");
-    if (colour_ptr[0] != 0 || colour_ptr[n_colours] != n_cells)
-      return fail(ctx, VK_ERR_ARG, "colour_ptr must start at 0 and end at n_cells");
-    int32_t mx = 0;
-    for (int c = 0; c < n_colours; ++c) {
-      const int32_t cnt = colour_ptr[c + 1] - colour_ptr[c];
-      if (cnt < 0) return fail(ctx, VK_ERR_ARG, "colour_ptr must be non-decreasing");
-      if (cnt > mx) mx = cnt;
-    }
     L.P = *P;
     L.R = *R;
     L.has_transfer = true;
-    L.n_cells = n_cells;
-    L.n_K = n_K;
-    L.cell_dofs = cell_dofs;
-    L.colour_cells = colour_cells;
-    L.colour_ptr.assign(colour_ptr, colour_ptr + n_colours + 1);
-    L.n_colours = n_colours;
-    L.max_colour_cells = mx;
+    int64_t items = 0;
+    for (int gi = 0; gi < n_groups; ++gi) {
+      const vk_cell_group& in = groups[gi];
+      if (in.n_cells <= 0 || in.n_K <= 0 || in.n_K > VK_MAX_NK)
+        return fail(ctx, VK_ERR_ARG, "n_cells must be positive and 1 <= n_K <= 512");
+      if (in.n_K > J->n_rows) return fail(ctx, VK_ERR_ARG, "n_K exceeds the number of unknowns");
+      if (!in.cell_dofs || !in.colour_cells || !in.colour_ptr || in.n_colours <= 0 || in.n_colours > 64)
+        return fail(ctx, VK_ERR_ARG, "cell_dofs, colour_cells, colour_ptr and 1 <= n_colours <= 64 required");
+      if (in.colour_ptr[0] != 0 || in.colour_ptr[in.n_colours] != in.n_cells)
+        return fail(ctx, VK_ERR_ARG, "colour_ptr must start at 0 and end at n_cells");
+      vk_group G;
+      for (int c = 0; c < in.n_colours; ++c) {
+        const int32_t cnt = in.colour_ptr[c + 1] - in.colour_ptr[c];
+        if (cnt < 0) return fail(ctx, VK_ERR_ARG, "colour_ptr must be non-decreasing");
+        if (cnt > G.max_colour_cells) G.max_colour_cells = cnt;
+      }
+      G.n_cells = in.n_cells;
+      G.n_K = in.n_K;
+      G.cell_dofs = in.cell_dofs;
+      G.colour_cells = in.colour_cells;
+      G.colour_ptr.assign(in.colour_ptr, in.colour_ptr + in.n_colours + 1);
+      G.n_colours = in.n_colours;
+      G.y_off = items;
+      items += (int64_t)in.n_cells * in.n_K;
+      L.groups.push_back(G);
+    }
+    if (items > INT32_MAX) return fail(ctx, VK_ERR_ARG, "too many (cell, DoF) pairs on one level");
+    L.n_items = items;
   }
   // structural validation on the device
   hipStream_t s = ctx->stream;
@@ -333,7 +396,9 @@ vk_status vk_set_level(vk_ctx* ctx, int32_t l, const vk_csr* J, const vk_csr* P,
   if (l > 0) {
     VK_TRY(launch_validate_csr(s, L.P, ctx->status + 1000));
     VK_TRY(launch_validate_csr(s, L.R, ctx->status + 1000));
-    VK_TRY(launch_validate_cells(s, L.n_cells, L.n_K, L.cell_dofs, L.J.n_rows, L.colour_cells, ctx->status + 1000));
+    for (const vk_group& G : L.groups)
+      VK_TRY(launch_validate_cells(s, G.n_cells, G.n_K, G.cell_dofs, L.J.n_rows, G.colour_cells,
+                                   ctx->status + 1000));
   }
   int32_t flag = 0;
   VK_TRY(hipMemcpyAsync(&flag, ctx->status + 1000, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -353,6 +418,39 @@ vk_status vk_set_level(vk_ctx* ctx, int32_t l, const vk_csr* J, const vk_csr* P,
   }
   L.set = true;
   ctx->lv[l] = L;
+  if (l == ctx->n_levels - 1) {
+    ctx->seg_rows = {0, L.J.n_rows};
+    ctx->n_seg = 1;
+  }
+  ctx->ws_ready = false;
+  ctx->setup_done = false;
+  return VK_OK;
+}
+
+vk_status vk_set_level(vk_ctx* ctx, int32_t l, const vk_csr* J, const vk_csr* P, const vk_csr* R, int32_t n_cells,
+                       int32_t n_K, const int32_t* cell_dofs, const int32_t* colour_cells,
+                       const int32_t* colour_ptr, int32_t n_colours) {
+  if (!ctx) return VK_ERR_ARG;
+  if (l == 0) {
+    if (!J) return fail(ctx, VK_ERR_ARG, "J must be a non-empty square CSR matrix with valid pointers");
+    const int64_t rows[2] = {0, J->n_rows};
+    return vk_set_level_groups(ctx, 0, J, nullptr, nullptr, 0, nullptr, 1, rows);
+  }
+  vk_cell_group g{n_cells, n_K, cell_dofs, colour_cells, colour_ptr, n_colours};
+  return vk_set_level_groups(ctx, l, J, P, R, 1, &g, 0, nullptr);
+}
+
+vk_status vk_set_segments(vk_ctx* ctx, int32_t n_seg, const int64_t* seg_rows) {
+  if (!ctx) return VK_ERR_ARG;
+  const vk_level& F = ctx->lv[ctx->n_levels - 1];
+  if (!F.set) return fail(ctx, VK_ERR_STATE, "set the finest level before its segments");
+  if (n_seg < 1 || n_seg > 4096 || !seg_rows) return fail(ctx, VK_ERR_ARG, "1 <= n_seg <= 4096 segments required");
+  if (seg_rows[0] != 0 || seg_rows[n_seg] != F.J.n_rows)
+    return fail(ctx, VK_ERR_ARG, "segments must start at 0 and end at the finest level's size");
+  for (int i = 0; i < n_seg; ++i)
+    if (seg_rows[i + 1] <= seg_rows[i]) return fail(ctx, VK_ERR_ARG, "segments must be non-empty and increasing");
+  ctx->seg_rows.assign(seg_rows, seg_rows + n_seg + 1);
+  ctx->n_seg = n_seg;
   ctx->ws_ready = false;
   ctx->setup_done = false;
   return VK_OK;
@@ -363,6 +461,7 @@ size_t vk_workspace_bytes(const vk_ctx* cctx, vk_prec prec, int32_t restart) {
   if (prec != VK_F64 && prec != VK_F32 && prec != VK_BF16) return 0;
   if (!levels_consistent(cctx, nullptr)) return 0;
   vk_ctx tmp = *cctx;  // plan on a copy: the query does not touch the context
+  tmp.ev.clear();
   return plan_workspace(&tmp, prec, restart, nullptr);
 }
 
@@ -374,6 +473,7 @@ vk_status vk_set_workspace(vk_ctx* ctx, void* dev, size_t bytes, vk_prec prec, i
   if (!levels_consistent(ctx, &why)) return fail(ctx, VK_ERR_STATE, why);
   if (!dev || (reinterpret_cast<uintptr_t>(dev) & 255u)) return fail(ctx, VK_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   vk_ctx probe = *ctx;
+  probe.ev.clear();
   const size_t need = plan_workspace(&probe, prec, restart, nullptr);
   if (bytes < need) {
     char buf[160];
@@ -381,21 +481,24 @@ vk_status vk_set_workspace(vk_ctx* ctx, void* dev, size_t bytes, vk_prec prec, i
     return fail(ctx, VK_ERR_WORKSPACE, buf);
   }
   for (int l = 1; l < ctx->n_levels; ++l) {
-    const vk_level& L = ctx->lv[l];
-    const int ld = (int)round_up(L.n_K, vk_prec_vw(prec));
-    const int cpb = L.cpb_override > 0 ? L.cpb_override : vk_default_cpb(L.n_K, ld, prec);
-    if (cpb <= 0 || VK_NT / cpb < ld / vk_prec_vw(prec))
-      return fail(ctx, VK_ERR_ARG, "patch too wide for the apply kernel at this precision / tile");
+    for (const vk_group& G : ctx->lv[l].groups) {
+      const int ld = (int)round_up(G.n_K, vk_prec_vw(prec));
+      const int cpb = G.cpb_override > 0 ? G.cpb_override : vk_default_cpb(G.n_K, ld, prec);
+      if (cpb <= 0 || VK_NT / cpb < ld / vk_prec_vw(prec))
+        return fail(ctx, VK_ERR_ARG, "patch too wide for the apply kernel at this precision / tile");
+    }
   }
   ctx->ws = reinterpret_cast<char*>(dev);
   ctx->ws_bytes = bytes;
   ctx->prec = prec;
   ctx->restart = restart;
   plan_workspace(ctx, prec, restart, ctx->ws);
+  VK_CHECK(upload_tables(ctx));
   ctx->ws_ready = true;
   ctx->setup_done = false;
   ctx->maps_ready = false;
-  for (int l = 0; l < ctx->n_levels; ++l) ctx->lv[l].cpb_tuned = 0;
+  for (int l = 0; l < ctx->n_levels; ++l)
+    for (vk_group& G : ctx->lv[l].groups) G.cpb_tuned = 0;
   return VK_OK;
 }
 
@@ -410,45 +513,56 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
   ctx->omega = omega;
   ctx->mode = mode;
   hipStream_t s = ctx->stream;
-  VK_TRY(launch_fill_i32(s, 64, INT_MAX, ctx->status));
-  // the coarse inversion occupies one workgroup at a time: run it on the side
+  // status words: [0] directly solved blocks (pivot), [1] block coupling, [64 + l] first singular cell of level l
+  VK_TRY(launch_fill_i32(s, 2, INT_MAX, ctx->status));
+  VK_TRY(launch_fill_i32(s, 1, 0, ctx->status + 1));
+  VK_TRY(launch_fill_i32(s, 64, INT_MAX, ctx->status + 64));
+  // the block inversions occupy one workgroup per block: run them on the side
   // stream while the patch inversions fill the rest of the GPU
   VK_TRY(hipEventRecord(ctx->fork_ev, s));
   VK_TRY(hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0));
-  VK_TRY(launch_coarse_invert(ctx->side, ctx->lv[0].J, ctx->c_inv, ctx->c_tmp, ctx->c_perm, ctx->status,
-                              &ctx->c_W));
+  for (int l = 0; l < ctx->n_levels; ++l) {
+    vk_level& L = ctx->lv[l];
+    if (L.cb_rows.size() > 1) VK_TRY(launch_block_invert(ctx->side, L, ctx->status, &L.cb_W));
+  }
   VK_TRY(hipEventRecord(ctx->join_ev, ctx->side));
   if (!ctx->maps_ready) {
     // multiplicities and DoF -> (cell, local) lists depend on the mesh only
     for (int l = 1; l < ctx->n_levels; ++l) {
       vk_level& L = ctx->lv[l];
-      VK_TRY(launch_multiplicity(s, L.n_cells, L.n_K, L.cell_dofs, L.J.n_rows, reinterpret_cast<int32_t*>(L.r),
-                                 L.inv_p));
-      VK_TRY(launch_dof_map(s, L, reinterpret_cast<int32_t*>(L.r), L.dof_off, L.dof_list));
+      int32_t* count = reinterpret_cast<int32_t*>(L.r);
+      VK_TRY(launch_fill_i32(s, L.J.n_rows, 0, count));
+      for (const vk_group& G : L.groups) VK_TRY(launch_count_add(s, G.n_cells, G.n_K, G.cell_dofs, count));
+      VK_TRY(launch_inv_count(s, L.J.n_rows, count, L.inv_p));
+      VK_TRY(launch_dof_map(s, L, count));
     }
   }
   for (int l = 1; l < ctx->n_levels; ++l) {
     vk_level& L = ctx->lv[l];
     Timed t(ctx, VK_KERNEL_PATCH_SETUP, l);
-    bool handled = false;
-    if (ctx->fast_setup) VK_TRY(launch_patch_setup_fast(s, L, ctx->prec, ctx->status + l, &handled));
-    if (!handled) VK_TRY(launch_patch_setup(s, L, ctx->prec, ctx->big_scratch, ctx->big_chunk, ctx->status + l));
+    for (const vk_group& G : L.groups) {
+      bool handled = false;
+      if (ctx->fast_setup) VK_TRY(launch_patch_setup_fast(s, L.J, G, ctx->prec, ctx->status + 64 + l, &handled));
+      if (!handled)
+        VK_TRY(launch_patch_setup(s, L.J, G, ctx->prec, ctx->big_scratch, ctx->big_chunk, ctx->status + 64 + l));
+    }
   }
   VK_TRY(hipStreamWaitEvent(s, ctx->join_ev, 0));
-  int32_t st[64];
-  VK_TRY(hipMemcpyAsync(st, ctx->status, sizeof(int32_t) * 64, hipMemcpyDeviceToHost, s));
+  int32_t st[128];
+  VK_TRY(hipMemcpyAsync(st, ctx->status, sizeof(int32_t) * 128, hipMemcpyDeviceToHost, s));
   VK_TRY(hipStreamSynchronize(s));
+  if (st[1] != 0) return fail(ctx, VK_ERR_ARG, "a directly solved block is coupled to rows outside it");
   if (st[0] != INT_MAX) {
     if (bad_level) *bad_level = 0;
     if (bad_cell) *bad_cell = -1;
-    return fail(ctx, VK_ERR_SINGULAR, "coarsest-level matrix J_0 is singular (zero pivot)");
+    return fail(ctx, VK_ERR_SINGULAR, "a directly solved (coarsest-level) block is singular (zero pivot)");
   }
   for (int l = 1; l < ctx->n_levels; ++l) {
-    if (st[l] != INT_MAX) {
+    if (st[64 + l] != INT_MAX) {
       if (bad_level) *bad_level = l;
-      if (bad_cell) *bad_cell = st[l];
+      if (bad_cell) *bad_cell = st[64 + l];
       char buf[128];
-      snprintf(buf, sizeof(buf), "patch matrix of cell %d on level %d is singular (zero pivot)", st[l], l);
+      snprintf(buf, sizeof(buf), "patch matrix of cell %d on level %d is singular (zero pivot)", st[64 + l], l);
       return fail(ctx, VK_ERR_SINGULAR, buf);
     }
   }
@@ -565,6 +679,102 @@ vk_status gmres_solve(vk_ctx* ctx, const double* b, double* x, int32_t restart, 
   return VK_OK;
 }
 
+vk_status gmres_solve_batched(vk_ctx* ctx, const double* b, double* x, int32_t restart, int32_t max_iter,
+                              double rtol, double atol, int32_t nu_pre, int32_t nu_post, int32_t* iters,
+                              double* true_rel_res, int32_t* all_converged) {
+  VK_CHECK(ready(ctx));
+  if (!b || !x || b == x) return fail(ctx, VK_ERR_ARG, "b and x must be distinct non-null vectors");
+  if (restart < 1 || restart > ctx->restart) return fail(ctx, VK_ERR_ARG, "restart exceeds the workspace's value");
+  if (max_iter < 0 || nu_pre < 0 || nu_post < 0 || !(rtol >= 0.0) || !(atol >= 0.0))
+    return fail(ctx, VK_ERR_ARG, "negative iteration count, sweep count or tolerance");
+  if (!iters || !true_rel_res) return fail(ctx, VK_ERR_ARG, "per-segment outputs required");
+  hipStream_t s = ctx->stream;
+  const int L = ctx->n_levels - 1;
+  vk_level& F = ctx->lv[L];
+  const int32_t ns = ctx->n_seg;
+  const int64_t ldv = ctx->n_pad;
+  const int32_t m = restart;
+  int64_t max_len = 0;
+  for (int i = 0; i < ns; ++i) max_len = std::max(max_len, ctx->seg_rows[i + 1] - ctx->seg_rows[i]);
+  const int64_t* seg = ctx->d_seg;
+  double* bnorm = ctx->seg_scal;
+  double* tol = bnorm + ns;
+  double* beta = tol + ns;
+  double* resid = beta + ns;  // resid[ns .. 2 ns) = norms of the new Arnoldi vectors
+  int32_t* active = ctx->seg_flags;
+  int32_t* its = active + ns;
+  int32_t* jn = its + ns;
+  const int64_t hs = (int64_t)(m + 1) * m;
+  std::vector<double> hb(ns);
+  std::vector<int32_t> hi(ns);
+  VK_TRY(launch_seg_dot(s, ns, seg, max_len, b, b, ctx->partial, ctx->n_partial, bnorm, true));
+  VK_TRY(hipMemcpyAsync(hb.data(), bnorm, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+  VK_TRY(hipStreamSynchronize(s));
+  std::vector<double> tl(ns), bn(hb);
+  for (int i = 0; i < ns; ++i) {
+    if (!std::isfinite(bn[i])) return fail(ctx, VK_ERR_ARG, "right-hand side is not finite");
+    // b_i = 0: x_i = 0 is exact; an infinite tolerance keeps the segment inactive
+    tl[i] = bn[i] == 0.0 ? __builtin_inf() : std::fmax(rtol * bn[i], atol);
+  }
+  VK_TRY(hipMemcpyAsync(tol, tl.data(), sizeof(double) * ns, hipMemcpyHostToDevice, s));
+  VK_TRY(launch_fill_i32(s, ns, 0, its));
+  VK_TRY(hipStreamSynchronize(s));  // tl must outlive the copy
+  for (;;) {
+    double* V0 = ctx->V;
+    VK_TRY(launch_spmv(s, F.J, F.lpr_J, -1.0, x, 1.0, b, V0));
+    VK_TRY(launch_seg_dot(s, ns, seg, max_len, V0, V0, ctx->partial, ctx->n_partial, beta, true));
+    VK_TRY(launch_seg_init(s, ns, m, ctx->H, ctx->g, beta, tol, its, max_iter, active, jn));
+    VK_TRY(hipMemcpyAsync(hi.data(), active, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, s));
+    VK_TRY(hipStreamSynchronize(s));
+    int n_active = 0;
+    for (int i = 0; i < ns; ++i) n_active += hi[i];
+    if (n_active == 0) break;
+    VK_TRY(launch_seg_scale(s, ns, seg, max_len, V0, beta, active, V0));
+    int32_t j_end = 0;
+    for (int32_t j = 0; j < m; ++j) {
+      double* Vj = ctx->V + (int64_t)j * ldv;
+      double* Vn = ctx->V + (int64_t)(j + 1) * ldv;
+      double* Zj = ctx->Z + (int64_t)j * ldv;
+      VK_CHECK(vcycle_level(ctx, L, Vj, Zj, nu_pre, nu_post));
+      VK_TRY(launch_spmv(s, F.J, F.lpr_J, 1.0, Zj, 0.0, nullptr, Vn));
+      // classical Gram-Schmidt twice, per segment; the first pass goes into column j of H
+      double* Hc = ctx->H + (int64_t)j * (m + 1);
+      VK_TRY(launch_seg_mdot(s, ns, seg, max_len, ctx->V, ldv, j + 1, Vn, ctx->partial, ctx->n_partial, Hc,
+                             (int32_t)hs));
+      VK_TRY(launch_seg_maxpy(s, ns, seg, max_len, ctx->V, ldv, j + 1, Hc, (int32_t)hs, nullptr, -1.0, Vn));
+      VK_TRY(launch_seg_mdot(s, ns, seg, max_len, ctx->V, ldv, j + 1, Vn, ctx->partial, ctx->n_partial, ctx->h2,
+                             m + 1));
+      VK_TRY(launch_seg_maxpy(s, ns, seg, max_len, ctx->V, ldv, j + 1, ctx->h2, m + 1, nullptr, -1.0, Vn));
+      VK_TRY(launch_seg_dot(s, ns, seg, max_len, Vn, Vn, ctx->partial, ctx->n_partial, resid + ns, true));
+      VK_TRY(launch_seg_givens(s, ns, j, m, ctx->H, ctx->h2, ctx->cs, ctx->sn, ctx->g, tol, its, max_iter, active,
+                               jn, resid));
+      VK_TRY(launch_seg_scale(s, ns, seg, max_len, Vn, resid + ns, active, Vn));
+      j_end = j + 1;
+      VK_TRY(hipMemcpyAsync(hi.data(), active, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, s));
+      VK_TRY(hipStreamSynchronize(s));
+      n_active = 0;
+      for (int i = 0; i < ns; ++i) n_active += hi[i];
+      if (n_active == 0) break;
+    }
+    VK_TRY(launch_seg_trisolve(s, ns, m, ctx->H, ctx->g, jn, ctx->y));
+    VK_TRY(launch_seg_maxpy(s, ns, seg, max_len, ctx->Z, ldv, j_end, ctx->y, m, nullptr, 1.0, x));
+  }
+  // final true residuals
+  VK_TRY(launch_spmv(s, F.J, F.lpr_J, -1.0, x, 1.0, b, ctx->V));
+  VK_TRY(launch_seg_dot(s, ns, seg, max_len, ctx->V, ctx->V, ctx->partial, ctx->n_partial, beta, true));
+  VK_TRY(hipMemcpyAsync(hb.data(), beta, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+  VK_TRY(hipMemcpyAsync(iters, its, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, s));
+  VK_TRY(hipStreamSynchronize(s));
+  int conv = 1;
+  for (int i = 0; i < ns; ++i) {
+    true_rel_res[i] = bn[i] > 0.0 ? hb[i] / bn[i] : 0.0;
+    if (!(bn[i] == 0.0 || hb[i] <= tl[i])) conv = 0;
+  }
+  if (all_converged) *all_converged = conv;
+  if (!conv) return fail(ctx, VK_ERR_NOCONV, "at least one system did not reach the tolerance");
+  return VK_OK;
+}
+
 vk_status vk_spmv(vk_ctx* ctx, int32_t l, double alpha, const double* x, double beta, const double* z, double* y) {
   if (!ctx) return VK_ERR_ARG;
   if (l < 0 || l >= ctx->n_levels || !ctx->lv[l].set) return fail(ctx, VK_ERR_ARG, "level not set");
@@ -577,18 +787,18 @@ vk_status vk_spmv(vk_ctx* ctx, int32_t l, double alpha, const double* x, double 
 
 vk_status vk_get_patch_inverses(vk_ctx* ctx, int32_t l, int32_t cell0, int32_t n, double* out) {
   VK_CHECK(ready(ctx));
-  if (l < 1 || l >= ctx->n_levels) return fail(ctx, VK_ERR_ARG, "patch inverses exist on levels >= 1");
-  const vk_level& L = ctx->lv[l];
-  if (cell0 < 0 || n < 0 || (int64_t)cell0 + n > L.n_cells || !out) return fail(ctx, VK_ERR_ARG, "cell range");
-  VK_TRY(launch_patch_export(ctx->stream, L, ctx->prec, cell0, n, out));
+  if (l < 1 || l >= ctx->n_levels || ctx->lv[l].groups.empty())
+    return fail(ctx, VK_ERR_ARG, "patch inverses exist on levels >= 1");
+  const vk_group& G = ctx->lv[l].groups[0];
+  if (cell0 < 0 || n < 0 || (int64_t)cell0 + n > G.n_cells || !out) return fail(ctx, VK_ERR_ARG, "cell range");
+  VK_TRY(launch_patch_export(ctx->stream, G, ctx->prec, cell0, n, out));
   return VK_OK;
 }
 
 vk_status vk_get_coarse_inverse(vk_ctx* ctx, double* out) {
   VK_CHECK(ready(ctx));
   if (!out) return fail(ctx, VK_ERR_ARG, "null output");
-  const int64_t n0 = ctx->lv[0].J.n_rows;
-  VK_TRY(launch_coarse_export(ctx->stream, n0, ctx->c_W, ctx->c_perm, out));
+  VK_TRY(launch_block_export(ctx->stream, ctx->lv[0], 0, out));
   return VK_OK;
 }
 
@@ -599,17 +809,18 @@ vk_status vk_set_patch_tile(vk_ctx* ctx, int32_t l, int32_t cells_per_block) {
         cells_per_block == 8))
     return fail(ctx, VK_ERR_ARG, "cells_per_block must be 0, 1, 2, 4 or 8");
   vk_level& L = ctx->lv[l];
-  if (ctx->ws_ready && cells_per_block > 0 && VK_NT / cells_per_block < L.ld / vk_prec_vw(ctx->prec))
-    return fail(ctx, VK_ERR_ARG, "tile leaves fewer threads per cell than 16-byte vectors per column");
-  L.cpb_override = cells_per_block;
+  for (const vk_group& G : L.groups)
+    if (ctx->ws_ready && cells_per_block > 0 && VK_NT / cells_per_block < G.ld / vk_prec_vw(ctx->prec))
+      return fail(ctx, VK_ERR_ARG, "tile leaves fewer threads per cell than 16-byte vectors per column");
+  for (vk_group& G : L.groups) G.cpb_override = cells_per_block;
   return VK_OK;
 }
 
 vk_status vk_patch_layout(const vk_ctx* ctx, int32_t l, int64_t* bytes_per_cell, int32_t* ld) {
-  if (!ctx || l < 1 || l >= ctx->n_levels || !ctx->ws_ready) return VK_ERR_ARG;
-  const vk_level& L = ctx->lv[l];
-  if (bytes_per_cell) *bytes_per_cell = L.cell_stride * vk_prec_bytes(ctx->prec);
-  if (ld) *ld = L.ld;
+  if (!ctx || l < 1 || l >= ctx->n_levels || !ctx->ws_ready || ctx->lv[l].groups.empty()) return VK_ERR_ARG;
+  const vk_group& G = ctx->lv[l].groups[0];
+  if (bytes_per_cell) *bytes_per_cell = G.cell_stride * vk_prec_bytes(ctx->prec);
+  if (ld) *ld = G.ld;
   return VK_OK;
 }
 
@@ -650,14 +861,16 @@ vk_status vk_autotune(vk_ctx* ctx, int32_t reps) {
     VK_TRY(launch_fill(s, C.J.n_rows, 1.0, C.b));
     L.lpr_P = tune_csr(L.P, C.b, L.r);
     L.lpr_R = tune_csr(L.R, L.b, C.r);
-    int best = 0;
-    float tb = 1e30f;
-    for (int cpb : {1, 2, 4, 8}) {
-      if (VK_NT / cpb < L.ld / vk_prec_vw(ctx->prec)) continue;
-      const float t = time_ms([&] { return launch_patch_gemv(s, L, ctx->prec, L.b, ctx->Y, cpb); });
-      if (t < tb) { tb = t; best = cpb; }
+    for (vk_group& G : L.groups) {
+      int best = 0;
+      float tb = 1e30f;
+      for (int cpb : {1, 2, 4, 8}) {
+        if (VK_NT / cpb < G.ld / vk_prec_vw(ctx->prec)) continue;
+        const float t = time_ms([&] { return launch_patch_gemv(s, G, ctx->prec, L.b, ctx->Y, cpb); });
+        if (t < tb) { tb = t; best = cpb; }
+      }
+      G.cpb_tuned = best;
     }
-    L.cpb_tuned = best;
   }
   VK_TRY(hipEventDestroy(e0));
   VK_TRY(hipEventDestroy(e1));

@@ -1,4 +1,6 @@
-// Coarsest-level direct solve (Sec. 3: a direct solver for J_0 d_0 = b_0 on T_0).
+// Directly solved diagonal blocks: the coarsest level (Sec. 3: a direct solver
+// for J_0 d_0 = b_0 on T_0), and in a batch of independent systems every
+// system's coarsest level.  All blocks of a level are processed together.
 //
 // Setup inverts the dense FP64 J_0 by blocked Gauss-Jordan elimination with
 // implicit partial pivoting: the pivot of column k is the not-yet-used row
@@ -20,26 +22,60 @@
 
 namespace {
 
-// one wavefront per row
-__global__ void csr_to_dense_kernel(int64_t n, const int64_t* __restrict__ row_ptr,
-                                    const int32_t* __restrict__ col, const double* __restrict__ val, double* M) {
-  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int lane = threadIdx.x & 63;
-  if (i >= n) return;
-  for (int64_t e = row_ptr[i] + lane; e < row_ptr[i + 1]; e += 64) M[i * n + col[e]] = val[e];
-}
-
 constexpr int CT = 256;  // panel kernel threads
 
+__device__ inline int block_of(const int64_t* __restrict__ rows, int nb, int64_t r) {
+  int lo = 0, hi = nb;  // last block with rows[b] <= r
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (rows[mid] <= r) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// dense block b from the CSR rows of its rows; a coupling outside the block
+// flags status[1] (the blocks must be diagonal blocks of J)
+__global__ void block_to_dense_kernel(int n_blocks, const int64_t* __restrict__ rows,
+                                      const int64_t* __restrict__ woff, const int64_t* __restrict__ row_ptr,
+                                      const int32_t* __restrict__ col, const double* __restrict__ val, double* M,
+                                      int32_t* status) {
+  const int64_t total = rows[n_blocks];
+  const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (t >= total - rows[0]) return;
+  const int64_t r = rows[0] + t;
+  const int b = block_of(rows, n_blocks, r);
+  const int64_t r0 = rows[b], nbk = rows[b + 1] - r0;
+  double* W = M + woff[b];
+  for (int64_t e = row_ptr[r] + lane; e < row_ptr[r + 1]; e += 64) {
+    const int64_t c = col[e];
+    if (c < r0 || c >= r0 + nbk) {
+      atomicOr(&status[1], 1);
+      continue;
+    }
+    W[(r - r0) * nbk + (c - r0)] = val[e];
+  }
+}
+
 template <int R, int NB>
-__global__ __launch_bounds__(CT) void coarse_panel_kernel(int64_t n, int64_t k0, int nb,
-                                                          const double* __restrict__ Min, double* __restrict__ Mout,
-                                                          int32_t* __restrict__ q_g, int32_t* __restrict__ used_g,
-                                                          int32_t* status) {
+__global__ __launch_bounds__(CT) void block_panel_kernel(const int64_t* __restrict__ rows,
+                                                         const int64_t* __restrict__ woff, int64_t k0,
+                                                         const double* __restrict__ Min_, double* __restrict__ Mout_,
+                                                         int32_t* __restrict__ q_all, int32_t* __restrict__ used_all,
+                                                         int32_t* status) {
   __shared__ double w_abs[CT / 64];
   __shared__ int w_idx[CT / 64];
   __shared__ double prow[NB];
   __shared__ int s_q[NB];
+  const int bk = blockIdx.x;
+  const int64_t r0 = rows[bk], n = rows[bk + 1] - r0;
+  const int64_t left = n - k0;
+  const int nb = left <= 0 ? 0 : (left < NB ? (int)left : NB);
+  if (nb == 0) return;  // uniform for the workgroup
+  const double* Min = Min_ + woff[bk];
+  double* Mout = Mout_ + woff[bk];
+  int32_t* q_g = q_all + r0;
+  int32_t* used_g = used_all + r0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // P[r][.]: panel row tid + r * CT; the column loop is unrolled completely
   double P[R][NB];
@@ -124,15 +160,26 @@ __global__ __launch_bounds__(CT) void coarse_panel_kernel(int64_t n, int64_t k0,
   if (tid < nb) q_g[k0 + tid] = s_q[tid];
 }
 
-// Rank-NB update of the columns outside the panel; tiles of 32 rows x 64 columns.
+// Rank-NB update of the columns outside the panel of every block (blockIdx.z);
+// tiles of 32 rows x 64 columns.  A block whose elimination is complete is
+// copied unchanged, so all blocks end in the same buffer.
 template <int NB>
-__global__ __launch_bounds__(256) void coarse_update_kernel(int64_t n, int64_t k0, int nb,
-                                                            const double* __restrict__ Min, double* Mout,
-                                                            const int32_t* __restrict__ q_g) {
+__global__ __launch_bounds__(256) void block_update_kernel(const int64_t* __restrict__ rows,
+                                                           const int64_t* __restrict__ woff, int64_t k0,
+                                                           const double* __restrict__ Min_, double* Mout_,
+                                                           const int32_t* __restrict__ q_all) {
   __shared__ double Rt[NB][64];
   __shared__ double Xt[32][NB + 1];
   __shared__ int qs[NB];
+  const int bk = blockIdx.z;
+  const int64_t rb0 = rows[bk], n = rows[bk + 1] - rb0;
   const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 64;
+  if (r0 >= n || c0 >= n) return;  // uniform for the workgroup
+  const int64_t left = n - k0;
+  const int nb = left <= 0 ? 0 : (left < NB ? (int)left : NB);
+  const double* Min = Min_ + woff[bk];
+  double* Mout = Mout_ + woff[bk];
+  const int32_t* q_g = q_all + rb0;
   const int tid = threadIdx.x;
   if (tid < NB) qs[tid] = tid < nb ? q_g[k0 + tid] : -1;
   __syncthreads();
@@ -173,23 +220,30 @@ __global__ __launch_bounds__(256) void coarse_update_kernel(int64_t n, int64_t k
   }
 }
 
-// y[k] = sum_j W[q_k][j] x[q_j], one wavefront per output entry.
-__global__ __launch_bounds__(256) void coarse_apply_kernel(int64_t n, const double* __restrict__ W,
-                                                           const int32_t* __restrict__ q,
-                                                           const double* __restrict__ x, double* __restrict__ y) {
-  const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+// y[r0 + k] = sum_j W_b[q_k][j] x[r0 + q_j] for every row of every block,
+// one wavefront per row
+__global__ __launch_bounds__(256) void block_apply_kernel(int n_blocks, const int64_t* __restrict__ rows,
+                                                          const int64_t* __restrict__ woff,
+                                                          const double* __restrict__ W_,
+                                                          const int32_t* __restrict__ q_all,
+                                                          const double* __restrict__ x, double* __restrict__ y) {
+  const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
-  if (k >= n) return;
-  const double* w = W + (int64_t)q[k] * n;
+  if (t >= rows[n_blocks] - rows[0]) return;
+  const int64_t r = rows[0] + t;
+  const int b = block_of(rows, n_blocks, r);
+  const int64_t r0 = rows[b], n = rows[b + 1] - r0, k = r - r0;
+  const int32_t* q = q_all + r0;
+  const double* w = W_ + woff[b] + (int64_t)q[k] * n;
   double s = 0.0;
-  for (int64_t j = lane; j < n; j += 64) s = fma(w[j], x[q[j]], s);
+  for (int64_t j = lane; j < n; j += 64) s = fma(w[j], x[r0 + q[j]], s);
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-  if (lane == 0) y[k] = s;
+  if (lane == 0) y[r] = s;
 }
 
-// out[k][q_j] = W[q_k][j]: the inverse in natural order
-__global__ void coarse_export_kernel(int64_t n, const double* __restrict__ W, const int32_t* __restrict__ q,
-                                     double* out) {
+// out[k][q_j] = W_b[q_k][j]: block b's inverse in natural order
+__global__ void block_export_kernel(int64_t n, const double* __restrict__ W, const int32_t* __restrict__ q,
+                                    double* out) {
   const int64_t total = n * n;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t k = e / n, j = e - k * n;
@@ -198,13 +252,13 @@ __global__ void coarse_export_kernel(int64_t n, const double* __restrict__ W, co
 }
 
 template <int R, int NB>
-hipError_t run_blocked(hipStream_t s, int64_t n, double** a, double** b, int32_t* q, int32_t* used,
-                       int32_t* status) {
-  const dim3 ugrid((unsigned)((n + 63) / 64), (unsigned)((n + 31) / 32));
+hipError_t run_blocked(hipStream_t s, const vk_level& L, double** a, double** b, int32_t* status) {
+  const int nbk = (int)L.cb_rows.size() - 1;
+  const int64_t n = L.cb_max;
+  const dim3 ugrid((unsigned)((n + 63) / 64), (unsigned)((n + 31) / 32), (unsigned)nbk);
   for (int64_t k0 = 0; k0 < n; k0 += NB) {
-    const int nb = (int)((n - k0) < NB ? (n - k0) : NB);
-    coarse_panel_kernel<R, NB><<<1, CT, 0, s>>>(n, k0, nb, *a, *b, q, used, status);
-    coarse_update_kernel<NB><<<ugrid, 256, 0, s>>>(n, k0, nb, *a, *b, q);
+    block_panel_kernel<R, NB><<<nbk, CT, 0, s>>>(L.d_cb_rows, L.d_cb_woff, k0, *a, *b, L.cb_q, L.cb_used, status);
+    block_update_kernel<NB><<<ugrid, 256, 0, s>>>(L.d_cb_rows, L.d_cb_woff, k0, *a, *b, L.cb_q);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     double* t = *a;
@@ -218,36 +272,47 @@ hipError_t run_blocked(hipStream_t s, int64_t n, double** a, double** b, int32_t
 
 int64_t vk_coarse_max_n() { return 4096; }
 
-hipError_t launch_coarse_invert(hipStream_t s, const vk_csr& J0, double* buf0, double* buf1, int32_t* perm,
-                                int32_t* status, double** result) {
-  const int64_t n = J0.n_rows;
-  hipError_t e = launch_fill(s, n * n, 0.0, buf0);
+hipError_t launch_block_invert(hipStream_t s, const vk_level& L, int32_t* status, double** result) {
+  const int nbk = (int)L.cb_rows.size() - 1;
+  *result = L.cb_a;
+  if (nbk <= 0) return hipSuccess;
+  const int64_t rows_total = L.cb_rows[nbk] - L.cb_rows[0];
+  hipError_t e = launch_fill(s, L.cb_sq, 0.0, L.cb_a);
   if (e != hipSuccess) return e;
-  csr_to_dense_kernel<<<(unsigned)((n * 64 + 255) / 256), 256, 0, s>>>(n, J0.row_ptr, J0.col, J0.val, buf0);
+  block_to_dense_kernel<<<(unsigned)((rows_total * 64 + 255) / 256), 256, 0, s>>>(
+      nbk, L.d_cb_rows, L.d_cb_woff, L.J.row_ptr, L.J.col, L.J.val, L.cb_a, status);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  int32_t* q = perm;
-  int32_t* used = perm + n;
-  if ((e = launch_fill_i32(s, n, 0, used)) != hipSuccess) return e;
-  double* a = buf0;
-  double* b = buf1;
+  if ((e = launch_fill_i32(s, L.J.n_rows, 0, L.cb_used)) != hipSuccess) return e;
+  double* a = L.cb_a;
+  double* b = L.cb_b;
   // R rows x NB panel columns per thread: R * NB <= 64 doubles
-  const int64_t R = (n + CT - 1) / CT;
-  if (R <= 4) e = run_blocked<4, 16>(s, n, &a, &b, q, used, status);
-  else if (R <= 8) e = run_blocked<8, 8>(s, n, &a, &b, q, used, status);
-  else e = run_blocked<16, 4>(s, n, &a, &b, q, used, status);
+  const int64_t R = (L.cb_max + CT - 1) / CT;
+  if (R <= 4) e = run_blocked<4, 16>(s, L, &a, &b, status);
+  else if (R <= 8) e = run_blocked<8, 8>(s, L, &a, &b, status);
+  else e = run_blocked<16, 4>(s, L, &a, &b, status);
   *result = a;
   return e;
 }
 
-hipError_t launch_coarse_apply(hipStream_t s, int64_t n, const double* W, const int32_t* q, const double* x,
-                               double* y) {
-  coarse_apply_kernel<<<(unsigned)((n * 64 + 255) / 256), 256, 0, s>>>(n, W, q, x, y);
+hipError_t launch_block_apply(hipStream_t s, const vk_level& L, const double* x, double* y) {
+  const int nbk = (int)L.cb_rows.size() - 1;
+  if (nbk <= 0) return hipSuccess;
+  const int64_t rows_total = L.cb_rows[nbk] - L.cb_rows[0];
+  block_apply_kernel<<<(unsigned)((rows_total * 64 + 255) / 256), 256, 0, s>>>(nbk, L.d_cb_rows, L.d_cb_woff,
+                                                                              L.cb_W, L.cb_q, x, y);
   return hipGetLastError();
 }
 
-hipError_t launch_coarse_export(hipStream_t s, int64_t n, const double* W, const int32_t* q, double* out) {
+hipError_t launch_block_export(hipStream_t s, const vk_level& L, int32_t block, double* out) {
+  const int64_t n = L.cb_rows[block + 1] - L.cb_rows[block];
+  int64_t woff = 0;
+  for (int b = 0; b < block; ++b) {
+    const int64_t nb = L.cb_rows[b + 1] - L.cb_rows[b];
+    woff += nb * nb;
+  }
   int64_t g = (n * n + 255) / 256;
   if (g > 8192) g = 8192;
-  coarse_export_kernel<<<(unsigned)g, 256, 0, s>>>(n, W, q, out);
+  if (g < 1) g = 1;
+  block_export_kernel<<<(unsigned)g, 256, 0, s>>>(n, L.cb_W + woff, L.cb_q + L.cb_rows[block], out);
   return hipGetLastError();
 }

@@ -340,18 +340,18 @@ inline unsigned capped_grid(int64_t work, int per_block, unsigned cap) {
 }
 
 template <int P>
-hipError_t setup_prec(hipStream_t s, const vk_level& L, double* big, int32_t chunk, int32_t* status) {
+hipError_t setup_prec(hipStream_t s, const vk_csr& J, const vk_group& L, double* big, int32_t chunk, int32_t* status) {
   const int n = L.n_K;
   if (n <= VK_LDS_SETUP_MAX_NK) {
     const size_t lds = (size_t)n * n * 8 + setup_small_bytes(n);
-    patch_setup_kernel<P, false><<<L.n_cells, VK_NT, lds, s>>>(L.J.row_ptr, L.J.col, L.J.val, L.cell_dofs, 0, n,
+    patch_setup_kernel<P, false><<<L.n_cells, VK_NT, lds, s>>>(J.row_ptr, J.col, J.val, L.cell_dofs, 0, n,
                                                                L.inv, L.ld, L.cell_stride, nullptr, status);
     return hipGetLastError();
   }
   const size_t lds = setup_small_bytes(n);
   for (int32_t c0 = 0; c0 < L.n_cells; c0 += chunk) {
     const int32_t cnt = (L.n_cells - c0) < chunk ? (L.n_cells - c0) : chunk;
-    patch_setup_kernel<P, true><<<cnt, VK_NT, lds, s>>>(L.J.row_ptr, L.J.col, L.J.val, L.cell_dofs, c0, n, L.inv,
+    patch_setup_kernel<P, true><<<cnt, VK_NT, lds, s>>>(J.row_ptr, J.col, J.val, L.cell_dofs, c0, n, L.inv,
                                                         L.ld, L.cell_stride, big, status);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -360,8 +360,8 @@ hipError_t setup_prec(hipStream_t s, const vk_level& L, double* big, int32_t chu
 }
 
 template <int P>
-hipError_t apply_prec(hipStream_t s, const vk_level& L, int cpb, int32_t colour, const double* r,
-                      const double* rK, double* d, double omega, bool average) {
+hipError_t apply_prec(hipStream_t s, const vk_group& L, int cpb, int32_t colour, const double* r,
+                      const double* rK, double* d, const double* ip, double omega) {
   const int32_t c0 = L.colour_ptr[colour], c1 = L.colour_ptr[colour + 1];
   const int32_t n_launch = c1 - c0;
   if (n_launch <= 0) return hipSuccess;
@@ -370,7 +370,6 @@ hipError_t apply_prec(hipStream_t s, const vk_level& L, int cpb, int32_t colour,
   using A = typename PT<P>::A;
   const size_t lds = (((size_t)cpb * L.n_K * 4 + 15) & ~(size_t)15) + (size_t)cpb * L.n_K * sizeof(A) +
                      (size_t)VK_NT * VW * sizeof(A);
-  const double* ip = average ? L.inv_p : nullptr;
   if (rK)
     patch_apply_kernel<P, true><<<grid, VK_NT, lds, s>>>(L.inv, L.ld, L.cell_stride, L.n_K, L.colour_cells + c0,
                                                          n_launch, L.cell_dofs, r, rK, d, ip, omega, cpb);
@@ -404,57 +403,56 @@ int vk_default_cpb(int32_t n_K, int32_t ld, vk_prec prec) {
   return best;
 }
 
-hipError_t launch_multiplicity(hipStream_t s, int32_t n_cells, int32_t n_K, const int32_t* cell_dofs, int64_t n,
-                               int32_t* count, double* inv_p) {
-  hipError_t e = launch_fill_i32(s, n, 0, count);
-  if (e != hipSuccess) return e;
+hipError_t launch_count_add(hipStream_t s, int32_t n_cells, int32_t n_K, const int32_t* cell_dofs, int32_t* count) {
   const int64_t total = (int64_t)n_cells * n_K;
+  if (total == 0) return hipSuccess;
   count_kernel<<<capped_grid(total, 256, 4096), 256, 0, s>>>(total, cell_dofs, count);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_inv_count(hipStream_t s, int64_t n, const int32_t* count, double* inv_p) {
   inv_count_kernel<<<capped_grid(n, 256, 4096), 256, 0, s>>>(n, count, inv_p);
   return hipGetLastError();
 }
 
-hipError_t launch_patch_setup(hipStream_t s, const vk_level& L, vk_prec prec, double* big, int32_t chunk,
-                              int32_t* status) {
-  if (L.n_cells == 0) return hipSuccess;
+hipError_t launch_patch_setup(hipStream_t s, const vk_csr& J, const vk_group& G, vk_prec prec, double* big,
+                              int32_t chunk, int32_t* status) {
+  if (G.n_cells == 0) return hipSuccess;
   switch (prec) {
-    case VK_F64: return setup_prec<VK_F64>(s, L, big, chunk, status);
-    case VK_F32: return setup_prec<VK_F32>(s, L, big, chunk, status);
-    default: return setup_prec<VK_BF16>(s, L, big, chunk, status);
+    case VK_F64: return setup_prec<VK_F64>(s, J, G, big, chunk, status);
+    case VK_F32: return setup_prec<VK_F32>(s, J, G, big, chunk, status);
+    default: return setup_prec<VK_BF16>(s, J, G, big, chunk, status);
   }
 }
 
-hipError_t launch_patch_apply(hipStream_t s, const vk_level& L, vk_prec prec, int32_t colour, const double* r,
-                              const double* rK, double* d, double omega, bool average) {
-  const int cpb = L.cpb_override > 0 ? L.cpb_override : vk_default_cpb(L.n_K, L.ld, prec);
+hipError_t launch_patch_apply(hipStream_t s, const vk_group& G, vk_prec prec, int32_t colour, const double* r,
+                              const double* rK, double* d, const double* inv_p, double omega) {
+  const int cpb = G.cpb_override > 0 ? G.cpb_override : vk_default_cpb(G.n_K, G.ld, prec);
   switch (prec) {
-    case VK_F64: return apply_prec<VK_F64>(s, L, cpb, colour, r, rK, d, omega, average);
-    case VK_F32: return apply_prec<VK_F32>(s, L, cpb, colour, r, rK, d, omega, average);
-    default: return apply_prec<VK_BF16>(s, L, cpb, colour, r, rK, d, omega, average);
+    case VK_F64: return apply_prec<VK_F64>(s, G, cpb, colour, r, rK, d, inv_p, omega);
+    case VK_F32: return apply_prec<VK_F32>(s, G, cpb, colour, r, rK, d, inv_p, omega);
+    default: return apply_prec<VK_BF16>(s, G, cpb, colour, r, rK, d, inv_p, omega);
   }
 }
 
-hipError_t launch_patch_residual(hipStream_t s, const vk_level& L, int32_t colour, const double* b,
-                                 const double* d, double* rK) {
+hipError_t launch_patch_residual(hipStream_t s, const vk_csr& J, int lpr, const vk_group& L, int32_t colour,
+                                 const double* b, const double* d, double* rK) {
   const int32_t c0 = L.colour_ptr[colour], c1 = L.colour_ptr[colour + 1];
   const int32_t n_launch = c1 - c0;
   if (n_launch <= 0) return hipSuccess;
   const int64_t items = (int64_t)n_launch * L.n_K;
-  const int lpr = L.lpr_J;
   const unsigned grid = capped_grid(items * lpr, 256, 0x7fffffff);
   switch (lpr) {
-    case 4: patch_residual_kernel<4><<<grid, 256, 0, s>>>(L.J.row_ptr, L.J.col, L.J.val, L.colour_cells + c0, n_launch, L.cell_dofs, L.n_K, b, d, rK); break;
-    case 8: patch_residual_kernel<8><<<grid, 256, 0, s>>>(L.J.row_ptr, L.J.col, L.J.val, L.colour_cells + c0, n_launch, L.cell_dofs, L.n_K, b, d, rK); break;
-    case 16: patch_residual_kernel<16><<<grid, 256, 0, s>>>(L.J.row_ptr, L.J.col, L.J.val, L.colour_cells + c0, n_launch, L.cell_dofs, L.n_K, b, d, rK); break;
-    case 32: patch_residual_kernel<32><<<grid, 256, 0, s>>>(L.J.row_ptr, L.J.col, L.J.val, L.colour_cells + c0, n_launch, L.cell_dofs, L.n_K, b, d, rK); break;
-    default: patch_residual_kernel<64><<<grid, 256, 0, s>>>(L.J.row_ptr, L.J.col, L.J.val, L.colour_cells + c0, n_launch, L.cell_dofs, L.n_K, b, d, rK); break;
+    case 4: patch_residual_kernel<4><<<grid, 256, 0, s>>>(J.row_ptr, J.col, J.val, L.colour_cells + c0, n_launch, L.cell_dofs, L.n_K, b, d, rK); break;
+    case 8: patch_residual_kernel<8><<<grid, 256, 0, s>>>(J.row_ptr, J.col, J.val, L.colour_cells + c0, n_launch, L.cell_dofs, L.n_K, b, d, rK); break;
+    case 16: patch_residual_kernel<16><<<grid, 256, 0, s>>>(J.row_ptr, J.col, J.val, L.colour_cells + c0, n_launch, L.cell_dofs, L.n_K, b, d, rK); break;
+    case 32: patch_residual_kernel<32><<<grid, 256, 0, s>>>(J.row_ptr, J.col, J.val, L.colour_cells + c0, n_launch, L.cell_dofs, L.n_K, b, d, rK); break;
+    default: patch_residual_kernel<64><<<grid, 256, 0, s>>>(J.row_ptr, J.col, J.val, L.colour_cells + c0, n_launch, L.cell_dofs, L.n_K, b, d, rK); break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_patch_export(hipStream_t s, const vk_level& L, vk_prec prec, int32_t cell0, int32_t n,
+hipError_t launch_patch_export(hipStream_t s, const vk_group& L, vk_prec prec, int32_t cell0, int32_t n,
                                double* out) {
   const int64_t total = (int64_t)n * L.n_K * L.n_K;
   if (total == 0) return hipSuccess;
@@ -625,13 +623,13 @@ __global__ __launch_bounds__(64 * RowCfg<N>::W) void patch_setup_rows_kernel(
 }
 
 template <int P>
-hipError_t setup_rows(hipStream_t s, const vk_level& L, int32_t* status, bool* handled) {
+hipError_t setup_rows(hipStream_t s, const vk_csr& J, const vk_group& L, int32_t* status, bool* handled) {
   *handled = true;
   switch (L.n_K) {
 #define VK_ROWS_CASE(NN)                                                                                \
   case NN:                                                                                              \
     patch_setup_rows_kernel<P, NN><<<L.n_cells, 64 * RowCfg<NN>::W, 0, s>>>(                            \
-        L.J.row_ptr, L.J.col, L.J.val, L.cell_dofs, L.inv, L.ld, L.cell_stride, status);               \
+        J.row_ptr, J.col, J.val, L.cell_dofs, L.inv, L.ld, L.cell_stride, status);                     \
     return hipGetLastError();
     VK_ROWS_CASE(42)
     VK_ROWS_CASE(63)
@@ -742,12 +740,12 @@ __global__ __launch_bounds__(1024) void scan_kernel(int64_t n, const int32_t* __
   }
 }
 
-__global__ void dof_fill_kernel(int64_t total, const int32_t* __restrict__ cell_dofs,
+__global__ void dof_fill_kernel(int64_t total, const int32_t* __restrict__ cell_dofs, int64_t base,
                                 const int32_t* __restrict__ off, int32_t* cursor, int32_t* list) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int32_t mu = cell_dofs[e];
     const int32_t pos = off[mu] + atomicAdd(&cursor[mu], 1);
-    list[pos] = (int32_t)e;
+    list[pos] = (int32_t)(base + e);
   }
 }
 
@@ -768,47 +766,59 @@ __global__ void dof_sort_kernel(int64_t n, const int32_t* __restrict__ off, int3
 }
 
 template <int P>
-hipError_t gemv_prec(hipStream_t s, const vk_level& L, int cpb, const double* r, void* Y) {
+hipError_t gemv_prec(hipStream_t s, const vk_group& L, int cpb, const double* r, void* Y) {
   using A = typename PT<P>::A;
   constexpr int VW = PT<P>::VW;
   const unsigned grid = (unsigned)((L.n_cells + cpb - 1) / cpb);
   const size_t lds = (size_t)cpb * L.n_K * sizeof(A) + (size_t)VK_NT * VW * sizeof(A);
   patch_gemv_kernel<P><<<grid, VK_NT, lds, s>>>(L.inv, L.ld, L.cell_stride, L.n_K, L.n_cells, L.cell_dofs, r,
-                                                reinterpret_cast<A*>(Y), cpb);
+                                                reinterpret_cast<A*>(Y) + L.y_off, cpb);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_patch_setup_fast(hipStream_t s, const vk_level& L, vk_prec prec, int32_t* status, bool* handled) {
+hipError_t launch_patch_setup_fast(hipStream_t s, const vk_csr& J, const vk_group& G, vk_prec prec, int32_t* status,
+                                   bool* handled) {
+  if (G.n_cells == 0) {
+    *handled = true;
+    return hipSuccess;
+  }
   switch (prec) {
-    case VK_F64: return setup_rows<VK_F64>(s, L, status, handled);
-    case VK_F32: return setup_rows<VK_F32>(s, L, status, handled);
-    default: return setup_rows<VK_BF16>(s, L, status, handled);
+    case VK_F64: return setup_rows<VK_F64>(s, J, G, status, handled);
+    case VK_F32: return setup_rows<VK_F32>(s, J, G, status, handled);
+    default: return setup_rows<VK_BF16>(s, J, G, status, handled);
   }
 }
 
-hipError_t launch_dof_map(hipStream_t s, const vk_level& L, int32_t* count, int32_t* off, int32_t* list) {
+// DoF -> (cell, local) lists of a level over all its cell groups
+hipError_t launch_dof_map(hipStream_t s, const vk_level& L, int32_t* count) {
   const int64_t n = L.J.n_rows;
-  const int64_t total = (int64_t)L.n_cells * L.n_K;
   hipError_t e = launch_fill_i32(s, n, 0, count);
   if (e != hipSuccess) return e;
-  count_kernel<<<capped_grid(total, 256, 4096), 256, 0, s>>>(total, L.cell_dofs, count);
-  scan_kernel<<<1, 1024, 0, s>>>(n, count, off);
+  for (const vk_group& G : L.groups)
+    if ((e = launch_count_add(s, G.n_cells, G.n_K, G.cell_dofs, count)) != hipSuccess) return e;
+  scan_kernel<<<1, 1024, 0, s>>>(n, count, L.dof_off);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = launch_fill_i32(s, n, 0, count)) != hipSuccess) return e;
-  dof_fill_kernel<<<capped_grid(total, 256, 4096), 256, 0, s>>>(total, L.cell_dofs, off, count, list);
-  dof_sort_kernel<<<capped_grid(n, 256, 4096), 256, 0, s>>>(n, off, list);
+  for (const vk_group& G : L.groups) {
+    const int64_t total = (int64_t)G.n_cells * G.n_K;
+    if (total == 0) continue;
+    dof_fill_kernel<<<capped_grid(total, 256, 4096), 256, 0, s>>>(total, G.cell_dofs, G.y_off, L.dof_off, count,
+                                                                  L.dof_list);
+  }
+  dof_sort_kernel<<<capped_grid(n, 256, 4096), 256, 0, s>>>(n, L.dof_off, L.dof_list);
   return hipGetLastError();
 }
 
-hipError_t launch_patch_gemv(hipStream_t s, const vk_level& L, vk_prec prec, const double* r, void* Y, int cpb) {
+hipError_t launch_patch_gemv(hipStream_t s, const vk_group& G, vk_prec prec, const double* r, void* Y, int cpb) {
+  if (G.n_cells == 0) return hipSuccess;
   if (cpb <= 0)
-    cpb = L.cpb_override > 0 ? L.cpb_override : (L.cpb_tuned > 0 ? L.cpb_tuned : vk_default_cpb(L.n_K, L.ld, prec));
+    cpb = G.cpb_override > 0 ? G.cpb_override : (G.cpb_tuned > 0 ? G.cpb_tuned : vk_default_cpb(G.n_K, G.ld, prec));
   switch (prec) {
-    case VK_F64: return gemv_prec<VK_F64>(s, L, cpb, r, Y);
-    case VK_F32: return gemv_prec<VK_F32>(s, L, cpb, r, Y);
-    default: return gemv_prec<VK_BF16>(s, L, cpb, r, Y);
+    case VK_F64: return gemv_prec<VK_F64>(s, G, cpb, r, Y);
+    case VK_F32: return gemv_prec<VK_F32>(s, G, cpb, r, Y);
+    default: return gemv_prec<VK_BF16>(s, G, cpb, r, Y);
   }
 }
 

@@ -58,10 +58,9 @@ __device__ inline int wave_min(int v) {
 }
 
 
-struct vk_level {
-  bool set = false;
-  vk_csr J{}, P{}, R{};
-  bool has_transfer = false;
+// A set of cells of one patch width on one level (one system, or all systems
+// of a batch with the same k).
+struct vk_group {
   int32_t n_cells = 0, n_K = 0;
   const int32_t* cell_dofs = nullptr;
   const int32_t* colour_cells = nullptr;
@@ -70,17 +69,37 @@ struct vk_level {
   int32_t max_colour_cells = 0;
   int32_t cpb_override = 0;
   int32_t cpb_tuned = 0;      // picked by vk_autotune for the patch GEMV
-  int lpr_J = 4, lpr_P = 4, lpr_R = 4;
   // carved from the workspace
   void* inv = nullptr;        // stored patch inverses
   int32_t ld = 0;             // leading dimension (rows, padded)
   int64_t cell_stride = 0;    // elements per cell
-  double* inv_p = nullptr;    // 1 / multiplicity
+  int64_t y_off = 0;          // first flat (cell, local) index of the group on its level
+};
+
+struct vk_level {
+  bool set = false;
+  vk_csr J{}, P{}, R{};
+  bool has_transfer = false;
+  std::vector<vk_group> groups;
+  int64_t n_items = 0;              // sum over groups of n_cells * n_K
+  std::vector<int64_t> cb_rows;     // directly solved diagonal blocks: row offsets (n_blocks + 1)
+  int64_t cb_max = 0;               // largest block
+  int64_t cb_sq = 0;                // sum of squared block sizes
+  int lpr_J = 4, lpr_P = 4, lpr_R = 4;
+  // carved from the workspace
+  double* inv_p = nullptr;      // 1 / multiplicity
   int32_t* dof_off = nullptr;   // DoF -> (cell, local) lists: offsets (n + 1)
-  int32_t* dof_list = nullptr;  // flat indices K * n_K + i, ascending per DoF
-  double* b = nullptr;        // V-cycle right-hand side (levels < L)
-  double* d = nullptr;        // V-cycle iterate (levels < L)
-  double* r = nullptr;        // defect scratch
+  int32_t* dof_list = nullptr;  // flat indices, ascending per DoF
+  double* b = nullptr;          // V-cycle right-hand side
+  double* d = nullptr;          // V-cycle iterate
+  double* r = nullptr;          // defect scratch
+  double* cb_a = nullptr;       // block Gauss-Jordan buffers (two, alternating)
+  double* cb_b = nullptr;
+  double* cb_W = nullptr;       // the one holding the eliminated blocks
+  int64_t* d_cb_rows = nullptr; // device copies of the block offsets
+  int64_t* d_cb_woff = nullptr; // offset of each block's dense matrix
+  int32_t* cb_q = nullptr;      // pivot rows (block-local), per block
+  int32_t* cb_used = nullptr;   // rows already used as pivots
 };
 
 struct vk_timing_rec {
@@ -113,11 +132,12 @@ struct vk_ctx {
   bool fast_setup = true;     // register-resident patch inversion where compiled
   bool maps_ready = false;    // multiplicities and DoF lists (depend on the mesh only)
   void* Y = nullptr;          // per-cell products y_K of the additive sweep
-  // coarse direct solve
-  double* c_inv = nullptr;   // Gauss-Jordan buffers (two, alternating)
-  double* c_tmp = nullptr;
-  double* c_W = nullptr;     // the one holding the eliminated matrix
-  int32_t* c_perm = nullptr; // rowmap (n_0) + panel interchanges (n_0)
+  // batched GMRES: segments of the finest level solved as independent systems
+  std::vector<int64_t> seg_rows;  // host, n_seg + 1
+  int32_t n_seg = 1;
+  int64_t* d_seg = nullptr;       // device copy
+  double* seg_scal = nullptr;     // per-segment scalars (see api.hip)
+  int32_t* seg_flags = nullptr;   // per-segment active flags and counters
   // setup scratch for patches too wide for LDS
   double* big_scratch = nullptr;
   int32_t big_chunk = 0;
@@ -149,32 +169,28 @@ hipError_t launch_validate_cells(hipStream_t s, int32_t n_cells, int32_t n_K, co
 hipError_t launch_fill(hipStream_t s, int64_t n, double v, double* x);
 hipError_t launch_fill_i32(hipStream_t s, int64_t n, int32_t v, int32_t* x);
 // patches
-hipError_t launch_multiplicity(hipStream_t s, int32_t n_cells, int32_t n_K, const int32_t* cell_dofs,
-                               int64_t n, int32_t* count, double* inv_p);
-hipError_t launch_patch_setup(hipStream_t s, const vk_level& L, vk_prec prec, double* big_scratch,
+hipError_t launch_count_add(hipStream_t s, int32_t n_cells, int32_t n_K, const int32_t* cell_dofs, int32_t* count);
+hipError_t launch_inv_count(hipStream_t s, int64_t n, const int32_t* count, double* inv_p);
+hipError_t launch_dof_map(hipStream_t s, const vk_level& L, int32_t* count);
+hipError_t launch_patch_setup(hipStream_t s, const vk_csr& J, const vk_group& G, vk_prec prec, double* big_scratch,
                               int32_t big_chunk, int32_t* status);
-hipError_t launch_patch_apply(hipStream_t s, const vk_level& L, vk_prec prec, int32_t colour,
-                              const double* r, const double* rK, double* d, double omega, bool average);
-hipError_t launch_patch_residual(hipStream_t s, const vk_level& L, int32_t colour, const double* b,
-                                 const double* d, double* rK);
-hipError_t launch_patch_export(hipStream_t s, const vk_level& L, vk_prec prec, int32_t cell0, int32_t n,
-                               double* out);
+hipError_t launch_patch_setup_fast(hipStream_t s, const vk_csr& J, const vk_group& G, vk_prec prec, int32_t* status,
+                                   bool* handled);
+hipError_t launch_patch_apply(hipStream_t s, const vk_group& G, vk_prec prec, int32_t colour, const double* r,
+                              const double* rK, double* d, const double* inv_p, double omega);
+hipError_t launch_patch_residual(hipStream_t s, const vk_csr& J, int lpr, const vk_group& G, int32_t colour,
+                                 const double* b, const double* d, double* rK);
+hipError_t launch_patch_export(hipStream_t s, const vk_group& G, vk_prec prec, int32_t cell0, int32_t n, double* out);
+hipError_t launch_patch_gemv(hipStream_t s, const vk_group& G, vk_prec prec, const double* r, void* Y, int cpb = 0);
+hipError_t launch_dof_gather(hipStream_t s, const vk_level& L, vk_prec prec, const void* Y, double omega, double* d);
 int vk_default_cpb(int32_t n_K, int32_t ld, vk_prec prec);
 int vk_prec_vw(vk_prec prec);
 int vk_prec_bytes(vk_prec prec);
-// coarse
+// directly solved blocks (the coarsest level, and in batches every system's coarsest level)
 int64_t vk_coarse_max_n();
-hipError_t launch_coarse_invert(hipStream_t s, const vk_csr& J0, double* buf0, double* buf1, int32_t* perm,
-                                int32_t* status, double** result);
-hipError_t launch_coarse_apply(hipStream_t s, int64_t n, const double* W, const int32_t* rowmap, const double* x,
-                               double* y);
-hipError_t launch_coarse_export(hipStream_t s, int64_t n, const double* W, const int32_t* rowmap, double* out);
-hipError_t launch_patch_setup_fast(hipStream_t s, const vk_level& L, vk_prec prec, int32_t* status, bool* handled);
-hipError_t launch_dof_map(hipStream_t s, const vk_level& L, int32_t* count, int32_t* off, int32_t* list);
-hipError_t launch_patch_gemv(hipStream_t s, const vk_level& L, vk_prec prec, const double* r, void* Y,
-                             int cpb = 0);
-hipError_t launch_dof_gather(hipStream_t s, const vk_level& L, vk_prec prec, const void* Y, double omega,
-                             double* d);
+hipError_t launch_block_invert(hipStream_t s, const vk_level& L, int32_t* status, double** result);
+hipError_t launch_block_apply(hipStream_t s, const vk_level& L, const double* x, double* y);
+hipError_t launch_block_export(hipStream_t s, const vk_level& L, int32_t block, double* out);
 // Krylov
 hipError_t launch_dot(hipStream_t s, int64_t n, const double* x, const double* y, double* partial,
                       int32_t n_partial, double* out, bool sqrt_out);
@@ -187,3 +203,21 @@ hipError_t launch_givens(hipStream_t s, int32_t j, int32_t ldh, double* H, const
                          double* sn, double* g, double* out);
 hipError_t launch_gmres_init(hipStream_t s, int32_t m, double* H, double* g, const double* beta);
 hipError_t launch_trisolve(hipStream_t s, int32_t jn, int32_t ldh, const double* H, const double* g, double* y);
+// segmented Krylov kernels (one independent system per segment)
+hipError_t launch_seg_dot(hipStream_t s, int32_t n_seg, const int64_t* seg, int64_t max_len, const double* x,
+                          const double* y, double* partial, int32_t n_partial, double* out, bool sqrt_out);
+hipError_t launch_seg_mdot(hipStream_t s, int32_t n_seg, const int64_t* seg, int64_t max_len, const double* V,
+                           int64_t ldv, int32_t m, const double* w, double* partial, int32_t n_partial, double* out,
+                           int32_t ldo);
+hipError_t launch_seg_maxpy(hipStream_t s, int32_t n_seg, const int64_t* seg, int64_t max_len, const double* V,
+                            int64_t ldv, int32_t m, const double* h, int32_t ldh, const int32_t* mcount,
+                            double sign, double* w);
+hipError_t launch_seg_scale(hipStream_t s, int32_t n_seg, const int64_t* seg, int64_t max_len, const double* x,
+                            const double* den, const int32_t* active, double* y);
+hipError_t launch_seg_init(hipStream_t s, int32_t n_seg, int32_t m, double* H, double* g, const double* beta,
+                           const double* tol, const int32_t* its, int32_t max_iter, int32_t* active, int32_t* jn);
+hipError_t launch_seg_givens(hipStream_t s, int32_t n_seg, int32_t j, int32_t m, double* H, const double* h2,
+                             double* cs, double* sn, double* g, const double* tol, int32_t* its, int32_t max_iter,
+                             int32_t* active, int32_t* jn, double* resid);
+hipError_t launch_seg_trisolve(hipStream_t s, int32_t n_seg, int32_t m, const double* H, const double* g,
+                               const int32_t* jn, double* y);

@@ -82,8 +82,11 @@ def inflow_state(mesh, U, rng, noise=0.05):
     return V
 
 
-def build_hierarchy(d, shape, lengths, levels, k, nu, tau, U, seed=0, noise=0.05, state=None):
-    shapes = hierarchy_shapes(shape, levels)
+def build_hierarchy(d, shape, lengths, levels, k, nu, tau, U, seed=0, noise=0.05, state=None, shapes=None):
+    """Levels 0 (coarsest) .. levels-1 of one problem; `shapes` overrides the coarsening rule."""
+    if shapes is None:
+        shapes = hierarchy_shapes(shape, levels)
+    levels = len(shapes)
     meshes = [StructuredMesh(s, lengths, k) for s in shapes]
     fine = meshes[-1]
     if state is None:
