@@ -93,6 +93,15 @@ def sweep_rate(torch, S, P, b_np, sweeps=40):
     return P.finest.mesh.n_cells * sweeps / dt
 
 
+def timed_steps(torch, step, reps):
+    """Wall time (s) of `reps` calls of step() bracketed by synchronisations, and their results."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [step() for _ in range(reps)]
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, res
+
+
 def cpu_baseline(P, nu, restart, n_steps_total_cells):
     """The FP64 oracle on the host: one full step (setup + GMRES to 1e-8)."""
     import oracle
@@ -112,6 +121,131 @@ def cpu_baseline(P, nu, restart, n_steps_total_cells):
                       f"{dt:.1f} s"}, x, its
 
 
+def run_batch(args, torch, vk, dev):
+    """64 independent systems (meshes 32x8 .. 128x24, k in {1,2,3}, seeded viscosities) in one
+    context: one vanka_setup and one gmres_solve_batched per step.  value = useful cell-sweeps
+    per second, summed over systems (each system's own iterations times its V-cycle's sweeps);
+    the lockstep also sweeps systems that have already converged, counted separately."""
+    from synth.batch import build_batch
+    import oracle
+    restart, max_iter, nu = 30, 300, (2, 2)
+    t0 = time.perf_counter()
+    B = build_batch(64, seed=0)
+    fin = B.levels[-1]
+    log(f"[bench] built batch: {len(B.systems)} systems, n = {fin.n}, finest cells = {B.n_cells_finest}, "
+        f"{time.perf_counter() - t0:.1f} s")
+    S = vk.Solver([vk.upload_packed_level(L, dev) for L in B.levels])
+    S.vk_set_segments(B.seg_rows)
+    S.vk_set_workspace(args.prec, restart, device=dev)
+    S.vanka_setup(0.7, "additive")
+    S.vk_autotune(10)
+    b = torch.from_numpy(B.b).to(dev)
+    x = torch.zeros_like(b)
+    order = sorted(fin.rows.items(), key=lambda kv: kv[1][0])  # segment order
+    cs_sys = np.array([sum(L.mesh.n_cells for L in B.hierarchies[si][1:]) * sum(nu) for si, _ in order])
+
+    def step():
+        S.vanka_setup(0.7, "additive")
+        x.zero_()
+        its, rel, conv = S.gmres_solve_batched(b, x, restart=restart, max_iter=max_iter, rtol=1e-8,
+                                               nu_pre=nu[0], nu_post=nu[1])
+        if not conv:
+            raise RuntimeError("batched GMRES did not converge")
+        return its, rel
+
+    S.vk_set_graphs(not args.no_graphs)
+    for w in range(args.warmup):
+        its, rel = step()
+        log(f"[bench] warmup {w}: its {its.min()}..{its.max()}")
+    dt, res = timed_steps(torch, step, args.steps)
+    its = res[-1][0]
+    useful = sum(int((r[0] * cs_sys).sum()) for r in res)
+    performed = sum(int(r[0].max()) * int(cs_sys.sum()) for r in res)
+    value = useful / dt
+    ms_per_step = dt / args.steps * 1e3
+    log(f"[bench] batch timed {args.steps} steps in {dt:.3f} s")
+    graph_stats = S.vk_graph_stats()
+
+    # eager pass with event timing of the finest level: roofline of the patch GEMV (one launch
+    # per patch width) and phase times
+    S.vk_set_graphs(False)
+    l_fine = len(B.levels) - 1
+    S.vk_timing_enable(True, l_fine)
+    dt_e, res_e = timed_steps(torch, step, max(3, args.steps // 4))
+    n_apply, ms_apply = S.vk_timing_read("patch_gemv", l_fine)
+    S.vk_timing_enable(False)
+    bytes_sweep = sum(g["cell_dofs"].shape[0] * (g["n_K"] ** 2 * PREC_BYTES[args.prec]
+                                                 + g["n_K"] * (4 + 8 + (8 if args.prec == "f64" else 4)))
+                      for g in fin.groups)
+    n_sweeps = n_apply / max(len(fin.groups), 1)
+    achieved = bytes_sweep * n_sweeps / (ms_apply * 1e-3) / 1e9
+    setup_ms = []
+    gm_ms = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.vanka_setup(0.7, "additive")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x.zero_()
+        S.vk_set_graphs(not args.no_graphs)
+        S.gmres_solve_batched(b, x, restart=restart, max_iter=max_iter, rtol=1e-8, nu_pre=nu[0], nu_post=nu[1])
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        setup_ms.append((t1 - t0) * 1e3)
+        gm_ms.append((t2 - t1) * 1e3)
+    rel = res[-1][1]
+    out = {
+        "metric": "Vanka cells·sweeps/s + GMRES time to 1e-8 rel. residual, FP32-patch vs FP64",
+        "value": value, "unit": "cell-sweeps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f32": "f32+f64", "bf16": "bf16+f32+f64", "f64": "f64"}[args.prec],
+        "data": "synthetic (64 seeded Newton linearisations of channel flows; no dataset)",
+        "config": {"workload": "batch64_seed0", "systems": len(B.systems), "unknowns": int(fin.n),
+                   "finest_cells": int(B.n_cells_finest), "nnz_finest": int(fin.J.nnz),
+                   "patch_sizes": sorted({g["n_K"] for g in fin.groups}), "packed_levels": len(B.levels),
+                   "patch_precision": args.prec, "gmres_restart": restart, "nu_pre": nu[0], "nu_post": nu[1],
+                   "omega": 0.7, "graphs": not args.no_graphs, "parallelism": "single GPU"},
+        "performed_cell_sweeps_per_s": performed / dt,
+        "gmres_iterations_per_system": [int(v) for v in its],
+        "gmres_true_rel_residual_max": float(np.max(rel)),
+        "setup_ms": float(np.median(setup_ms)), "gmres_ms_to_1e-8": float(np.median(gm_ms)),
+        "eager_ms_per_step": dt_e / len(res_e) * 1e3, "graph_recordings_and_replays": list(graph_stats),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "patch_gemv (finest packed level, one launch per patch width)",
+                     "bytes_per_sweep": bytes_sweep, "launches": n_apply,
+                     "avg_sweep_ms": ms_apply / max(n_sweeps, 1)},
+        "systems": [{"nx": s["shape"][0], "ny": s["shape"][1], "k": s["k"], "nu": s["nu"]} for s in B.systems],
+    }
+    S.close()
+    if not args.no_cpu_baseline:
+        # the FP64 oracle, one full step (setup + GMRES to 1e-8) of the first systems in turn
+        t0 = time.perf_counter()
+        cs = 0
+        done = 0
+        for si in range(len(B.systems)):
+            H = oracle.OracleHierarchy(B.hierarchies[si])
+            _, its_o, *_ = oracle.gmres(B.hierarchies[si][-1].J, B.rhs[si],
+                                        lambda v, h=H: oracle.vcycle(h, v, *nu), restart=restart, rtol=1e-8)
+            cs += its_o * sum(L.mesh.n_cells for L in B.hierarchies[si][1:]) * sum(nu)
+            done += 1
+            if time.perf_counter() - t0 > 15.0:
+                break
+        dt_c = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": cs / dt_c, "unit": "cell-sweeps/s", "cores": _threads(), "kind": "oracle",
+                               "sample": f"one full step of systems 0..{done - 1} of the batch, {dt_c:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
+def _threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([i.get("num_threads", 1) for i in threadpool_info()] + [1]))
+    except Exception:
+        return 1
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +255,7 @@ def main():
     ap.add_argument("--prec", default="f32", choices=["f64", "f32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64/BF16 comparison runs")
+    ap.add_argument("--no-graphs", action="store_true", help="batch: launch Arnoldi steps eagerly")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for {args.gpus})",
@@ -131,8 +266,10 @@ def main():
     import paper_2210_02690_amd as vk
     from synth import build_problem, CONFIGS
 
-    restart, max_iter, nu = 30, 300, (2, 2)
     dev = torch.device("cuda:0")
+    if args.config == "batch64_seed0":
+        return run_batch(args, torch, vk, dev)
+    restart, max_iter, nu = 30, 300, (2, 2)
     t0 = time.perf_counter()
     P = build_problem(args.config)
     log(f"[bench] built {args.config}: n = {P.finest.n}, levels = {len(P.levels)}, "
@@ -203,6 +340,20 @@ def main():
         out["finest_sweep_rate"] = {args.prec: sweep_rate(torch, S, P, P.b)}
     except Exception as e:  # pragma: no cover
         log(f"[bench] sweep rate failed: {e}")
+
+    # the same steps with every Arnoldi step replayed from a recorded hipGraph
+    S.vk_set_graphs(True)
+    run_step(S, b, x, nu, restart, max_iter)  # records the step graphs
+    reps = max(5, args.steps // 2)
+    dt_g, res = timed_steps(torch, lambda: run_step(S, b, x, nu, restart, max_iter), reps)
+    s_ms, g_ms, its_g, rel_g = phase_times(torch, S, b, x, nu, restart, max_iter)
+    out["graphs"] = {"value": sum(r[0] for r in res) * cs_per_vc / dt_g, "ms_per_step": dt_g / reps * 1e3,
+                     "gmres_ms_to_1e-8": g_ms, "setup_ms": s_ms, "gmres_iterations": its_g,
+                     "rel_diff_solution_vs_headline": float(np.linalg.norm(x.cpu().numpy() - x_head)
+                                                             / np.linalg.norm(x_head)),
+                     "graph_recordings": S.vk_graph_stats()[0]}
+    log(f"[bench] graphs: {dt_g / reps * 1e3:.2f} ms/step, gmres {g_ms:.2f} ms")
+    S.vk_set_graphs(False)
     S.close()
 
     if not args.no_compare:

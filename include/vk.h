@@ -236,6 +236,21 @@ vk_status vk_set_setup_variant(vk_ctx* ctx, int32_t variant);
  * A later vk_set_workspace resets the choices (vk_set_patch_tile overrides). */
 vk_status vk_autotune(vk_ctx* ctx, int32_t reps);
 
+/* ---- hipGraph replay --------------------------------------------------------
+ * With graphs enabled, gmres_solve and gmres_solve_batched record each Arnoldi
+ * step (V-cycle, J z, two Gram-Schmidt passes, norm, Givens update, scaling; one
+ * graph per step index j) the first time it runs and replay the recorded graph
+ * on the context's stream afterwards; vcycle records one graph per (b, x,
+ * nu_pre, nu_post).  Any call that changes what a graph has baked in (levels,
+ * segments, workspace, vanka_setup, tiles, autotuning, sweep variant, timing)
+ * makes the next step record again.  Results equal the eager launches bit for
+ * bit (the same kernels with the same arguments run in the same order).
+ * Recording needs a second stream, created by the first enable.  While timing
+ * is enabled, launches are eager.  vk_graph_stats returns the number of
+ * recordings and replays since vk_create. */
+vk_status vk_set_graphs(vk_ctx* ctx, int32_t enable);
+vk_status vk_graph_stats(const vk_ctx* ctx, int64_t* captures, int64_t* launches);
+
 /* ---- per-launch timing (benchmarks) --------------------------------------
  * With timing enabled, the library brackets every launch of the kernel classes
  * below with a pair of HIP events on the context's stream (a pool of 16384

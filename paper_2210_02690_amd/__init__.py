@@ -69,6 +69,8 @@ _SIGS = {
     "vk_set_sweep_variant": (ctypes.c_int, [_P, _I32]),
     "vk_set_setup_variant": (ctypes.c_int, [_P, _I32]),
     "vk_autotune": (ctypes.c_int, [_P, _I32]),
+    "vk_set_graphs": (ctypes.c_int, [_P, _I32]),
+    "vk_graph_stats": (ctypes.c_int, [_P, _PI64, _PI64]),
     "vk_set_level_groups": (ctypes.c_int, [_P, _I32, ctypes.POINTER(vk_csr), ctypes.POINTER(vk_csr),
                                            ctypes.POINTER(vk_csr), _I32, ctypes.POINTER(vk_cell_group), _I32,
                                            _PI64]),
@@ -311,6 +313,14 @@ class Solver:
 
     def vk_autotune(self, reps=10):
         self._check(_lib.vk_autotune(self.ctx, reps))
+
+    def vk_set_graphs(self, enable=True):
+        self._check(_lib.vk_set_graphs(self.ctx, 1 if enable else 0))
+
+    def vk_graph_stats(self):
+        c, n = ctypes.c_int64(0), ctypes.c_int64(0)
+        self._check(_lib.vk_graph_stats(self.ctx, ctypes.byref(c), ctypes.byref(n)))
+        return c.value, n.value
 
     def vk_timing_enable(self, enable=True, level=-1):
         self._check(_lib.vk_timing_enable(self.ctx, 1 if enable else 0, level))

@@ -263,6 +263,49 @@ vk_status read_scalars(vk_ctx* ctx, const double* dev, int count, double* out) {
   return VK_OK;
 }
 
+// Runs enqueue() on ctx->stream, or, with graphs on, replays the graph held in `slot` when it was
+// captured under the same key and parameter generation (capturing it first otherwise).  enqueue
+// must take its stream from ctx->stream, which points at the capture stream while recording.
+// Event timing needs eager launches, so it turns replay off.
+template <class F>
+vk_status replay(vk_ctx* ctx, size_t slot, const int64_t (&key)[6], F&& enqueue) {
+  if (!ctx->graphs || ctx->timing) return enqueue();
+  if (ctx->gslots.size() <= slot) ctx->gslots.resize(slot + 1);
+  vk_ctx::graph_slot& g = ctx->gslots[slot];
+  const bool hit = g.exec && g.gen == ctx->gen && std::equal(key, key + 6, g.key);
+  if (!hit) {
+    if (g.exec) {
+      (void)hipGraphExecDestroy(g.exec);
+      g.exec = nullptr;
+    }
+    hipStream_t user = ctx->stream;
+    VK_TRY(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeRelaxed));
+    ctx->stream = ctx->cap;
+    const vk_status st = enqueue();
+    ctx->stream = user;
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(ctx->cap, &graph);
+    if (st != VK_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipGetLastError();
+      return st;
+    }
+    if (e != hipSuccess) return fail_hip(ctx, e, "hipStreamEndCapture");
+    const hipError_t e2 = hipGraphInstantiateWithFlags(&g.exec, graph, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) {
+      g.exec = nullptr;
+      return fail_hip(ctx, e2, "hipGraphInstantiateWithFlags");
+    }
+    g.gen = ctx->gen;
+    std::copy(key, key + 6, g.key);
+    ++ctx->graph_captures;
+  }
+  VK_TRY(hipGraphLaunch(g.exec, ctx->stream));
+  ++ctx->graph_launches;
+  return VK_OK;
+}
+
 char g_create_err[256] = "";
 
 vk_status create_fail(vk_status st, const char* msg) {
@@ -314,6 +357,9 @@ void vk_destroy(vk_ctx* ctx) {
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   else (void)hipDeviceSynchronize();
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+  for (vk_ctx::graph_slot& g : ctx->gslots)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
   if (ctx->side) (void)hipStreamSynchronize(ctx->side);
   if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
   if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
@@ -328,6 +374,7 @@ vk_status vk_set_level_groups(vk_ctx* ctx, int32_t l, const vk_csr* J, const vk_
                               int32_t n_groups, const vk_cell_group* groups, int32_t n_blocks,
                               const int64_t* block_rows) {
   if (!ctx) return VK_ERR_ARG;
+  ++ctx->gen;
   if (l < 0 || l >= ctx->n_levels) return fail(ctx, VK_ERR_ARG, "level index out of range");
   if (!csr_ok(J) || J->n_rows != J->n_cols || J->n_rows == 0)
     return fail(ctx, VK_ERR_ARG, "J must be a non-empty square CSR matrix with valid pointers");
@@ -442,6 +489,7 @@ vk_status vk_set_level(vk_ctx* ctx, int32_t l, const vk_csr* J, const vk_csr* P,
 
 vk_status vk_set_segments(vk_ctx* ctx, int32_t n_seg, const int64_t* seg_rows) {
   if (!ctx) return VK_ERR_ARG;
+  ++ctx->gen;
   const vk_level& F = ctx->lv[ctx->n_levels - 1];
   if (!F.set) return fail(ctx, VK_ERR_STATE, "set the finest level before its segments");
   if (n_seg < 1 || n_seg > 4096 || !seg_rows) return fail(ctx, VK_ERR_ARG, "1 <= n_seg <= 4096 segments required");
@@ -467,6 +515,7 @@ size_t vk_workspace_bytes(const vk_ctx* cctx, vk_prec prec, int32_t restart) {
 
 vk_status vk_set_workspace(vk_ctx* ctx, void* dev, size_t bytes, vk_prec prec, int32_t restart) {
   if (!ctx) return VK_ERR_ARG;
+  ++ctx->gen;
   if (prec != VK_F64 && prec != VK_F32 && prec != VK_BF16) return fail(ctx, VK_ERR_ARG, "unknown precision");
   if (restart < 1 || restart > VK_MAX_RESTART) return fail(ctx, VK_ERR_ARG, "restart must be in [1, 64]");
   std::string why;
@@ -510,8 +559,12 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
   if (!(omega > 0.0) || !std::isfinite(omega)) return fail(ctx, VK_ERR_ARG, "omega must be positive");
   if (mode != VK_ADDITIVE && mode != VK_MULT_COLOURED) return fail(ctx, VK_ERR_ARG, "unknown smoother mode");
   ctx->setup_done = false;
+  // recorded graphs stay valid across setups unless omega, the mode or where an inverse lives changes
+  if (omega != ctx->omega || mode != ctx->mode) ++ctx->gen;
   ctx->omega = omega;
   ctx->mode = mode;
+  std::vector<double*> old_W;
+  for (const vk_level& L : ctx->lv) old_W.push_back(L.cb_W);
   hipStream_t s = ctx->stream;
   // status words: [0] directly solved blocks (pivot), [1] block coupling, [64 + l] first singular cell of level l
   VK_TRY(launch_fill_i32(s, 2, INT_MAX, ctx->status));
@@ -526,6 +579,8 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
     if (L.cb_rows.size() > 1) VK_TRY(launch_block_invert(ctx->side, L, ctx->status, &L.cb_W));
   }
   VK_TRY(hipEventRecord(ctx->join_ev, ctx->side));
+  for (int l = 0; l < ctx->n_levels; ++l)
+    if (ctx->lv[l].cb_W != old_W[l]) ++ctx->gen;
   if (!ctx->maps_ready) {
     // multiplicities and DoF -> (cell, local) lists depend on the mesh only
     for (int l = 1; l < ctx->n_levels; ++l) {
@@ -589,7 +644,8 @@ vk_status vcycle(vk_ctx* ctx, const double* b, double* x, int32_t nu_pre, int32_
   VK_CHECK(ready(ctx));
   if (!b || !x || b == x) return fail(ctx, VK_ERR_ARG, "b and x must be distinct non-null vectors");
   if (nu_pre < 0 || nu_post < 0) return fail(ctx, VK_ERR_ARG, "negative sweep count");
-  return vcycle_level(ctx, ctx->n_levels - 1, b, x, nu_pre, nu_post);
+  const int64_t key[6] = {(int64_t)(uintptr_t)b, (int64_t)(uintptr_t)x, nu_pre, nu_post, 0, 0};
+  return replay(ctx, 0, key, [&]() { return vcycle_level(ctx, ctx->n_levels - 1, b, x, nu_pre, nu_post); });
 }
 
 vk_status gmres_solve(vk_ctx* ctx, const double* b, double* x, int32_t restart, int32_t max_iter, double rtol,
@@ -648,16 +704,22 @@ vk_status gmres_solve(vk_ctx* ctx, const double* b, double* x, int32_t restart, 
       double* Vn = ctx->V + (int64_t)(j + 1) * ldv;
       double* Zj = ctx->Z + (int64_t)j * ldv;
       double* Hc = ctx->H + (int64_t)j * ldh;
-      VK_CHECK(vcycle_level(ctx, L, Vj, Zj, nu_pre, nu_post));
-      VK_TRY(launch_spmv(s, F.J, F.lpr_J, 1.0, Zj, 0.0, nullptr, Vn));
-      // classical Gram-Schmidt, applied twice
-      VK_TRY(launch_mdot(s, n, ctx->V, ldv, j + 1, Vn, ctx->partial, ctx->n_partial, Hc));
-      VK_TRY(launch_maxpy(s, n, ctx->V, ldv, j + 1, Hc, -1.0, Vn));
-      VK_TRY(launch_mdot(s, n, ctx->V, ldv, j + 1, Vn, ctx->partial, ctx->n_partial, ctx->h2));
-      VK_TRY(launch_maxpy(s, n, ctx->V, ldv, j + 1, ctx->h2, -1.0, Vn));
-      VK_TRY(launch_dot(s, n, Vn, Vn, ctx->partial, ctx->n_partial, Hc + j + 1, true));
-      VK_TRY(launch_givens(s, j, ldh, ctx->H, ctx->h2, ctx->cs, ctx->sn, ctx->g, sc + 2));
-      VK_TRY(launch_scale_by_inv(s, n, Vn, sc + 3, Vn));
+      auto step = [&]() -> vk_status {
+        hipStream_t q = ctx->stream;
+        VK_CHECK(vcycle_level(ctx, L, Vj, Zj, nu_pre, nu_post));
+        VK_TRY(launch_spmv(q, F.J, F.lpr_J, 1.0, Zj, 0.0, nullptr, Vn));
+        // classical Gram-Schmidt, applied twice
+        VK_TRY(launch_mdot(q, n, ctx->V, ldv, j + 1, Vn, ctx->partial, ctx->n_partial, Hc));
+        VK_TRY(launch_maxpy(q, n, ctx->V, ldv, j + 1, Hc, -1.0, Vn));
+        VK_TRY(launch_mdot(q, n, ctx->V, ldv, j + 1, Vn, ctx->partial, ctx->n_partial, ctx->h2));
+        VK_TRY(launch_maxpy(q, n, ctx->V, ldv, j + 1, ctx->h2, -1.0, Vn));
+        VK_TRY(launch_dot(q, n, Vn, Vn, ctx->partial, ctx->n_partial, Hc + j + 1, true));
+        VK_TRY(launch_givens(q, j, ldh, ctx->H, ctx->h2, ctx->cs, ctx->sn, ctx->g, sc + 2));
+        VK_TRY(launch_scale_by_inv(q, n, Vn, sc + 3, Vn));
+        return VK_OK;
+      };
+      const int64_t key[6] = {j, ldh, nu_pre, nu_post, 0, 0};
+      VK_CHECK(replay(ctx, 1 + (size_t)j, key, step));
       VK_CHECK(read_scalars(ctx, sc + 2, 2, hb));
       ++its;
       jn = j + 1;
@@ -735,20 +797,26 @@ vk_status gmres_solve_batched(vk_ctx* ctx, const double* b, double* x, int32_t r
       double* Vj = ctx->V + (int64_t)j * ldv;
       double* Vn = ctx->V + (int64_t)(j + 1) * ldv;
       double* Zj = ctx->Z + (int64_t)j * ldv;
-      VK_CHECK(vcycle_level(ctx, L, Vj, Zj, nu_pre, nu_post));
-      VK_TRY(launch_spmv(s, F.J, F.lpr_J, 1.0, Zj, 0.0, nullptr, Vn));
       // classical Gram-Schmidt twice, per segment; the first pass goes into column j of H
       double* Hc = ctx->H + (int64_t)j * (m + 1);
-      VK_TRY(launch_seg_mdot(s, ns, seg, max_len, ctx->V, ldv, j + 1, Vn, ctx->partial, ctx->n_partial, Hc,
-                             (int32_t)hs));
-      VK_TRY(launch_seg_maxpy(s, ns, seg, max_len, ctx->V, ldv, j + 1, Hc, (int32_t)hs, nullptr, -1.0, Vn));
-      VK_TRY(launch_seg_mdot(s, ns, seg, max_len, ctx->V, ldv, j + 1, Vn, ctx->partial, ctx->n_partial, ctx->h2,
-                             m + 1));
-      VK_TRY(launch_seg_maxpy(s, ns, seg, max_len, ctx->V, ldv, j + 1, ctx->h2, m + 1, nullptr, -1.0, Vn));
-      VK_TRY(launch_seg_dot(s, ns, seg, max_len, Vn, Vn, ctx->partial, ctx->n_partial, resid + ns, true));
-      VK_TRY(launch_seg_givens(s, ns, j, m, ctx->H, ctx->h2, ctx->cs, ctx->sn, ctx->g, tol, its, max_iter, active,
-                               jn, resid));
-      VK_TRY(launch_seg_scale(s, ns, seg, max_len, Vn, resid + ns, active, Vn));
+      auto step = [&]() -> vk_status {
+        hipStream_t q = ctx->stream;
+        VK_CHECK(vcycle_level(ctx, L, Vj, Zj, nu_pre, nu_post));
+        VK_TRY(launch_spmv(q, F.J, F.lpr_J, 1.0, Zj, 0.0, nullptr, Vn));
+        VK_TRY(launch_seg_mdot(q, ns, seg, max_len, ctx->V, ldv, j + 1, Vn, ctx->partial, ctx->n_partial, Hc,
+                               (int32_t)hs));
+        VK_TRY(launch_seg_maxpy(q, ns, seg, max_len, ctx->V, ldv, j + 1, Hc, (int32_t)hs, nullptr, -1.0, Vn));
+        VK_TRY(launch_seg_mdot(q, ns, seg, max_len, ctx->V, ldv, j + 1, Vn, ctx->partial, ctx->n_partial, ctx->h2,
+                               m + 1));
+        VK_TRY(launch_seg_maxpy(q, ns, seg, max_len, ctx->V, ldv, j + 1, ctx->h2, m + 1, nullptr, -1.0, Vn));
+        VK_TRY(launch_seg_dot(q, ns, seg, max_len, Vn, Vn, ctx->partial, ctx->n_partial, resid + ns, true));
+        VK_TRY(launch_seg_givens(q, ns, j, m, ctx->H, ctx->h2, ctx->cs, ctx->sn, ctx->g, tol, its, max_iter,
+                                 active, jn, resid));
+        VK_TRY(launch_seg_scale(q, ns, seg, max_len, Vn, resid + ns, active, Vn));
+        return VK_OK;
+      };
+      const int64_t key[6] = {j, m, nu_pre, nu_post, max_iter, 0};
+      VK_CHECK(replay(ctx, 1 + (size_t)ctx->restart + (size_t)j, key, step));
       j_end = j + 1;
       VK_TRY(hipMemcpyAsync(hi.data(), active, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, s));
       VK_TRY(hipStreamSynchronize(s));
@@ -804,6 +872,7 @@ vk_status vk_get_coarse_inverse(vk_ctx* ctx, double* out) {
 
 vk_status vk_set_patch_tile(vk_ctx* ctx, int32_t l, int32_t cells_per_block) {
   if (!ctx) return VK_ERR_ARG;
+  ++ctx->gen;
   if (l < 1 || l >= ctx->n_levels || !ctx->lv[l].set) return fail(ctx, VK_ERR_ARG, "level not set");
   if (!(cells_per_block == 0 || cells_per_block == 1 || cells_per_block == 2 || cells_per_block == 4 ||
         cells_per_block == 8))
@@ -826,6 +895,7 @@ vk_status vk_patch_layout(const vk_ctx* ctx, int32_t l, int64_t* bytes_per_cell,
 
 vk_status vk_autotune(vk_ctx* ctx, int32_t reps) {
   VK_CHECK(ready(ctx));
+  ++ctx->gen;
   if (reps < 1) reps = 1;
   hipStream_t s = ctx->stream;
   hipEvent_t e0, e1;
@@ -879,6 +949,7 @@ vk_status vk_autotune(vk_ctx* ctx, int32_t reps) {
 
 vk_status vk_set_sweep_variant(vk_ctx* ctx, int32_t variant) {
   if (!ctx) return VK_ERR_ARG;
+  ++ctx->gen;
   if (variant != VK_SWEEP_DOF_GATHER && variant != VK_SWEEP_COLOURED_SCATTER)
     return fail(ctx, VK_ERR_ARG, "unknown sweep variant");
   ctx->sweep_variant = variant;
@@ -893,8 +964,24 @@ vk_status vk_set_setup_variant(vk_ctx* ctx, int32_t variant) {
   return VK_OK;
 }
 
+vk_status vk_set_graphs(vk_ctx* ctx, int32_t enable) {
+  if (!ctx) return VK_ERR_ARG;
+  if (enable != 0 && enable != 1) return fail(ctx, VK_ERR_ARG, "enable must be 0 or 1");
+  if (enable && !ctx->cap) VK_TRY(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+  ctx->graphs = enable != 0;
+  return VK_OK;
+}
+
+vk_status vk_graph_stats(const vk_ctx* ctx, int64_t* captures, int64_t* launches) {
+  if (!ctx) return VK_ERR_ARG;
+  if (captures) *captures = ctx->graph_captures;
+  if (launches) *launches = ctx->graph_launches;
+  return VK_OK;
+}
+
 vk_status vk_timing_enable(vk_ctx* ctx, int32_t enable, int32_t level) {
   if (!ctx) return VK_ERR_ARG;
+  ++ctx->gen;
   if (enable) {
     if (ctx->ev.empty()) {
       ctx->ev.resize(2 * kTimingPool);

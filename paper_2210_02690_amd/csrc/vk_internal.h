@@ -156,6 +156,19 @@ struct vk_ctx {
   double* partial = nullptr;  // block partial sums
   double* scal = nullptr;     // device scalars
   int32_t n_partial = 0;
+  // hipGraph replay: one graph per Arnoldi step index (single and batched GMRES) and one
+  // for the stand-alone V-cycle, captured on first use and replayed while nothing baked
+  // into them (pointers, launch shapes, omega, sweep counts) has changed
+  bool graphs = false;
+  hipStream_t cap = nullptr;  // capture stream (the caller's stream may be the null stream)
+  uint64_t gen = 1;           // bumped by every call that changes a baked parameter
+  struct graph_slot {
+    hipGraphExec_t exec = nullptr;
+    uint64_t gen = 0;
+    int64_t key[6] = {0, 0, 0, 0, 0, 0};
+  };
+  std::vector<graph_slot> gslots;
+  int64_t graph_launches = 0, graph_captures = 0;
 };
 
 // ---- launchers (defined in the .hip files) --------------------------------
