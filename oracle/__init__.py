@@ -14,7 +14,12 @@ float64, written from the paper's description (Sec. 3):
                   Gram-Schmidt and Givens rotations;
   * precision.py  round-to-nearest-even storage of the patch inverses in FP32
                   and BF16 (a project extension; parity unpinned, bounded by
-                  rounding analysis instead).
+                  rounding analysis instead);
+  * newton.py     the damped Newton iteration of one slab and the march over
+                  consecutive slabs;
+  * mlp.py        the multilayer perceptron of the learned initial guess (a
+                  project extension): forward, mean-squared-error gradient and
+                  Adam, in FP64 with optional BF16 rounding at the stores.
 """
 from .vanka import (patch_matrix, patch_matrices, invert_patches, multiplicity, setup_level,
                     additive_sweep, additive_sweep_loop, additive_sweep_correction,
@@ -22,10 +27,13 @@ from .vanka import (patch_matrix, patch_matrices, invert_patches, multiplicity, 
 from .multigrid import OracleHierarchy, vcycle
 from .gmres import gmres
 from .precision import round_bf16, round_f32
+from .newton import newton_slab, march
+from . import mlp
 
 __all__ = [
     "patch_matrix", "patch_matrices", "invert_patches", "multiplicity", "setup_level",
     "additive_sweep", "additive_sweep_loop", "additive_sweep_correction",
     "multiplicative_sweep", "smooth", "cell_order",
     "OracleHierarchy", "vcycle", "gmres", "round_bf16", "round_f32",
+    "newton_slab", "march", "mlp",
 ]

@@ -19,6 +19,7 @@ import torch  # noqa: F401
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libvk.so")
 HEADER = os.path.join(os.path.dirname(_PKG), "include", "vk.h")
+HEADERS = [HEADER, os.path.join(os.path.dirname(_PKG), "include", "vk_mlp.h")]
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python paper_2210_02690_amd/build.py`")
@@ -77,6 +78,22 @@ _SIGS = {
     "vk_set_segments": (ctypes.c_int, [_P, _I32, _PI64]),
     "gmres_solve_batched": (ctypes.c_int, [_P, _P, _P, _I32, _I32, _D, _D, _I32, _I32, _PI32, _PD, _PI32]),
     "vk_timing_read": (ctypes.c_int, [_P, _I32, _I32, _PI64, _PD]),
+    # learned initial guess (vk_mlp.h)
+    "vk_mlp_create": (ctypes.c_int, [ctypes.POINTER(_P), _I32, _I32, _I32, _I32, _I32, _P]),
+    "vk_mlp_destroy": (None, [_P]),
+    "vk_mlp_last_error": (ctypes.c_char_p, [_P]),
+    "vk_mlp_param_count": (_I64, [_P]),
+    "vk_mlp_workspace_bytes": (_SZ, [_P]),
+    "vk_mlp_set_workspace": (ctypes.c_int, [_P, _P, _SZ]),
+    "vk_mlp_set_params": (ctypes.c_int, [_P, _P]),
+    "vk_mlp_get_params": (ctypes.c_int, [_P, _P]),
+    "vk_mlp_forward": (ctypes.c_int, [_P, _I32, _P, _P, _P]),
+    "vk_mlp_gradient": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P]),
+    "vk_mlp_adam": (ctypes.c_int, [_P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]),
+    "vk_mlp_patch_features": (ctypes.c_int, [_P, _I32, _I32, _P, _P, _P, _P, _P, _P, _P]),
+    "vk_mlp_patch_targets": (ctypes.c_int, [_P, _I32, _I32, _P, _P, _P, _P, _P, _P]),
+    "vk_mlp_patch_average": (ctypes.c_int, [_P, _I64, _P, _P, _I32, _P, _P, _P, _P, _P]),
+    "vk_mlp_slab_extrapolate": (ctypes.c_int, [_P, _I64, _I32, _PD, _P, _P]),
 }
 KERNEL_KINDS = {"patch_apply": 0, "spmv": 1, "patch_setup": 2, "patch_residual": 3, "patch_gemv": 4,
                 "dof_gather": 5}
@@ -87,12 +104,15 @@ for _name, (_res, _args) in _SIGS.items():
     _f.argtypes = _args
 
 
-def header_functions(path=HEADER):
-    """Names of the functions declared in include/vk.h."""
-    with open(path) as f:
-        text = f.read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(?:vk_status|void|size_t|const char\*)\s+\*?(\w+)\s*\(", text)))
+def header_functions(paths=None):
+    """Names of the functions declared in include/vk.h and include/vk_mlp.h."""
+    names = set()
+    for path in (HEADERS if paths is None else ([paths] if isinstance(paths, str) else paths)):
+        with open(path) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(?:vk_status|void|size_t|int64_t|const char\*)\s+\*?(\w+)\s*\(", text))
+    return sorted(names)
 
 
 class VkError(RuntimeError):
@@ -338,3 +358,99 @@ class Solver:
 
 def lib():
     return _lib
+
+
+class MLP:
+    """A vk_mlp context: the BF16 network of the learned initial guess and its patch kernels.
+
+    Tensors passed in must live on the context's device; BF16 arrays are torch.bfloat16."""
+
+    def __init__(self, n_in, width, n_hidden, n_out, max_batch, device="cuda", stream=None):
+        import torch
+        ctx = _P()
+        st = _lib.vk_mlp_create(ctypes.byref(ctx), n_in, width, n_hidden, n_out, max_batch, _stream_handle(stream))
+        if st != VK_OK:
+            raise VkError(st, _lib.vk_mlp_last_error(None).decode())
+        self.ctx = ctx
+        self.shape = (n_in, width, n_hidden, n_out)
+        self.n_params = int(_lib.vk_mlp_param_count(ctx))
+        nbytes = int(_lib.vk_mlp_workspace_bytes(ctx))
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-ws.data_ptr()) % 256
+        self._check(_lib.vk_mlp_set_workspace(ctx, ctypes.c_void_p(ws.data_ptr() + off), nbytes))
+        self.workspace = ws
+        self.device = device
+
+    def _check(self, st):
+        if st != VK_OK:
+            raise VkError(st, _lib.vk_mlp_last_error(self.ctx).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            _lib.vk_mlp_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        self._check(_lib.vk_mlp_set_params(self.ctx, _ptr(params)))
+
+    def get_params(self):
+        import torch
+        out = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        self._check(_lib.vk_mlp_get_params(self.ctx, _ptr(out)))
+        return out
+
+    def forward(self, x, rows=None, out=None):
+        import torch
+        batch = int(rows.numel()) if rows is not None else int(x.shape[0])
+        if out is None:
+            out = torch.empty((batch, self.shape[3]), dtype=torch.float32, device=self.device)
+        self._check(_lib.vk_mlp_forward(self.ctx, batch, _ptr(x), _ptr(rows), _ptr(out)))
+        return out
+
+    def gradient(self, x, target, rows=None, want_grad=True):
+        import torch
+        batch = int(rows.numel()) if rows is not None else int(x.shape[0])
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        grad = torch.empty(self.n_params, dtype=torch.float32, device=self.device) if want_grad else None
+        self._check(_lib.vk_mlp_gradient(self.ctx, batch, _ptr(x), _ptr(rows), _ptr(target), _ptr(loss),
+                                         _ptr(grad)))
+        return loss, grad
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._check(_lib.vk_mlp_adam(self.ctx, lr, beta1, beta2, eps))
+
+    def patch_features(self, cell_dofs, X1, X2, B, mean, inv_std, out):
+        n_cells, n_K = cell_dofs.shape
+        self._check(_lib.vk_mlp_patch_features(self.ctx, n_cells, n_K, _ptr(cell_dofs), _ptr(X1), _ptr(X2),
+                                               _ptr(B), _ptr(mean), _ptr(inv_std), _ptr(out)))
+
+    def patch_targets(self, cell_dofs, X, base, mean, inv_std, out):
+        n_cells, n_K = cell_dofs.shape
+        self._check(_lib.vk_mlp_patch_targets(self.ctx, n_cells, n_K, _ptr(cell_dofs), _ptr(X), _ptr(base),
+                                              _ptr(mean), _ptr(inv_std), _ptr(out)))
+
+    def patch_average(self, dof_ptr, dof_list, n_K, pred, mean, std, base, out):
+        self._check(_lib.vk_mlp_patch_average(self.ctx, int(base.numel()), _ptr(dof_ptr), _ptr(dof_list), n_K,
+                                              _ptr(pred), _ptr(mean), _ptr(std), _ptr(base), _ptr(out)))
+
+    def slab_extrapolate(self, E, X, out):
+        Eh = np.ascontiguousarray(E, dtype=np.float64)
+        n_time = Eh.shape[0]
+        self._check(_lib.vk_mlp_slab_extrapolate(self.ctx, int(X.numel()) // n_time, n_time,
+                                                 Eh.ctypes.data_as(_PD), _ptr(X), _ptr(out)))
+
+
+def dof_entries(cell_dofs, n):
+    """CSR of DoF -> patch entries (cell * n_K + local), ascending, for MLP.patch_average (host)."""
+    cd = np.asarray(cell_dofs, dtype=np.int64)
+    flat = cd.ravel()
+    order = np.argsort(flat, kind="stable")
+    ptr = np.concatenate([[0], np.cumsum(np.bincount(flat, minlength=n))]).astype(np.int64)
+    return ptr, order.astype(np.int64)

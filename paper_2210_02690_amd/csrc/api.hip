@@ -112,7 +112,8 @@ size_t plan_workspace(vk_ctx* ctx, vk_prec prec, int32_t restart, char* base) {
     const int nbk = (int)L.cb_rows.size() - 1;
     if (nbk > 0) {
       L.cb_a = cv.take<double>(L.cb_sq);
-      L.cb_b = cv.take<double>(L.cb_sq);
+      L.cb_gi = cv.take<double>((int64_t)nbk * VK_GJ_NBI_MAX * VK_GJ_NBO);
+      L.cb_go = cv.take<double>((int64_t)VK_GJ_NBO * (L.cb_rows[nbk] - L.cb_rows[0]));
       L.d_cb_rows = cv.take<int64_t>(nbk + 1);
       L.d_cb_woff = cv.take<int64_t>(nbk);
       L.cb_q = cv.take<int32_t>(n);

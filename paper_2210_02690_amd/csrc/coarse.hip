@@ -2,27 +2,34 @@
 // for J_0 d_0 = b_0 on T_0), and in a batch of independent systems every
 // system's coarsest level.  All blocks of a level are processed together.
 //
-// Setup inverts the dense FP64 J_0 by blocked Gauss-Jordan elimination with
-// implicit partial pivoting: the pivot of column k is the not-yet-used row
-// q_k with the largest |value| (the first such row on ties); rows never move.
-// For each panel of NB columns:
-//   panel kernel  (one 256-thread workgroup, the panel rows in registers):
-//                 the NB elimination steps restricted to the panel columns;
-//   update kernel (whole GPU): the same transformation on every other
-//                 column, as the rank-NB update
-//                   out[i, c] = (i a pivot row of the panel ? 0 : in[i, c])
-//                               + sum_j X[i, j] in[q_j, c],
-//                 X the eliminated panel.
-// Two buffers alternate so no workgroup reads what another writes.  The
-// stored matrix W then satisfies J_0^{-1}[k][q_j] = W[q_k][j], so the coarse
-// solve is y[k] = sum_j W[q_k][j] b[q_j].
+// Setup inverts each dense FP64 block in place by blocked Gauss-Jordan
+// elimination with implicit partial pivoting: the pivot of column k is the
+// not-yet-used row q_k with the largest |value| (the first such row on ties);
+// rows never move.  The stored matrix W then satisfies
+// J^{-1}[k][q_j] = W[q_k][j], so the solve is y[k] = sum_j W[q_k][j] b[q_j].
+//
+// Two levels of blocking.  The columns are taken in outer blocks of NBO = 64;
+// within an outer block, inner panels of NB columns:
+//   panel kernel  (one workgroup per block, the panel rows in registers): the
+//                 NB elimination steps restricted to the panel's columns; it
+//                 records each new pivot row's column and copies the pivot
+//                 rows' old values in the rest of the outer block;
+//   inner update: the same steps on the rest of the outer block (rank NB).
+// After the outer block's columns are eliminated, one rank-NBO update brings
+// every other column along; eliminating a set of pivots P at once gives, for
+// the eliminated columns C and any other column c,
+//   W'[i, c] = (i in P ? 0 : W[i, c]) + sum_{t in C} W'[i, t] W[q_t, c],
+// a GEMM on the FP64 matrix cores (the pivot rows' old values are copied out
+// first, so the update runs in place).
 #include <climits>
 
 #include "vk_internal.h"
 
 namespace {
 
-constexpr int CT = 256;  // panel kernel threads
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int NBO = VK_GJ_NBO;
 
 __device__ inline int block_of(const int64_t* __restrict__ rows, int nb, int64_t r) {
   int lo = 0, hi = nb;  // last block with rows[b] <= r
@@ -57,14 +64,17 @@ __global__ void block_to_dense_kernel(int n_blocks, const int64_t* __restrict__ 
   }
 }
 
-template <int R, int NB>
-__global__ __launch_bounds__(CT) void block_panel_kernel(const int64_t* __restrict__ rows,
-                                                         const int64_t* __restrict__ woff, int64_t k0,
-                                                         const double* __restrict__ Min_, double* __restrict__ Mout_,
-                                                         int32_t* __restrict__ q_all, int32_t* __restrict__ used_all,
-                                                         int32_t* status) {
-  __shared__ double w_abs[CT / 64];
-  __shared__ int w_idx[CT / 64];
+// Panel of columns [k0, k0 + NB) of every block (blockIdx.x), in place.  pcol[i] is
+// 0 for a row not yet used as a pivot, else 1 + the column it was pivot of.  gi: the
+// new pivot rows' old values in the outer block's other columns, laid out [t][c - c0o].
+template <int CTT, int R, int NB>
+__global__ __launch_bounds__(CTT) void block_panel_kernel(const int64_t* __restrict__ rows,
+                                                          const int64_t* __restrict__ woff, int64_t k0, int64_t c0o,
+                                                          double* W_all, int32_t* __restrict__ q_all,
+                                                          int32_t* __restrict__ pcol_all, double* __restrict__ gi_all,
+                                                          int32_t* status) {
+  __shared__ double w_abs[CTT / 64];
+  __shared__ int w_idx[CTT / 64];
   __shared__ double prow[NB];
   __shared__ int s_q[NB];
   const int bk = blockIdx.x;
@@ -72,21 +82,20 @@ __global__ __launch_bounds__(CT) void block_panel_kernel(const int64_t* __restri
   const int64_t left = n - k0;
   const int nb = left <= 0 ? 0 : (left < NB ? (int)left : NB);
   if (nb == 0) return;  // uniform for the workgroup
-  const double* Min = Min_ + woff[bk];
-  double* Mout = Mout_ + woff[bk];
+  double* W = W_all + woff[bk];
   int32_t* q_g = q_all + r0;
-  int32_t* used_g = used_all + r0;
+  int32_t* pcol_g = pcol_all + r0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // P[r][.]: panel row tid + r * CT; the column loop is unrolled completely
+  // P[r][.]: panel row tid + r * CTT; the column loop is unrolled completely
   double P[R][NB];
   uint32_t used = 0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int64_t i = tid + (int64_t)r * CT;
+    const int64_t i = tid + (int64_t)r * CTT;
     const bool ok = i < n;
 #pragma unroll
-    for (int c = 0; c < NB; ++c) P[r][c] = (ok && c < nb) ? Min[i * n + k0 + c] : 0.0;
-    if (!ok || used_g[i]) used |= 1u << r;
+    for (int c = 0; c < NB; ++c) P[r][c] = (ok && c < nb) ? W[i * n + k0 + c] : 0.0;
+    if (!ok || pcol_g[i] != 0) used |= 1u << r;
   }
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
@@ -96,7 +105,7 @@ __global__ __launch_bounds__(CT) void block_panel_kernel(const int64_t* __restri
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const double av = fabs(P[r][j]);
-        if (!((used >> r) & 1u) && av > ba) { ba = av; bi = tid + r * CT; }
+        if (!((used >> r) & 1u) && av > ba) { ba = av; bi = tid + r * CTT; }
       }
       const double m = wave_max(ba);
       const int wi = wave_min((ba == m && bi != INT_MAX) ? bi : INT_MAX);
@@ -105,13 +114,13 @@ __global__ __launch_bounds__(CT) void block_panel_kernel(const int64_t* __restri
       double pm = w_abs[0];
       int p = w_idx[0];
 #pragma unroll
-      for (int w = 1; w < CT / 64; ++w) {
+      for (int w = 1; w < CTT / 64; ++w) {
         const double om = w_abs[w];
         const int oi = w_idx[w];
         if (om > pm || (om == pm && oi < p)) { pm = om; p = oi; }
       }
       const bool bad = p == INT_MAX || !(pm > 0.0) || !isfinite(pm);
-      const int owner = bad ? -1 : p % CT, slot = bad ? -1 : p / CT;
+      const int owner = bad ? -1 : p % CTT, slot = bad ? -1 : p / CTT;
       if (tid == owner) {
         double v[NB];
 #pragma unroll
@@ -139,8 +148,8 @@ __global__ __launch_bounds__(CT) void block_panel_kernel(const int64_t* __restri
           const double keep = piv ? 0.0 : 1.0;
 #pragma unroll
           for (int c = 0; c < NB; ++c) {
-            const double pc = prow[c];
-            P[r][c] = (c == j) ? -f * pc : fma(-f, pc, keep * P[r][c]);
+            const double pcv = prow[c];
+            P[r][c] = (c == j) ? -f * pcv : fma(-f, pcv, keep * P[r][c]);
           }
         }
       }
@@ -149,73 +158,99 @@ __global__ __launch_bounds__(CT) void block_panel_kernel(const int64_t* __restri
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int64_t i = tid + (int64_t)r * CT;
+    const int64_t i = tid + (int64_t)r * CTT;
     if (i < n) {
 #pragma unroll
       for (int c = 0; c < NB; ++c)
-        if (c < nb) Mout[i * n + k0 + c] = P[r][c];
-      used_g[i] = (used >> r) & 1u;
+        if (c < nb) W[i * n + k0 + c] = P[r][c];
     }
   }
-  if (tid < nb) q_g[k0 + tid] = s_q[tid];
+  if (tid < nb) {
+    q_g[k0 + tid] = s_q[tid];
+    pcol_g[s_q[tid]] = (int32_t)(k0 + tid + 1);
+  }
+  // old values of the new pivot rows in the other columns of the outer block (this kernel
+  // writes only the panel's columns)
+  const int64_t ge = (c0o + NBO < n ? c0o + NBO : n);
+  const int64_t gw = ge - c0o;
+  double* gi = gi_all + (int64_t)bk * NB * NBO;
+  for (int64_t e = tid; e < (int64_t)nb * gw; e += CTT) {
+    const int t = (int)(e / gw);
+    const int64_t c = c0o + (e - (int64_t)t * gw);
+    if (c < k0 || c >= k0 + nb) gi[t * NBO + (c - c0o)] = W[(int64_t)s_q[t] * n + c];
+  }
 }
 
-// Rank-NB update of the columns outside the panel of every block (blockIdx.z);
-// tiles of 32 rows x 64 columns.  A block whose elimination is complete is
-// copied unchanged, so all blocks end in the same buffer.
-template <int NB>
-__global__ __launch_bounds__(256) void block_update_kernel(const int64_t* __restrict__ rows,
-                                                           const int64_t* __restrict__ woff, int64_t k0,
-                                                           const double* __restrict__ Min_, double* Mout_,
-                                                           const int32_t* __restrict__ q_all) {
-  __shared__ double Rt[NB][64];
-  __shared__ double Xt[32][NB + 1];
-  __shared__ int qs[NB];
+// old values of the outer block's pivot rows in every column: go[t][c] = W[q[c0o + t]][c]
+__global__ void gather_pivot_rows_kernel(const int64_t* __restrict__ rows, const int64_t* __restrict__ woff,
+                                         int64_t c0o, const double* __restrict__ W_all,
+                                         const int32_t* __restrict__ q_all, double* __restrict__ go_all) {
+  const int bk = blockIdx.z;
+  const int64_t r0 = rows[bk], n = rows[bk + 1] - r0;
+  const int64_t kk = n - c0o < NBO ? n - c0o : NBO;
+  const int t = blockIdx.y;
+  if (t >= kk) return;
+  const double* W = W_all + woff[bk];
+  const int64_t q = q_all[r0 + c0o + t];
+  double* go = go_all + (int64_t)NBO * (r0 - rows[0]) + (int64_t)t * n;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
+    go[c] = W[q * n + c];
+}
+
+// In-place update of columns [cb, ce) \ [sk0, sk1) of every block (blockIdx.z):
+//   W[i, c] = (pcol[i] - 1 in [p0, p1) ? 0 : W[i, c]) + sum_{t < K} W[i, kc + t] G[t][c - gc0]
+// with K clipped to the block.  G: inner mode (g_stride > 0) block b at b * g_stride with
+// leading dimension ldg; outer mode (g_stride == 0) block b at NBO * (rows[b] - rows[0]) with
+// leading dimension n_b.  Workgroup tile 64 x 64 (four wavefronts of 16 rows), FP64 matrix
+// cores (16 x 16 x 4); lane l holds A(l % 16, l / 16), B(l / 16, l % 16) and, in accumulator
+// element i, C(4 i + l / 16, l % 16).
+__global__ __launch_bounds__(256) void gj_update_kernel(const int64_t* __restrict__ rows,
+                                                        const int64_t* __restrict__ woff, double* W_all,
+                                                        const int32_t* __restrict__ pcol_all, int64_t kc, int32_t K,
+                                                        const double* __restrict__ G_all, int64_t g_stride,
+                                                        int64_t ldg, int64_t gc0, int64_t cb, int64_t ce,
+                                                        int64_t sk0, int64_t sk1, int64_t p0, int64_t p1,
+                                                        int64_t tile_c0) {
   const int bk = blockIdx.z;
   const int64_t rb0 = rows[bk], n = rows[bk + 1] - rb0;
-  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 64;
-  if (r0 >= n || c0 >= n) return;  // uniform for the workgroup
-  const int64_t left = n - k0;
-  const int nb = left <= 0 ? 0 : (left < NB ? (int)left : NB);
-  const double* Min = Min_ + woff[bk];
-  double* Mout = Mout_ + woff[bk];
-  const int32_t* q_g = q_all + rb0;
-  const int tid = threadIdx.x;
-  if (tid < NB) qs[tid] = tid < nb ? q_g[k0 + tid] : -1;
-  __syncthreads();
-  for (int e = tid; e < NB * 64; e += 256) {
-    const int j = e >> 6, cc = e & 63;
-    const int64_t c = c0 + cc;
-    Rt[j][cc] = (j < nb && c < n) ? Min[(int64_t)qs[j] * n + c] : 0.0;
+  const int64_t kk = (n - kc < K) ? n - kc : K;
+  const int64_t ceb = ce < n ? ce : n;
+  const int64_t ct = tile_c0 + (int64_t)blockIdx.x * 64;
+  const int64_t rt = (int64_t)blockIdx.y * 64;
+  if (kk <= 0 || ct >= ceb || rt >= n) return;  // uniform for the workgroup
+  double* W = W_all + woff[bk];
+  const int32_t* pcol = pcol_all + rb0;
+  const double* G = g_stride > 0 ? G_all + (int64_t)bk * g_stride : G_all + (int64_t)NBO * (rb0 - rows[0]);
+  const int64_t lg = g_stride > 0 ? ldg : n;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i16 = lane & 15, kq = lane >> 4;
+  const int64_t ra = rt + 16 * wave + i16;  // A row of this lane
+  f64x4 acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  for (int64_t ks = 0; ks < kk; ks += 4) {
+    const int64_t k = ks + kq;
+    const bool k_ok = k < kk;
+    const double a = (k_ok && ra < n) ? W[ra * n + kc + k] : 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t c = ct + 16 * j + i16;
+      const double b = (k_ok && c < ceb) ? G[k * lg + (c - gc0)] : 0.0;
+      acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
+    }
   }
-  for (int e = tid; e < 32 * NB; e += 256) {
-    const int rr = e / NB, j = e - rr * NB;
-    const int64_t i = r0 + rr;
-    Xt[rr][j] = (i < n && j < nb) ? Mout[i * n + k0 + j] : 0.0;
-  }
-  const int tx = tid & 63, ty = tid >> 6;
-  const int64_t c = c0 + tx;
-  const bool col_ok = c < n && !(c >= k0 && c < k0 + nb);
-  double base[8];
 #pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    const int64_t i = r0 + ty + 4 * s;
-    base[s] = (col_ok && i < n) ? Min[i * n + c] : 0.0;  // issued before the barrier
-  }
-  __syncthreads();
-  if (!col_ok) return;
+  for (int j = 0; j < 4; ++j) {
+    const int64_t c = ct + 16 * j + i16;
+    if (c < cb || c >= ceb || (c >= sk0 && c < sk1)) continue;
 #pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    const int rr = ty + 4 * s;
-    const int64_t i = r0 + rr;
-    if (i < n) {
-      bool pivot_row = false;
-#pragma unroll
-      for (int j = 0; j < NB; ++j) pivot_row |= (qs[j] == i);
-      double acc = pivot_row ? 0.0 : base[s];
-#pragma unroll
-      for (int j = 0; j < NB; ++j) acc = fma(Xt[rr][j], Rt[j][tx], acc);
-      Mout[i * n + c] = acc;
+    for (int i = 0; i < 4; ++i) {
+      const int64_t r = rt + 16 * wave + 4 * i + kq;
+      if (r >= n) continue;
+      const int32_t u = pcol[r] - 1;
+      const bool zero = u >= p0 && u < p1;
+      const double old = W[r * n + c];
+      W[r * n + c] = (zero ? 0.0 : old) + acc[j][i];
     }
   }
 }
@@ -251,26 +286,36 @@ __global__ void block_export_kernel(int64_t n, const double* __restrict__ W, con
   }
 }
 
-template <int R, int NB>
-hipError_t run_blocked(hipStream_t s, const vk_level& L, double** a, double** b, int32_t* status) {
+template <int CTT, int R, int NB>
+hipError_t run_blocked(hipStream_t s, const vk_level& L, int32_t* status) {
+  static_assert(NBO % NB == 0 && NB <= VK_GJ_NBI_MAX, "inner panels must tile the outer block");
   const int nbk = (int)L.cb_rows.size() - 1;
   const int64_t n = L.cb_max;
-  const dim3 ugrid((unsigned)((n + 63) / 64), (unsigned)((n + 31) / 32), (unsigned)nbk);
-  for (int64_t k0 = 0; k0 < n; k0 += NB) {
-    block_panel_kernel<R, NB><<<nbk, CT, 0, s>>>(L.d_cb_rows, L.d_cb_woff, k0, *a, *b, L.cb_q, L.cb_used, status);
-    block_update_kernel<NB><<<ugrid, 256, 0, s>>>(L.d_cb_rows, L.d_cb_woff, k0, *a, *b, L.cb_q);
+  const unsigned row_tiles = (unsigned)((n + 63) / 64);
+  for (int64_t c0o = 0; c0o < n; c0o += NBO) {
+    for (int64_t k0 = c0o; k0 < c0o + NBO && k0 < n; k0 += NB) {
+      block_panel_kernel<CTT, R, NB><<<nbk, CTT, 0, s>>>(L.d_cb_rows, L.d_cb_woff, k0, c0o, L.cb_a, L.cb_q,
+                                                         L.cb_used, L.cb_gi, status);
+      // the same steps on the outer block's other columns, before and after the panel
+      if (n > NB)
+        gj_update_kernel<<<dim3(1, row_tiles, nbk), 256, 0, s>>>(
+            L.d_cb_rows, L.d_cb_woff, L.cb_a, L.cb_used, k0, NB, L.cb_gi, (int64_t)NB * NBO, NBO, c0o, c0o,
+            c0o + NBO, k0, k0 + NB, k0, k0 + NB, c0o);
+    }
+    gather_pivot_rows_kernel<<<dim3((unsigned)((n + 255) / 256 < 64 ? (n + 255) / 256 : 64), NBO, nbk), 256, 0, s>>>(
+        L.d_cb_rows, L.d_cb_woff, c0o, L.cb_a, L.cb_q, L.cb_go);
+    gj_update_kernel<<<dim3(row_tiles, row_tiles, nbk), 256, 0, s>>>(L.d_cb_rows, L.d_cb_woff, L.cb_a, L.cb_used,
+                                                                     c0o, NBO, L.cb_go, 0, 0, 0, 0, n, c0o,
+                                                                     c0o + NBO, c0o, c0o + NBO, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    double* t = *a;
-    *a = *b;
-    *b = t;
   }
   return hipSuccess;
 }
 
 }  // namespace
 
-int64_t vk_coarse_max_n() { return 4096; }
+int64_t vk_coarse_max_n() { return 9216; }
 
 hipError_t launch_block_invert(hipStream_t s, const vk_level& L, int32_t* status, double** result) {
   const int nbk = (int)L.cb_rows.size() - 1;
@@ -283,14 +328,14 @@ hipError_t launch_block_invert(hipStream_t s, const vk_level& L, int32_t* status
       nbk, L.d_cb_rows, L.d_cb_woff, L.J.row_ptr, L.J.col, L.J.val, L.cb_a, status);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = launch_fill_i32(s, L.J.n_rows, 0, L.cb_used)) != hipSuccess) return e;
-  double* a = L.cb_a;
-  double* b = L.cb_b;
-  // R rows x NB panel columns per thread: R * NB <= 64 doubles
-  const int64_t R = (L.cb_max + CT - 1) / CT;
-  if (R <= 4) e = run_blocked<4, 16>(s, L, &a, &b, status);
-  else if (R <= 8) e = run_blocked<8, 8>(s, L, &a, &b, status);
-  else e = run_blocked<16, 4>(s, L, &a, &b, status);
-  *result = a;
+  // panel rows per thread R, panel width NB: R * NB <= 64 doubles in registers (<= 36 at
+  // 1024 threads, whose waves may hold 128 registers each)
+  const int64_t m = L.cb_max;
+  if (m <= 1024) e = run_blocked<256, 4, 16>(s, L, status);
+  else if (m <= 2048) e = run_blocked<256, 8, 8>(s, L, status);
+  else if (m <= 4096) e = run_blocked<512, 8, 8>(s, L, status);
+  else if (m <= 8192) e = run_blocked<1024, 8, 4>(s, L, status);
+  else e = run_blocked<1024, 9, 4>(s, L, status);
   return e;
 }
 

@@ -18,6 +18,9 @@
 #define VK_LDS_SETUP_MAX_NK 88
 #define VK_MAX_NK 512
 #define VK_MAX_RESTART 64
+// blocked Gauss-Jordan of the directly solved blocks: outer block width, widest inner panel
+#define VK_GJ_NBO 64
+#define VK_GJ_NBI_MAX 16
 
 // ---- wavefront reductions through DPP (row shifts, then row broadcasts);
 // the result of lane 63 is returned to every lane ----
@@ -93,13 +96,14 @@ struct vk_level {
   double* b = nullptr;          // V-cycle right-hand side
   double* d = nullptr;          // V-cycle iterate
   double* r = nullptr;          // defect scratch
-  double* cb_a = nullptr;       // block Gauss-Jordan buffers (two, alternating)
-  double* cb_b = nullptr;
-  double* cb_W = nullptr;       // the one holding the eliminated blocks
+  double* cb_a = nullptr;       // the blocks, eliminated in place by Gauss-Jordan
+  double* cb_gi = nullptr;      // pivot rows' old values, inner panels (per block VK_GJ_NBI_MAX x VK_GJ_NBO)
+  double* cb_go = nullptr;      // pivot rows' old values, outer blocks (per block VK_GJ_NBO x n_b)
+  double* cb_W = nullptr;       // the eliminated blocks (= cb_a)
   int64_t* d_cb_rows = nullptr; // device copies of the block offsets
   int64_t* d_cb_woff = nullptr; // offset of each block's dense matrix
   int32_t* cb_q = nullptr;      // pivot rows (block-local), per block
-  int32_t* cb_used = nullptr;   // rows already used as pivots
+  int32_t* cb_used = nullptr;   // per row: 0, or 1 + the column it is the pivot of
 };
 
 struct vk_timing_rec {

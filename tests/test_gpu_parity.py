@@ -394,3 +394,35 @@ def test_autotuned_matches_oracle(vk):
     x = torch.empty(P.finest.n, dtype=torch.float64, device=DEV)
     S.vcycle(t(b), x, 2, 2)
     assert rel(x.cpu().numpy(), oracle.vcycle(H, b, 2, 2)) <= 1e-10
+
+
+def test_coarse_solve_3d_box_size(vk):
+    """The 3D box's coarsest level (25 x 2 x 2 hexahedra, dG(1), n = 8 450, the largest directly
+    solved block) on its own: the one-level V-cycle is the direct solve; it agrees with a sparse
+    LU solve and leaves a residual at rounding level."""
+    import time
+    import scipy.sparse.linalg as spla
+    from synth.assemble import assemble_jacobian
+    from synth.mesh import StructuredMesh
+    from synth.problems import Level, inflow_state
+    m = StructuredMesh((25, 2, 2), (2.5, 0.41, 0.41), 1)
+    V = inflow_state(m, 0.45, np.random.default_rng(1002))
+    J = assemble_jacobian(m, V, 1e-3, 0.01)
+    assert J.shape[0] == 8450
+    lv = Level(mesh=m, J=J, P=None, R=None, cell_dofs=m.cell_dofs(), colours=m.colours(), state=V)
+    S = vk.Solver([vk.upload_level(lv, DEV)])
+    S.vk_set_workspace("f64", 30, device=DEV)
+    _say("coarse 8450 setup")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.vanka_setup(0.7, "additive")
+    torch.cuda.synchronize()
+    _say(f"coarse 8450 setup {1e3 * (time.perf_counter() - t0):.1f} ms")
+    b = np.random.default_rng(7).standard_normal(J.shape[0])
+    x = torch.empty(J.shape[0], dtype=torch.float64, device=DEV)
+    S.vcycle(t(b), x, 0, 0)
+    xg = x.cpu().numpy()
+    xs = spla.spsolve(J.tocsc(), b)
+    assert np.linalg.norm(xg - xs) <= 1e-9 * np.linalg.norm(xs)
+    assert np.linalg.norm(J @ xg - b) <= 1e-11 * np.linalg.norm(b) * max(1.0, abs(J).max())
+    S.close()
