@@ -322,6 +322,7 @@ def main():
     ap.add_argument("--prec", default="f32", choices=["f64", "f32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64/BF16 comparison runs")
+    ap.add_argument("--compare-precs", default="f64,bf16", help="precisions of the comparison runs")
     ap.add_argument("--no-graphs", action="store_true", help="batch: launch Arnoldi steps eagerly")
     ap.add_argument("--epochs", type=int, default=40, help="learned guess: training epochs")
     args = ap.parse_args()
@@ -427,7 +428,7 @@ def main():
     S.close()
 
     if not args.no_compare:
-        for prec in [p for p in ("f64", "bf16") if p != args.prec]:
+        for prec in [p for p in args.compare_precs.split(",") if p and p != args.prec]:
             S2 = make(prec)
             S2.vanka_setup(0.7, "additive")
             S2.vk_autotune(10)

@@ -17,6 +17,10 @@ import scipy.sparse as sp
 
 from .mesh import StructuredMesh, hierarchy_shapes
 from .assemble import assemble_jacobian
+from .assemble_chunked import assemble_jacobian_chunked
+
+# element-matrix entries above which a level is assembled chunk by chunk straight into CSR
+CHUNKED_ASSEMBLY_ENTRIES = 2e7
 from .transfer import prolongation, inject_nodes
 
 H_CHANNEL = 0.41
@@ -97,7 +101,10 @@ def build_hierarchy(d, shape, lengths, levels, k, nu, tau, U, seed=0, noise=0.05
         states[l] = states[l + 1][:, inject_nodes(meshes[l], meshes[l + 1]), :]
     out = []
     for l, m in enumerate(meshes):
-        J = assemble_jacobian(m, states[l], nu, tau)
+        if m.n_cells * m.n_K ** 2 > CHUNKED_ASSEMBLY_ENTRIES:
+            J = assemble_jacobian_chunked(m, states[l], nu, tau)
+        else:
+            J = assemble_jacobian(m, states[l], nu, tau)
         if l > 0:
             P = prolongation(meshes[l - 1], m)
             R = P.T.tocsr()

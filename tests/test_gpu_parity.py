@@ -39,6 +39,8 @@ CASES = {
     "cfg0": ("channel2d_44x8_k1", {}),
     "ragged_k2": ("channel2d_44x8_k1", dict(shape=(10, 6), levels=2, k=2)),
     "k3": ("channel2d_44x8_k1", dict(shape=(12, 4), levels=2, k=3)),
+    # 3D box, Q2/P1disc hexahedra, dG(1): n_K = 170 (the box's patch width) on a small mesh
+    "box3d": ("box3d_100x16x16_k1", dict(shape=(8, 4, 4), levels=2)),
 }
 
 _cache = {}
