@@ -622,6 +622,181 @@ __global__ __launch_bounds__(64 * RowCfg<N>::W) void patch_setup_rows_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Wide patches (n_K up to 8 x 22 = 176, e.g. 170 for the 3D Q2/P1disc dG(1)
+// patch): the FP64 matrix does not fit one row per lane, so it is spread over
+// a 512-thread workgroup in registers: wavefront w holds the columns
+// [w CW, (w + 1) CW), lane l the rows l, l + 64, l + 128.  Step k of the same
+// implicit-pivoting Gauss-Jordan elimination: the wavefront owning column k
+// finds the pivot (DPP reductions) and publishes the column through LDS (two
+// buffers, so one barrier per step suffices); every wavefront reads the pivot
+// row's values of its own columns from the owning lane (readlane) and updates.
+// ---------------------------------------------------------------------------
+template <int N> struct WideCfg {
+  static constexpr int NW = 8;                     // wavefronts per cell
+  static constexpr int CW = (N + NW - 1) / NW;     // columns per wavefront
+  static constexpr int R = (N + 63) / 64;          // rows per lane
+};
+
+__device__ inline double readlane_f64(double v, int lane) {
+  const int2 a = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_readlane(a.x, lane);
+  r.y = __builtin_amdgcn_readlane(a.y, lane);
+  return __builtin_bit_cast(double, r);
+}
+
+template <int P, int N>
+__global__ __launch_bounds__(64 * WideCfg<N>::NW) void patch_setup_wide_kernel(
+    const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const double* __restrict__ val,
+    const int32_t* __restrict__ cell_dofs, void* inv_out, int32_t ld, int64_t cell_stride, int32_t* status) {
+  constexpr int NW = WideCfg<N>::NW, CW = WideCfg<N>::CW, R = WideCfg<N>::R, NT = 64 * NW;
+  static_assert(NW * CW >= N && R * 64 >= N && R <= 4, "wide patch layout");
+  __shared__ int sdof[N], skey[N], sloc[N], qs[N], kinv[N];
+  __shared__ double stage[64 * N];
+  __shared__ double fcol[2][64 * R];
+  __shared__ int piv_s[2];
+  __shared__ double pabs_s[2];
+  const int K = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < N; i += NT) {
+    sdof[i] = cell_dofs[(int64_t)K * N + i];
+    skey[i] = 0x7fffffff;
+    sloc[i] = 0;
+    qs[i] = i;      // overwritten by every successful step; keeps the output in range otherwise
+    kinv[i] = i;
+  }
+  __syncthreads();
+  for (int i = tid; i < N; i += NT) {
+    const int v = sdof[i];
+    int rank = 0;
+    for (int j = 0; j < N; ++j) rank += (sdof[j] < v) ? 1 : 0;
+    skey[rank] = v;
+    sloc[rank] = i;
+  }
+  // gather: rows in chunks of 64 through LDS, then each lane keeps its row's columns
+  double Pm[R][CW];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    __syncthreads();
+    for (int e = tid; e < 64 * N; e += NT) stage[e] = 0.0;
+    __syncthreads();
+    {
+      constexpr int LPR = NT / 64;
+      const int rr = tid / LPR, sub = tid - rr * LPR;
+      const int i = r * 64 + rr;
+      if (i < N) {
+        const int64_t grow = sdof[i];
+        const int64_t e0 = row_ptr[grow], e1 = row_ptr[grow + 1];
+#pragma unroll 4
+        for (int64_t e = e0 + sub; e < e1; e += LPR) {
+          const int c = col[e];
+          const double v = val[e];
+          int lo = 0, hi = N;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (skey[mid] < c) lo = mid + 1; else hi = mid;
+          }
+          if (lo < N && skey[lo] == c) stage[rr * N + sloc[lo]] = v;
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CW; ++c) {
+      const int j = wave * CW + c;
+      Pm[r][c] = (r * 64 + lane < N && j < N) ? stage[lane * N + j] : 0.0;
+    }
+  }
+  uint32_t used = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (r * 64 + lane >= N) used |= 1u << r;
+  bool singular = false;
+#pragma unroll 1
+  for (int wk = 0; wk < NW; ++wk) {
+#pragma unroll
+    for (int ck = 0; ck < CW; ++ck) {
+      const int k = wk * CW + ck;
+      if (k < N) {  // uniform
+        const int buf = k & 1;
+        if (wave == wk) {
+          double best = -1.0;
+          int bi = 0x7fffffff;
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const double av = fabs(Pm[r][ck]);
+            if (!((used >> r) & 1u) && av > best) { best = av; bi = r * 64 + lane; }
+          }
+          const double m = wave_max(best);
+          const int wi = wave_min((best == m && bi != 0x7fffffff) ? bi : 0x7fffffff);
+#pragma unroll
+          for (int r = 0; r < R; ++r) fcol[buf][r * 64 + lane] = Pm[r][ck];
+          if (lane == 0) {
+            piv_s[buf] = wi;
+            pabs_s[buf] = m;
+          }
+        }
+        __syncthreads();
+        const int p = __builtin_amdgcn_readfirstlane(piv_s[buf]);
+        const double pa = pabs_s[buf];
+        const bool bad = p >= N || !(pa > 0.0) || !isfinite(pa);  // uniform
+        if (bad) {
+          singular = true;
+        } else {
+          const double inv = 1.0 / fcol[buf][p];
+          const int pl = p & 63, ps = p >> 6;
+          double f[R], keep[R];
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const bool piv = (r * 64 + lane) == p;
+            f[r] = piv ? -1.0 : fcol[buf][r * 64 + lane];
+            keep[r] = piv ? 0.0 : 1.0;
+          }
+          const bool own = wave == wk;
+#pragma unroll
+          for (int c = 0; c < CW; ++c) {
+            double pv = Pm[0][c];
+#pragma unroll
+            for (int r = 1; r < R; ++r) pv = (ps == r) ? Pm[r][c] : pv;
+            pv = readlane_f64(pv, pl);
+            const bool kc = own && (c == ck);
+            const double pc = kc ? inv : pv * inv;
+#pragma unroll
+            for (int r = 0; r < R; ++r) Pm[r][c] = kc ? -f[r] * pc : fma(-f[r], pc, keep[r] * Pm[r][c]);
+          }
+          if (pl == lane) used |= 1u << ps;
+          if (tid == 0) {
+            qs[k] = p;
+            kinv[p] = k;
+          }
+        }
+      }
+    }
+  }
+  if (singular && tid == 0) atomicMin(status, K);
+  __syncthreads();
+  using S = typename PT<P>::S;
+  S* out = reinterpret_cast<S*>(inv_out) + (int64_t)K * cell_stride;
+  // J_K^{-1}[kinv[i]][q_j] = W[i][j]; column-major with leading dimension ld
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = r * 64 + lane;
+    if (i < N) {
+      const int ki = kinv[i];
+#pragma unroll
+      for (int c = 0; c < CW; ++c) {
+        const int j = wave * CW + c;
+        if (j < N) out[(int64_t)qs[j] * ld + ki] = store_cvt<P>(Pm[r][c]);
+      }
+    }
+  }
+  for (int e = tid; e < N * (ld - N); e += NT) {
+    const int c = e / (ld - N), i = N + (e - c * (ld - N));
+    out[(int64_t)c * ld + i] = store_cvt<P>(0.0);
+  }
+}
+
 template <int P>
 hipError_t setup_rows(hipStream_t s, const vk_csr& J, const vk_group& L, int32_t* status, bool* handled) {
   *handled = true;
@@ -635,6 +810,10 @@ hipError_t setup_rows(hipStream_t s, const vk_csr& J, const vk_group& L, int32_t
     VK_ROWS_CASE(63)
     VK_ROWS_CASE(84)
 #undef VK_ROWS_CASE
+    case 170:
+      patch_setup_wide_kernel<P, 170><<<L.n_cells, 64 * WideCfg<170>::NW, 0, s>>>(
+          J.row_ptr, J.col, J.val, L.cell_dofs, L.inv, L.ld, L.cell_stride, status);
+      return hipGetLastError();
     default:
       *handled = false;
       return hipSuccess;

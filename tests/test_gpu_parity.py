@@ -354,7 +354,7 @@ def test_sweep_variants(vk, variant, prec):
         assert rel(d.cpu().numpy(), Href.smooth(l, b, d0, 2)) <= tol
 
 
-@pytest.mark.parametrize("case", ["cfg0", "ragged_k2", "k3"])
+@pytest.mark.parametrize("case", ["cfg0", "ragged_k2", "k3", "box3d"])
 def test_setup_variants_agree(vk, case):
     """The register-resident and the LDS Gauss-Jordan kernels give the same inverses."""
     P, H = problem(case)
