@@ -305,6 +305,52 @@ def run_learned(args, torch, vk, dev):
     print(json.dumps(out), flush=True)
 
 
+def run_pmc_probe(args, torch, vk, dev):
+    """Short fixed workload for hardware-counter runs (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE):
+    three copies of a 512 MiB FP64 buffer (the calibration kernel: 512 MiB read and written per
+    launch), then 20 finest-level additive sweeps of the default workload with the same setup as
+    the timed benchmark (the dominant kernel: patch_gemv over all finest cells)."""
+    from synth import build_problem
+    P = build_problem(args.config)
+    S = vk.Solver([vk.upload_level(L, dev) for L in P.levels])
+    S.vk_set_workspace(args.prec, 30, device=dev)
+    S.vanka_setup(0.7, "additive")
+    S.vk_autotune(10)
+    n = (512 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    l = len(P.levels) - 1
+    b = torch.from_numpy(P.b).to(dev)
+    d = torch.zeros_like(b)
+    S.vanka_smooth(l, b, d, 20, d_is_zero=False)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": args.config, "copy_bytes_per_launch": 2 * n * 8, "copy_launches": 3,
+                      "patch_gemv_launches": 20, "patch_gemv_bytes_per_launch": patch_gemv_bytes(P.finest, args.prec),
+                      "finest_cells": P.finest.mesh.n_cells}), flush=True)
+    S.close()
+
+
+def pmc_traffic(prec, config):
+    """HBM bytes per finest patch_gemv launch from the committed counter summary, scaled by the
+    copy-kernel calibration; None if the summary is missing or the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"pmc_patch_gemv_{config}_{prec}.json")
+    src = os.path.join(ROOT, "paper_2210_02690_amd", "csrc", "patch.hip")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("patch_hip_sha256") != digest:
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
 def _threads():
     try:
         from threadpoolctl import threadpool_info
@@ -325,6 +371,7 @@ def main():
     ap.add_argument("--compare-precs", default="f64,bf16", help="precisions of the comparison runs")
     ap.add_argument("--no-graphs", action="store_true", help="batch: launch Arnoldi steps eagerly")
     ap.add_argument("--epochs", type=int, default=40, help="learned guess: training epochs")
+    ap.add_argument("--pmc-probe", action="store_true", help="short fixed workload for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for {args.gpus})",
@@ -340,6 +387,8 @@ def main():
         return run_batch(args, torch, vk, dev)
     if args.config == "learned_guess_88x16":
         return run_learned(args, torch, vk, dev)
+    if args.pmc_probe:
+        return run_pmc_probe(args, torch, vk, dev)
     restart, max_iter, nu = 30, 300, (2, 2)
     t0 = time.perf_counter()
     P = build_problem(args.config)
@@ -401,7 +450,7 @@ def main():
         "gmres_iterations": its_h, "gmres_true_rel_residual": rel_h,
         "gmres_ms_to_1e-8": gmres_ms, "setup_ms": setup_ms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": pmc_traffic(args.prec, args.config),
                      "kernel": "patch_gemv (finest level, all cells per launch)",
                      "bytes_per_launch": bytes_launch, "avg_launch_ms": avg_ms, "launches": n_apply},
         "finest_level_kernels_avg_ms": {"patch_gemv": avg_ms, "dof_gather": ms_gather / max(n_gather, 1),
