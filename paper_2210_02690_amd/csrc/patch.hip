@@ -843,7 +843,7 @@ __global__ __launch_bounds__(VK_NT) void patch_gemv_kernel(const void* __restric
   A* part = srk + cpb * n_K;
   const int tpc = VK_NT / cpb;
   const int slot = threadIdx.x / tpc, t = threadIdx.x - slot * tpc;
-  const int64_t K = (int64_t)blockIdx.x * cpb + slot;
+  const int64_t K = (int64_t)xcd_block(blockIdx.x, gridDim.x) * cpb + slot;
   const bool valid = K < n_cells;
   for (int j = t; j < n_K; j += tpc) srk[slot * n_K + j] = valid ? (A)r[cell_dofs[K * n_K + j]] : (A)0;
   __syncthreads();
@@ -884,7 +884,7 @@ template <typename TY>
 __global__ __launch_bounds__(256) void dof_gather_kernel(int64_t n, const int32_t* __restrict__ off,
                                                          const int32_t* __restrict__ list,
                                                          const TY* __restrict__ Y, double omega, double* d) {
-  const int64_t mu = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t mu = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (mu >= n) return;
   const int32_t e0 = off[mu], e1 = off[mu + 1];
   double z = 0.0;

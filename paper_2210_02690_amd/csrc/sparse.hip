@@ -11,7 +11,7 @@ __global__ __launch_bounds__(256) void spmv_kernel(int64_t n_rows, const int64_t
                                                    const double* __restrict__ val,
                                                    const double* __restrict__ x, double alpha, double beta,
                                                    const double* z, double* y) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gid = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int64_t row = gid / LPR;
   const int lane = threadIdx.x & (LPR - 1);
   double s0 = 0.0, s1 = 0.0;

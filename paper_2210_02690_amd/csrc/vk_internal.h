@@ -33,6 +33,15 @@ __device__ inline double dpp_move(double v, double ident) {
   return __builtin_bit_cast(double, r);
 }
 
+// Workgroup i of a launch runs on XCD i mod 8 (round-robin dispatch over the 8 dies, each with
+// its own L2).  xcd_block(i, n) gives XCD x the contiguous block range [x q + min(x, r), ...)
+// (q = n / 8, r = n mod 8; a bijection of [0, n)), so neighbouring blocks, which share the cache
+// lines at their boundaries, sit behind the same L2.
+__device__ inline unsigned xcd_block(unsigned b, unsigned n) {
+  const unsigned q = n >> 3, r = n & 7u, x = b & 7u, i = b >> 3;
+  return x * q + (x < r ? x : r) + i;
+}
+
 // maximum over the 64 lanes, returned to every lane (NaN lanes are ignored)
 __device__ inline double wave_max(double v) {
   const double id = -__builtin_inf();
