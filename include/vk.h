@@ -118,7 +118,7 @@ typedef struct {
 
 /* General form of vk_set_level: n_groups cell groups (levels >= 1) and
  * n_blocks directly solved diagonal blocks, rows [block_rows[b],
- * block_rows[b+1]) (host array, n_blocks + 1 entries, at most 4096 rows per
+ * block_rows[b+1]) (host array, n_blocks + 1 entries, at most 9216 rows per
  * block).  A block must not be coupled to rows outside it (checked at setup).
  * vk_set_level(l = 0) is one block covering the level; vk_set_level(l >= 1) one
  * group and no blocks. */
