@@ -10,9 +10,10 @@
  *   - The caller owns every array it passes (level matrices, transfer
  *     matrices, cell maps, workspace, vectors) and keeps them alive and
  *     unchanged until vk_destroy; the context stores the pointers, not copies.
- *   - Apart from one 4 KiB status block allocated by vk_create, the library
- *     allocates no device memory: all scratch lives in the caller-provided
- *     workspace (vk_workspace_bytes / vk_set_workspace).
+ *   - Apart from one 4 KiB status block and a 64 KiB pinned host staging
+ *     buffer for small reads (both allocated by vk_create), the library
+ *     allocates no memory: all scratch lives in the caller-provided workspace
+ *     (vk_workspace_bytes / vk_set_workspace).
  *   - All work is enqueued on the stream given to vk_create.  Calls are
  *     asynchronous except those returning host outputs (vanka_setup's singular
  *     check, gmres_solve's counts), which synchronise that stream.
@@ -157,9 +158,14 @@ vk_status vk_set_workspace(vk_ctx* ctx, void* dev, size_t bytes, vk_prec prec, i
  * and store A_K in `prec`; compute 1/p_mu, p_mu = number of cells containing
  * DoF mu (Eq. 3.5b); and form the FP64 inverse of J_0 for the coarsest-level
  * direct solve.  omega is the under-relaxation of Eq. 3.4 (the paper uses 0.7).
- * On a zero pivot returns VK_ERR_SINGULAR with *bad_level / *bad_cell (host,
- * may be NULL) naming the first failing level and cell (cell -1 = the coarse
- * matrix).  Synchronises the stream. */
+ * On a zero pivot in a patch returns VK_ERR_SINGULAR with *bad_level /
+ * *bad_cell (host, may be NULL) naming the first failing level and cell.
+ * Synchronises the stream for the patch inversions only: the inversion of the
+ * directly solved blocks (the coarse matrix) keeps running on an internal
+ * stream and overlaps the start of the next solve; the first call that applies
+ * a block (vcycle, gmres_solve, gmres_solve_batched, vk_get_coarse_inverse)
+ * orders itself after it and reports a singular or coupled block there
+ * (VK_ERR_SINGULAR / VK_ERR_ARG, after which setup must run again). */
 vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_level, int32_t* bad_cell);
 
 /* `sweeps` Vanka iterations on level l >= 1 for J_l d = b (Eq. 3.5, or the

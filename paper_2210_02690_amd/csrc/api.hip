@@ -238,10 +238,13 @@ vk_status smooth(vk_ctx* ctx, int l, const double* b, double* d, int32_t sweeps,
   return VK_OK;
 }
 
+vk_status coarse_wait(vk_ctx* ctx, bool check_now);
+
 vk_status vcycle_level(vk_ctx* ctx, int l, const double* b, double* x, int32_t nu1, int32_t nu2) {
   hipStream_t s = ctx->stream;
   vk_level& L = ctx->lv[l];
   if (l == 0) {
+    if (ctx->coarse_pending) VK_CHECK(coarse_wait(ctx, false));  // only now wait for the inversion
     VK_TRY(launch_block_apply(s, L, b, x));
     return VK_OK;
   }
@@ -249,6 +252,7 @@ vk_status vcycle_level(vk_ctx* ctx, int l, const double* b, double* x, int32_t n
   if (nu1 > 0) VK_CHECK(smooth(ctx, l, b, x, nu1, true));
   else VK_TRY(launch_fill(s, L.J.n_rows, 0.0, x));
   // systems whose coarsest level is this one are solved directly (their rows carry no cells)
+  if (ctx->coarse_pending && L.cb_rows.size() > 1) VK_CHECK(coarse_wait(ctx, false));
   VK_TRY(launch_block_apply(s, L, b, x));
   VK_TRY(launch_spmv(s, L.J, L.lpr_J, -1.0, x, 1.0, b, L.r));
   VK_TRY(launch_spmv(s, L.R, L.lpr_R, 1.0, L.r, 0.0, nullptr, C.b));
@@ -258,10 +262,34 @@ vk_status vcycle_level(vk_ctx* ctx, int l, const double* b, double* x, int32_t n
   return VK_OK;
 }
 
-vk_status read_scalars(vk_ctx* ctx, const double* dev, int count, double* out) {
-  VK_TRY(hipMemcpyAsync(out, dev, sizeof(double) * count, hipMemcpyDeviceToHost, ctx->stream));
+// Device-to-host copy on the context stream through the pinned staging buffer; synchronises
+// the context stream only.
+vk_status to_host(vk_ctx* ctx, void* dst, const void* src, size_t bytes) {
+  if (bytes <= ctx->pinned_bytes) {
+    VK_TRY(hipMemcpyAsync(ctx->pinned, src, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    VK_TRY(hipStreamSynchronize(ctx->stream));
+    std::memcpy(dst, ctx->pinned, bytes);
+  } else {
+    VK_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    VK_TRY(hipStreamSynchronize(ctx->stream));
+  }
+  return VK_OK;
+}
+
+// Host-to-device copy on the context stream; synchronises the context stream.
+vk_status to_dev(vk_ctx* ctx, void* dst, const void* src, size_t bytes) {
+  if (bytes <= ctx->pinned_bytes) {
+    std::memcpy(ctx->pinned, src, bytes);
+    VK_TRY(hipMemcpyAsync(dst, ctx->pinned, bytes, hipMemcpyHostToDevice, ctx->stream));
+  } else {
+    VK_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream));
+  }
   VK_TRY(hipStreamSynchronize(ctx->stream));
   return VK_OK;
+}
+
+vk_status read_scalars(vk_ctx* ctx, const double* dev, int count, double* out) {
+  return to_host(ctx, out, dev, sizeof(double) * count);
 }
 
 // Runs enqueue() on ctx->stream, or, with graphs on, replays the graph held in `slot` when it was
@@ -271,6 +299,7 @@ vk_status read_scalars(vk_ctx* ctx, const double* dev, int count, double* out) {
 template <class F>
 vk_status replay(vk_ctx* ctx, size_t slot, const int64_t (&key)[6], F&& enqueue) {
   if (!ctx->graphs || ctx->timing) return enqueue();
+  VK_CHECK(coarse_wait(ctx, false));  // outside the recording: an ordinary wait on the caller's stream
   if (ctx->gslots.size() <= slot) ctx->gslots.resize(slot + 1);
   vk_ctx::graph_slot& g = ctx->gslots[slot];
   const bool hit = g.exec && g.gen == ctx->gen && std::equal(key, key + 6, g.key);
@@ -307,6 +336,37 @@ vk_status replay(vk_ctx* ctx, size_t slot, const int64_t (&key)[6], F&& enqueue)
   return VK_OK;
 }
 
+// Make the context stream wait for the block inversions of the last setup (no host wait).
+// With check_now the stream is synchronised and their status words are checked at once.
+vk_status coarse_check(vk_ctx* ctx);
+vk_status coarse_wait(vk_ctx* ctx, bool check_now) {
+  if (ctx->coarse_pending) {
+    VK_TRY(hipStreamWaitEvent(ctx->stream, ctx->join_ev, 0));
+    ctx->coarse_pending = false;
+    ctx->coarse_check_due = true;
+  }
+  if (check_now) return coarse_check(ctx);
+  return VK_OK;
+}
+
+// Status of the block inversions: [0] pivot failure, [1] coupling outside a block.  Call
+// after coarse_wait; synchronises the stream.
+vk_status coarse_check(vk_ctx* ctx) {
+  if (!ctx->coarse_check_due) return VK_OK;
+  int32_t st[2];
+  VK_CHECK(to_host(ctx, st, ctx->status, sizeof(st)));
+  ctx->coarse_check_due = false;
+  if (st[1] != 0) {
+    ctx->setup_done = false;
+    return fail(ctx, VK_ERR_ARG, "a directly solved block is coupled to rows outside it");
+  }
+  if (st[0] != INT_MAX) {
+    ctx->setup_done = false;
+    return fail(ctx, VK_ERR_SINGULAR, "a directly solved (coarsest-level) block is singular (zero pivot)");
+  }
+  return VK_OK;
+}
+
 char g_create_err[256] = "";
 
 vk_status create_fail(vk_status st, const char* msg) {
@@ -335,6 +395,8 @@ vk_status vk_create(vk_ctx** out, int32_t n_levels, void* hip_stream) {
   ctx->lv.resize(n_levels);
   ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
   hipError_t e = hipMalloc(&ctx->status, 4096);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ctx->pinned), 65536, hipHostMallocDefault);
+  if (e == hipSuccess) ctx->pinned_bytes = 65536;
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming);
@@ -343,6 +405,7 @@ vk_status vk_create(vk_ctx** out, int32_t n_levels, void* hip_stream) {
     if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
     if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->status) (void)hipFree(ctx->status);
     delete ctx;
     char buf[256];
@@ -360,11 +423,13 @@ void vk_destroy(vk_ctx* ctx) {
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
   for (vk_ctx::graph_slot& g : ctx->gslots)
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
+
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
   if (ctx->side) (void)hipStreamSynchronize(ctx->side);
   if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
   if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
   if (ctx->side) (void)hipStreamDestroy(ctx->side);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->status) (void)hipFree(ctx->status);
   delete ctx;
 }
@@ -376,6 +441,9 @@ vk_status vk_set_level_groups(vk_ctx* ctx, int32_t l, const vk_csr* J, const vk_
                               const int64_t* block_rows) {
   if (!ctx) return VK_ERR_ARG;
   ++ctx->gen;
+  if (ctx->side) (void)hipStreamSynchronize(ctx->side);  // block inversions still reading the old setup
+  ctx->coarse_pending = false;
+  ctx->coarse_check_due = false;
   if (l < 0 || l >= ctx->n_levels) return fail(ctx, VK_ERR_ARG, "level index out of range");
   if (!csr_ok(J) || J->n_rows != J->n_cols || J->n_rows == 0)
     return fail(ctx, VK_ERR_ARG, "J must be a non-empty square CSR matrix with valid pointers");
@@ -449,8 +517,7 @@ vk_status vk_set_level_groups(vk_ctx* ctx, int32_t l, const vk_csr* J, const vk_
                                    ctx->status + 1000));
   }
   int32_t flag = 0;
-  VK_TRY(hipMemcpyAsync(&flag, ctx->status + 1000, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  VK_TRY(hipStreamSynchronize(s));
+  VK_CHECK(to_host(ctx, &flag, ctx->status + 1000, sizeof(int32_t)));
   if (flag != 0) {
     char buf[256];
     snprintf(buf, sizeof(buf),
@@ -517,6 +584,9 @@ size_t vk_workspace_bytes(const vk_ctx* cctx, vk_prec prec, int32_t restart) {
 vk_status vk_set_workspace(vk_ctx* ctx, void* dev, size_t bytes, vk_prec prec, int32_t restart) {
   if (!ctx) return VK_ERR_ARG;
   ++ctx->gen;
+  if (ctx->side) (void)hipStreamSynchronize(ctx->side);  // block inversions still reading the old setup
+  ctx->coarse_pending = false;
+  ctx->coarse_check_due = false;
   if (prec != VK_F64 && prec != VK_F32 && prec != VK_BF16) return fail(ctx, VK_ERR_ARG, "unknown precision");
   if (restart < 1 || restart > VK_MAX_RESTART) return fail(ctx, VK_ERR_ARG, "restart must be in [1, 64]");
   std::string why;
@@ -560,6 +630,9 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
   if (!(omega > 0.0) || !std::isfinite(omega)) return fail(ctx, VK_ERR_ARG, "omega must be positive");
   if (mode != VK_ADDITIVE && mode != VK_MULT_COLOURED) return fail(ctx, VK_ERR_ARG, "unknown smoother mode");
   ctx->setup_done = false;
+  // the previous setup's block inversions (and their status words) come before this one's
+  VK_CHECK(coarse_wait(ctx, false));
+  ctx->coarse_check_due = false;
   // recorded graphs stay valid across setups unless omega, the mode or where an inverse lives changes
   if (omega != ctx->omega || mode != ctx->mode) ++ctx->gen;
   ctx->omega = omega;
@@ -575,13 +648,6 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
   // stream while the patch inversions fill the rest of the GPU
   VK_TRY(hipEventRecord(ctx->fork_ev, s));
   VK_TRY(hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0));
-  for (int l = 0; l < ctx->n_levels; ++l) {
-    vk_level& L = ctx->lv[l];
-    if (L.cb_rows.size() > 1) VK_TRY(launch_block_invert(ctx->side, L, ctx->status, &L.cb_W));
-  }
-  VK_TRY(hipEventRecord(ctx->join_ev, ctx->side));
-  for (int l = 0; l < ctx->n_levels; ++l)
-    if (ctx->lv[l].cb_W != old_W[l]) ++ctx->gen;
   if (!ctx->maps_ready) {
     // multiplicities and DoF -> (cell, local) lists depend on the mesh only
     for (int l = 1; l < ctx->n_levels; ++l) {
@@ -603,22 +669,26 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
         VK_TRY(launch_patch_setup(s, L.J, G, ctx->prec, ctx->big_scratch, ctx->big_chunk, ctx->status + 64 + l));
     }
   }
-  VK_TRY(hipStreamWaitEvent(s, ctx->join_ev, 0));
-  int32_t st[128];
-  VK_TRY(hipMemcpyAsync(st, ctx->status, sizeof(int32_t) * 128, hipMemcpyDeviceToHost, s));
-  VK_TRY(hipStreamSynchronize(s));
-  if (st[1] != 0) return fail(ctx, VK_ERR_ARG, "a directly solved block is coupled to rows outside it");
-  if (st[0] != INT_MAX) {
-    if (bad_level) *bad_level = 0;
-    if (bad_cell) *bad_cell = -1;
-    return fail(ctx, VK_ERR_SINGULAR, "a directly solved (coarsest-level) block is singular (zero pivot)");
+  // Block inversions on the side stream, concurrent with the patch inversions (enqueued after
+  // them, so the host's launch work does not hold the patch kernels back).
+  for (int l = 0; l < ctx->n_levels; ++l) {
+    vk_level& L = ctx->lv[l];
+    if (L.cb_rows.size() > 1) VK_TRY(launch_block_invert(ctx->side, L, ctx->status, &L.cb_W));
   }
+  VK_TRY(hipEventRecord(ctx->join_ev, ctx->side));
+  for (int l = 0; l < ctx->n_levels; ++l)
+    if (ctx->lv[l].cb_W != old_W[l]) ++ctx->gen;
+  // the block inversions keep running on the side stream: the first solve waits for them
+  ctx->coarse_pending = true;
+  ctx->coarse_check_due = false;
+  int32_t st[64];
+  VK_CHECK(to_host(ctx, st, ctx->status + 64, sizeof(st)));
   for (int l = 1; l < ctx->n_levels; ++l) {
-    if (st[64 + l] != INT_MAX) {
+    if (st[l] != INT_MAX) {
       if (bad_level) *bad_level = l;
-      if (bad_cell) *bad_cell = st[64 + l];
+      if (bad_cell) *bad_cell = st[l];
       char buf[128];
-      snprintf(buf, sizeof(buf), "patch matrix of cell %d on level %d is singular (zero pivot)", st[64 + l], l);
+      snprintf(buf, sizeof(buf), "patch matrix of cell %d on level %d is singular (zero pivot)", st[l], l);
       return fail(ctx, VK_ERR_SINGULAR, buf);
     }
   }
@@ -645,6 +715,7 @@ vk_status vcycle(vk_ctx* ctx, const double* b, double* x, int32_t nu_pre, int32_
   VK_CHECK(ready(ctx));
   if (!b || !x || b == x) return fail(ctx, VK_ERR_ARG, "b and x must be distinct non-null vectors");
   if (nu_pre < 0 || nu_post < 0) return fail(ctx, VK_ERR_ARG, "negative sweep count");
+  VK_CHECK(coarse_wait(ctx, true));
   const int64_t key[6] = {(int64_t)(uintptr_t)b, (int64_t)(uintptr_t)x, nu_pre, nu_post, 0, 0};
   return replay(ctx, 0, key, [&]() { return vcycle_level(ctx, ctx->n_levels - 1, b, x, nu_pre, nu_post); });
 }
@@ -722,6 +793,7 @@ vk_status gmres_solve(vk_ctx* ctx, const double* b, double* x, int32_t restart, 
       const int64_t key[6] = {j, ldh, nu_pre, nu_post, 0, 0};
       VK_CHECK(replay(ctx, 1 + (size_t)j, key, step));
       VK_CHECK(read_scalars(ctx, sc + 2, 2, hb));
+      VK_CHECK(coarse_check(ctx));
       ++its;
       jn = j + 1;
       if (history) history[its] = hb[0];
@@ -771,24 +843,21 @@ vk_status gmres_solve_batched(vk_ctx* ctx, const double* b, double* x, int32_t r
   std::vector<double> hb(ns);
   std::vector<int32_t> hi(ns);
   VK_TRY(launch_seg_dot(s, ns, seg, max_len, b, b, ctx->partial, ctx->n_partial, bnorm, true));
-  VK_TRY(hipMemcpyAsync(hb.data(), bnorm, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
-  VK_TRY(hipStreamSynchronize(s));
+  VK_CHECK(to_host(ctx, hb.data(), bnorm, sizeof(double) * ns));
   std::vector<double> tl(ns), bn(hb);
   for (int i = 0; i < ns; ++i) {
     if (!std::isfinite(bn[i])) return fail(ctx, VK_ERR_ARG, "right-hand side is not finite");
     // b_i = 0: x_i = 0 is exact; an infinite tolerance keeps the segment inactive
     tl[i] = bn[i] == 0.0 ? __builtin_inf() : std::fmax(rtol * bn[i], atol);
   }
-  VK_TRY(hipMemcpyAsync(tol, tl.data(), sizeof(double) * ns, hipMemcpyHostToDevice, s));
+  VK_CHECK(to_dev(ctx, tol, tl.data(), sizeof(double) * ns));
   VK_TRY(launch_fill_i32(s, ns, 0, its));
-  VK_TRY(hipStreamSynchronize(s));  // tl must outlive the copy
   for (;;) {
     double* V0 = ctx->V;
     VK_TRY(launch_spmv(s, F.J, F.lpr_J, -1.0, x, 1.0, b, V0));
     VK_TRY(launch_seg_dot(s, ns, seg, max_len, V0, V0, ctx->partial, ctx->n_partial, beta, true));
     VK_TRY(launch_seg_init(s, ns, m, ctx->H, ctx->g, beta, tol, its, max_iter, active, jn));
-    VK_TRY(hipMemcpyAsync(hi.data(), active, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, s));
-    VK_TRY(hipStreamSynchronize(s));
+    VK_CHECK(to_host(ctx, hi.data(), active, sizeof(int32_t) * ns));
     int n_active = 0;
     for (int i = 0; i < ns; ++i) n_active += hi[i];
     if (n_active == 0) break;
@@ -819,8 +888,8 @@ vk_status gmres_solve_batched(vk_ctx* ctx, const double* b, double* x, int32_t r
       const int64_t key[6] = {j, m, nu_pre, nu_post, max_iter, 0};
       VK_CHECK(replay(ctx, 1 + (size_t)ctx->restart + (size_t)j, key, step));
       j_end = j + 1;
-      VK_TRY(hipMemcpyAsync(hi.data(), active, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, s));
-      VK_TRY(hipStreamSynchronize(s));
+      VK_CHECK(to_host(ctx, hi.data(), active, sizeof(int32_t) * ns));
+      VK_CHECK(coarse_check(ctx));
       n_active = 0;
       for (int i = 0; i < ns; ++i) n_active += hi[i];
       if (n_active == 0) break;
@@ -831,9 +900,8 @@ vk_status gmres_solve_batched(vk_ctx* ctx, const double* b, double* x, int32_t r
   // final true residuals
   VK_TRY(launch_spmv(s, F.J, F.lpr_J, -1.0, x, 1.0, b, ctx->V));
   VK_TRY(launch_seg_dot(s, ns, seg, max_len, ctx->V, ctx->V, ctx->partial, ctx->n_partial, beta, true));
-  VK_TRY(hipMemcpyAsync(hb.data(), beta, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
-  VK_TRY(hipMemcpyAsync(iters, its, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, s));
-  VK_TRY(hipStreamSynchronize(s));
+  VK_CHECK(to_host(ctx, hb.data(), beta, sizeof(double) * ns));
+  VK_CHECK(to_host(ctx, iters, its, sizeof(int32_t) * ns));
   int conv = 1;
   for (int i = 0; i < ns; ++i) {
     true_rel_res[i] = bn[i] > 0.0 ? hb[i] / bn[i] : 0.0;
@@ -867,6 +935,7 @@ vk_status vk_get_patch_inverses(vk_ctx* ctx, int32_t l, int32_t cell0, int32_t n
 vk_status vk_get_coarse_inverse(vk_ctx* ctx, double* out) {
   VK_CHECK(ready(ctx));
   if (!out) return fail(ctx, VK_ERR_ARG, "null output");
+  VK_CHECK(coarse_wait(ctx, true));
   VK_TRY(launch_block_export(ctx->stream, ctx->lv[0], 0, out));
   return VK_OK;
 }

@@ -132,6 +132,10 @@ struct vk_ctx {
   std::vector<vk_level> lv;
   std::string err;
   int32_t* status = nullptr;   // device status block (4 KiB)
+  // pinned host staging for small device-to-host reads: a read into pageable memory can wait
+  // for every stream of the device, which would serialise the side stream's block inversions
+  char* pinned = nullptr;
+  size_t pinned_bytes = 0;
   // workspace
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -144,6 +148,12 @@ struct vk_ctx {
   int32_t sweep_variant = 0;  // additive sweep: 0 DoF gather, 1 coloured scatter
   bool fast_setup = true;     // register-resident patch inversion where compiled
   bool maps_ready = false;    // multiplicities and DoF lists (depend on the mesh only)
+  // the block inversions of the last setup run on `side`; the first call that applies a
+  // block makes `stream` wait for them, and the first synchronisation after that checks
+  // their status words
+  bool coarse_pending = false;
+  bool coarse_check_due = false;
+
   void* Y = nullptr;          // per-cell products y_K of the additive sweep
   // batched GMRES: segments of the finest level solved as independent systems
   std::vector<int64_t> seg_rows;  // host, n_seg + 1

@@ -428,3 +428,28 @@ def test_coarse_solve_3d_box_size(vk):
     assert np.linalg.norm(xg - xs) <= 1e-9 * np.linalg.norm(xs)
     assert np.linalg.norm(J @ xg - b) <= 1e-11 * np.linalg.norm(b) * max(1.0, abs(J).max())
     S.close()
+
+
+def test_singular_coarse_block_reported_by_the_solve(vk):
+    """The block inversion overlaps the next solve: a singular coarse matrix is reported by the first
+    call that applies it, and setup must run again before the next solve."""
+    import copy
+    P, _ = problem("cfg0")
+    levels = copy.copy(P.levels)
+    L0 = copy.copy(levels[0])
+    J0 = L0.J.copy()
+    J0.data[J0.indptr[5]:J0.indptr[6]] = 0.0   # a zero row: J_0 is singular
+    L0.J = J0
+    levels[0] = L0
+    for call in ("gmres", "vcycle"):
+        S = make_solver(vk, type("P", (), {"levels": levels})())
+        b = t(P.b)
+        x = torch.zeros_like(b)
+        with pytest.raises(vk.VkError, match="singular"):
+            if call == "gmres":
+                S.gmres_solve(b, x)
+            else:
+                S.vcycle(b, x, 2, 2)
+        with pytest.raises(vk.VkError, match="vanka_setup"):
+            S.gmres_solve(b, x)
+        S.close()
