@@ -14,20 +14,22 @@ __global__ __launch_bounds__(256) void spmv_kernel(int64_t n_rows, const int64_t
   const int64_t gid = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int64_t row = gid / LPR;
   const int lane = threadIdx.x & (LPR - 1);
-  double s0 = 0.0, s1 = 0.0;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   if (row < n_rows) {
     const int64_t e1 = row_ptr[row + 1];
     int64_t e = row_ptr[row] + lane;
-    // two independent loads in flight per lane
-    for (; e + LPR < e1; e += 2 * LPR) {
-      const double v0 = val[e], v1 = val[e + LPR];
-      const int32_t c0 = col[e], c1 = col[e + LPR];
+    // four independent loads in flight per lane
+    for (; e + 3 * LPR < e1; e += 4 * LPR) {
+      const int32_t c0 = col[e], c1 = col[e + LPR], c2 = col[e + 2 * LPR], c3 = col[e + 3 * LPR];
+      const double v0 = val[e], v1 = val[e + LPR], v2 = val[e + 2 * LPR], v3 = val[e + 3 * LPR];
       s0 = fma(v0, x[c0], s0);
       s1 = fma(v1, x[c1], s1);
+      s2 = fma(v2, x[c2], s2);
+      s3 = fma(v3, x[c3], s3);
     }
-    if (e < e1) s0 = fma(val[e], x[col[e]], s0);
+    for (; e < e1; e += LPR) s0 = fma(val[e], x[col[e]], s0);
   }
-  double sum = s0 + s1;
+  double sum = (s0 + s1) + (s2 + s3);
 #pragma unroll
   for (int o = LPR / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, LPR);
   if (row < n_rows && lane == 0) {
