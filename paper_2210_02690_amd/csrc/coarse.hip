@@ -8,6 +8,10 @@
 // rows never move.  The stored matrix W then satisfies
 // J^{-1}[k][q_j] = W[q_k][j], so the solve is y[k] = sum_j W[q_k][j] b[q_j].
 //
+// During the elimination each block is stored column-major, so a panel's
+// columns are contiguous; a final in-place transpose leaves W row-major for the
+// solve.
+//
 // Two levels of blocking.  The columns are taken in outer blocks of NBO = 64;
 // within an outer block, inner panels of NB columns:
 //   panel kernel  (one workgroup per block, the panel rows in registers): the
@@ -60,7 +64,7 @@ __global__ void block_to_dense_kernel(int n_blocks, const int64_t* __restrict__ 
       atomicOr(&status[1], 1);
       continue;
     }
-    W[(r - r0) * nbk + (c - r0)] = val[e];
+    W[(c - r0) * nbk + (r - r0)] = val[e];  // column-major during the elimination
   }
 }
 
@@ -94,7 +98,7 @@ __global__ __launch_bounds__(CTT) void block_panel_kernel(const int64_t* __restr
     const int64_t i = tid + (int64_t)r * CTT;
     const bool ok = i < n;
 #pragma unroll
-    for (int c = 0; c < NB; ++c) P[r][c] = (ok && c < nb) ? W[i * n + k0 + c] : 0.0;
+    for (int c = 0; c < NB; ++c) P[r][c] = (ok && c < nb) ? W[(k0 + c) * n + i] : 0.0;
     if (!ok || pcol_g[i] != 0) used |= 1u << r;
   }
 #pragma unroll
@@ -162,7 +166,7 @@ __global__ __launch_bounds__(CTT) void block_panel_kernel(const int64_t* __restr
     if (i < n) {
 #pragma unroll
       for (int c = 0; c < NB; ++c)
-        if (c < nb) W[i * n + k0 + c] = P[r][c];
+        if (c < nb) W[(k0 + c) * n + i] = P[r][c];
     }
   }
   if (tid < nb) {
@@ -177,7 +181,7 @@ __global__ __launch_bounds__(CTT) void block_panel_kernel(const int64_t* __restr
   for (int64_t e = tid; e < (int64_t)nb * gw; e += CTT) {
     const int t = (int)(e / gw);
     const int64_t c = c0o + (e - (int64_t)t * gw);
-    if (c < k0 || c >= k0 + nb) gi[t * NBO + (c - c0o)] = W[(int64_t)s_q[t] * n + c];
+    if (c < k0 || c >= k0 + nb) gi[t * NBO + (c - c0o)] = W[c * n + s_q[t]];
   }
 }
 
@@ -194,16 +198,18 @@ __global__ void gather_pivot_rows_kernel(const int64_t* __restrict__ rows, const
   const int64_t q = q_all[r0 + c0o + t];
   double* go = go_all + (int64_t)NBO * (r0 - rows[0]) + (int64_t)t * n;
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
-    go[c] = W[q * n + c];
+    go[c] = W[c * n + q];
 }
 
-// In-place update of columns [cb, ce) \ [sk0, sk1) of every block (blockIdx.z):
+// In-place update of columns [cb, ce) \ [sk0, sk1) of every block (blockIdx.z), W column-major:
 //   W[i, c] = (pcol[i] - 1 in [p0, p1) ? 0 : W[i, c]) + sum_{t < K} W[i, kc + t] G[t][c - gc0]
 // with K clipped to the block.  G: inner mode (g_stride > 0) block b at b * g_stride with
 // leading dimension ldg; outer mode (g_stride == 0) block b at NBO * (rows[b] - rows[0]) with
-// leading dimension n_b.  Workgroup tile 64 x 64 (four wavefronts of 16 rows), FP64 matrix
-// cores (16 x 16 x 4); lane l holds A(l % 16, l / 16), B(l / 16, l % 16) and, in accumulator
-// element i, C(4 i + l / 16, l % 16).
+// leading dimension n_b.  Workgroup tile 64 rows x 64 columns, wavefront w the columns
+// [16 w, 16 w + 16).  The FP64 matrix cores (16 x 16 x 4) compute the transposed tile
+// D(c, i) = sum_t G(t, c) W(i, t): lane l holds A = G(l / 16, c_0 + l % 16) and
+// B = W(i_0 + l % 16, l / 16), and accumulator element v holds D(4 v + l / 16, l % 16), so
+// lanes 0..15 own 16 consecutive rows of one column (contiguous in memory).
 __global__ __launch_bounds__(256) void gj_update_kernel(const int64_t* __restrict__ rows,
                                                         const int64_t* __restrict__ woff, double* W_all,
                                                         const int32_t* __restrict__ pcol_all, int64_t kc, int32_t K,
@@ -224,34 +230,64 @@ __global__ __launch_bounds__(256) void gj_update_kernel(const int64_t* __restric
   const int64_t lg = g_stride > 0 ? ldg : n;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i16 = lane & 15, kq = lane >> 4;
-  const int64_t ra = rt + 16 * wave + i16;  // A row of this lane
+  const int64_t ca = ct + 16 * wave + i16;  // the column of this lane's A operand
+  const bool ca_ok = ca < ceb;
   f64x4 acc[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) acc[j] = (f64x4){0.0, 0.0, 0.0, 0.0};
   for (int64_t ks = 0; ks < kk; ks += 4) {
     const int64_t k = ks + kq;
     const bool k_ok = k < kk;
-    const double a = (k_ok && ra < n) ? W[ra * n + kc + k] : 0.0;
+    const double a = (k_ok && ca_ok) ? G[k * lg + (ca - gc0)] : 0.0;
+    const double* wk = W + (kc + k) * n;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int64_t c = ct + 16 * j + i16;
-      const double b = (k_ok && c < ceb) ? G[k * lg + (c - gc0)] : 0.0;
+      const int64_t r = rt + 16 * j + i16;
+      const double b = (k_ok && r < n) ? wk[r] : 0.0;
       acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
     }
   }
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int64_t c = ct + 16 * j + i16;
+  for (int v = 0; v < 4; ++v) {
+    const int64_t c = ct + 16 * wave + 4 * v + kq;
     if (c < cb || c >= ceb || (c >= sk0 && c < sk1)) continue;
+    double* wc = W + c * n;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t r = rt + 16 * wave + 4 * i + kq;
+    for (int j = 0; j < 4; ++j) {
+      const int64_t r = rt + 16 * j + i16;
       if (r >= n) continue;
       const int32_t u = pcol[r] - 1;
       const bool zero = u >= p0 && u < p1;
-      const double old = W[r * n + c];
-      W[r * n + c] = (zero ? 0.0 : old) + acc[j][i];
+      const double old = wc[r];
+      wc[r] = (zero ? 0.0 : old) + acc[j][v];
     }
+  }
+}
+
+// In-place transpose of every block (column-major -> row-major), 32 x 32 tiles through LDS:
+// workgroup (I, J) with I <= J swaps tiles (I, J) and (J, I).
+__global__ __launch_bounds__(256) void block_transpose_kernel(const int64_t* __restrict__ rows,
+                                                              const int64_t* __restrict__ woff, double* W_all) {
+  __shared__ double ta[32][33];
+  __shared__ double tb[32][33];
+  const int bk = blockIdx.z;
+  const int64_t n = rows[bk + 1] - rows[bk];
+  const int64_t I = blockIdx.y, J = blockIdx.x;
+  if (I > J || I * 32 >= n || J * 32 >= n) return;  // uniform
+  double* W = W_all + woff[bk];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t r = I * 32 + y, c = J * 32 + tx;
+    ta[y][tx] = (r < n && c < n) ? W[r * n + c] : 0.0;
+    const int64_t r2 = J * 32 + y, c2 = I * 32 + tx;
+    tb[y][tx] = (r2 < n && c2 < n) ? W[r2 * n + c2] : 0.0;
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t r = I * 32 + y, c = J * 32 + tx;
+    if (r < n && c < n) W[r * n + c] = tb[tx][y];
+    const int64_t r2 = J * 32 + y, c2 = I * 32 + tx;
+    if (r2 < n && c2 < n) W[r2 * n + c2] = ta[tx][y];
   }
 }
 
@@ -310,7 +346,9 @@ hipError_t run_blocked(hipStream_t s, const vk_level& L, int32_t* status) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  const unsigned tiles = (unsigned)((n + 31) / 32);
+  block_transpose_kernel<<<dim3(tiles, tiles, nbk), 256, 0, s>>>(L.d_cb_rows, L.d_cb_woff, L.cb_a);
+  return hipGetLastError();
 }
 
 }  // namespace
