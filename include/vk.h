@@ -157,11 +157,15 @@ vk_status vk_set_workspace(vk_ctx* ctx, void* dev, size_t bytes, vk_prec prec, i
  * with partial pivoting (first row of maximal |pivot|; the LU pivot sequence)
  * and store A_K in `prec`; compute 1/p_mu, p_mu = number of cells containing
  * DoF mu (Eq. 3.5b); and form the FP64 inverse of J_0 for the coarsest-level
- * direct solve.  omega is the under-relaxation of Eq. 3.4 (the paper uses 0.7).
+ * direct solve (blocked Gauss-Jordan with partial pivoting: the largest |pivot|
+ * up to a relative 2^-38, the lowest row among those).  omega is the
+ * under-relaxation of Eq. 3.4 (the paper uses 0.7).
  * On a zero pivot in a patch returns VK_ERR_SINGULAR with *bad_level /
  * *bad_cell (host, may be NULL) naming the first failing level and cell.
- * Synchronises the stream for the patch inversions only: the inversion of the
- * directly solved blocks (the coarse matrix) keeps running on an internal
+ * The patch inversions run on an internal stream restricted to 15/16 of the
+ * CUs (when the runtime supports CU masks), which the context's stream waits
+ * for; vanka_setup synchronises for them only.  The inversion of the
+ * directly solved blocks (the coarse matrix) keeps running on a second internal
  * stream and overlaps the start of the next solve; the first call that applies
  * a block (vcycle, gmres_solve, gmres_solve_batched, vk_get_coarse_inverse)
  * orders itself after it and reports a singular or coupled block there
@@ -259,12 +263,15 @@ vk_status vk_graph_stats(const vk_ctx* ctx, int64_t* captures, int64_t* launches
 
 /* ---- per-launch timing (benchmarks) --------------------------------------
  * With timing enabled, the library brackets every launch of the kernel classes
- * below with a pair of HIP events on the context's stream (a pool of 16384
- * pairs; launches beyond it are not recorded).  vk_timing_enable(ctx, 1, l)
+ * below with a pair of HIP events on the stream the launch runs on (a pool of
+ * 16384 pairs; launches beyond it are not recorded).  vk_timing_enable(ctx, 1, l)
  * clears earlier records and records launches on level l only (l = -1: all
- * levels); enable = 0 stops recording.  vk_timing_read synchronises the
- * stream and returns the number of recorded launches of class `kind` on level
- * l (l = -1: all levels) and their summed duration in milliseconds. */
+ * levels); enable = 0 stops recording.  vk_timing_kinds restricts recording to
+ * the classes whose bit (1 << kind) is set in `mask` (default: all); each
+ * recorded launch costs two event records, so a benchmark records only what it
+ * reads.  vk_timing_read synchronises the streams and returns the number of
+ * recorded launches of class `kind` on level l (l = -1: all levels) and their
+ * summed duration in milliseconds. */
 typedef enum {
   VK_KERNEL_PATCH_APPLY = 0,    /* gather - patch GEMV - scatter, one colour */
   VK_KERNEL_SPMV = 1,           /* level defect b - J d */
@@ -274,6 +281,7 @@ typedef enum {
   VK_KERNEL_DOF_GATHER = 5      /* d += omega z / p from the y_K (additive, DoF gather) */
 } vk_kernel_kind;
 vk_status vk_timing_enable(vk_ctx* ctx, int32_t enable, int32_t level);
+vk_status vk_timing_kinds(vk_ctx* ctx, uint32_t mask);
 vk_status vk_timing_read(vk_ctx* ctx, int32_t kind, int32_t l, int64_t* launches, double* total_ms);
 
 #ifdef __cplusplus

@@ -179,16 +179,18 @@ constexpr int32_t kTimingPool = 16384;
 // Brackets one launch with a pair of events when timing is on.
 struct Timed {
   vk_ctx* ctx;
+  hipStream_t stream;
   int32_t slot = -1;
-  Timed(vk_ctx* c, int32_t kind, int32_t level) : ctx(c) {
+  Timed(vk_ctx* c, int32_t kind, int32_t level, hipStream_t s = nullptr) : ctx(c), stream(s ? s : c->stream) {
     if (!ctx->timing || (int32_t)ctx->recs.size() >= kTimingPool) return;
     if (ctx->timing_level >= 0 && level != ctx->timing_level) return;
+    if (!((ctx->timing_kinds >> kind) & 1u)) return;
     slot = (int32_t)ctx->recs.size();
     ctx->recs.push_back({kind, level, slot});
-    (void)hipEventRecord(ctx->ev[2 * slot], ctx->stream);
+    (void)hipEventRecord(ctx->ev[2 * slot], stream);
   }
   ~Timed() {
-    if (slot >= 0) (void)hipEventRecord(ctx->ev[2 * slot + 1], ctx->stream);
+    if (slot >= 0) (void)hipEventRecord(ctx->ev[2 * slot + 1], stream);
   }
 };
 
@@ -383,6 +385,26 @@ vk_status ready(vk_ctx* ctx) {
 
 }  // namespace
 
+// The patch inversions fill every CU they may use, and the block inversions, one workgroup per
+// block and a long chain of launches, would wait for a whole CU to drain before each launch.
+// Their stream therefore leaves 1/16 of the CUs (16 of 256) out of its mask.  Without CU
+// masking the patch inversions stay on the caller's stream.
+void create_setup_stream(vk_ctx* ctx) {
+  int dev = 0, n_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 32) {
+    (void)hipGetLastError();
+    return;
+  }
+  const int keep = n_cu - n_cu / 16;
+  std::vector<uint32_t> mask((n_cu + 31) / 32, 0u);
+  for (int c = 0; c < keep; ++c) mask[c / 32] |= 1u << (c % 32);
+  if (hipExtStreamCreateWithCUMask(&ctx->setup, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->setup = nullptr;
+  }
+}
+
 extern "C" {
 
 vk_status vk_create(vk_ctx** out, int32_t n_levels, void* hip_stream) {
@@ -400,8 +422,12 @@ vk_status vk_create(vk_ctx** out, int32_t n_levels, void* hip_stream) {
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->setup_ev, hipEventDisableTiming);
+  if (e == hipSuccess) create_setup_stream(ctx);
   if (e != hipSuccess) {
     (void)hipGetLastError();  // do not leave the error for the caller's next check
+    if (ctx->setup) (void)hipStreamDestroy(ctx->setup);
+    if (ctx->setup_ev) (void)hipEventDestroy(ctx->setup_ev);
     if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
     if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
@@ -425,6 +451,11 @@ void vk_destroy(vk_ctx* ctx) {
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
 
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
+  if (ctx->setup) {
+    (void)hipStreamSynchronize(ctx->setup);
+    (void)hipStreamDestroy(ctx->setup);
+  }
+  if (ctx->setup_ev) (void)hipEventDestroy(ctx->setup_ev);
   if (ctx->side) (void)hipStreamSynchronize(ctx->side);
   if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
   if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
@@ -442,6 +473,7 @@ vk_status vk_set_level_groups(vk_ctx* ctx, int32_t l, const vk_csr* J, const vk_
   if (!ctx) return VK_ERR_ARG;
   ++ctx->gen;
   if (ctx->side) (void)hipStreamSynchronize(ctx->side);  // block inversions still reading the old setup
+  if (ctx->setup) (void)hipStreamSynchronize(ctx->setup);  // and patch inversions after a failed setup
   ctx->coarse_pending = false;
   ctx->coarse_check_due = false;
   if (l < 0 || l >= ctx->n_levels) return fail(ctx, VK_ERR_ARG, "level index out of range");
@@ -585,6 +617,7 @@ vk_status vk_set_workspace(vk_ctx* ctx, void* dev, size_t bytes, vk_prec prec, i
   if (!ctx) return VK_ERR_ARG;
   ++ctx->gen;
   if (ctx->side) (void)hipStreamSynchronize(ctx->side);  // block inversions still reading the old setup
+  if (ctx->setup) (void)hipStreamSynchronize(ctx->setup);  // and patch inversions after a failed setup
   ctx->coarse_pending = false;
   ctx->coarse_check_due = false;
   if (prec != VK_F64 && prec != VK_F32 && prec != VK_BF16) return fail(ctx, VK_ERR_ARG, "unknown precision");
@@ -648,26 +681,33 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
   // stream while the patch inversions fill the rest of the GPU
   VK_TRY(hipEventRecord(ctx->fork_ev, s));
   VK_TRY(hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0));
+  // the patch inversions on the CU-masked setup stream
+  const hipStream_t ps = ctx->setup ? ctx->setup : s;
+  if (ps != s) VK_TRY(hipStreamWaitEvent(ps, ctx->fork_ev, 0));
   if (!ctx->maps_ready) {
     // multiplicities and DoF -> (cell, local) lists depend on the mesh only
     for (int l = 1; l < ctx->n_levels; ++l) {
       vk_level& L = ctx->lv[l];
       int32_t* count = reinterpret_cast<int32_t*>(L.r);
-      VK_TRY(launch_fill_i32(s, L.J.n_rows, 0, count));
-      for (const vk_group& G : L.groups) VK_TRY(launch_count_add(s, G.n_cells, G.n_K, G.cell_dofs, count));
-      VK_TRY(launch_inv_count(s, L.J.n_rows, count, L.inv_p));
-      VK_TRY(launch_dof_map(s, L, count));
+      VK_TRY(launch_fill_i32(ps, L.J.n_rows, 0, count));
+      for (const vk_group& G : L.groups) VK_TRY(launch_count_add(ps, G.n_cells, G.n_K, G.cell_dofs, count));
+      VK_TRY(launch_inv_count(ps, L.J.n_rows, count, L.inv_p));
+      VK_TRY(launch_dof_map(ps, L, count));
     }
   }
   for (int l = 1; l < ctx->n_levels; ++l) {
     vk_level& L = ctx->lv[l];
-    Timed t(ctx, VK_KERNEL_PATCH_SETUP, l);
+    Timed t(ctx, VK_KERNEL_PATCH_SETUP, l, ps);
     for (const vk_group& G : L.groups) {
       bool handled = false;
-      if (ctx->fast_setup) VK_TRY(launch_patch_setup_fast(s, L.J, G, ctx->prec, ctx->status + 64 + l, &handled));
+      if (ctx->fast_setup) VK_TRY(launch_patch_setup_fast(ps, L.J, G, ctx->prec, ctx->status + 64 + l, &handled));
       if (!handled)
-        VK_TRY(launch_patch_setup(s, L.J, G, ctx->prec, ctx->big_scratch, ctx->big_chunk, ctx->status + 64 + l));
+        VK_TRY(launch_patch_setup(ps, L.J, G, ctx->prec, ctx->big_scratch, ctx->big_chunk, ctx->status + 64 + l));
     }
+  }
+  if (ps != s) {
+    VK_TRY(hipEventRecord(ctx->setup_ev, ps));
+    VK_TRY(hipStreamWaitEvent(s, ctx->setup_ev, 0));
   }
   // Block inversions on the side stream, concurrent with the patch inversions (enqueued after
   // them, so the host's launch work does not hold the patch kernels back).
@@ -1065,9 +1105,16 @@ vk_status vk_timing_enable(vk_ctx* ctx, int32_t enable, int32_t level) {
   return VK_OK;
 }
 
+vk_status vk_timing_kinds(vk_ctx* ctx, uint32_t mask) {
+  if (!ctx) return VK_ERR_ARG;
+  ctx->timing_kinds = mask;
+  return VK_OK;
+}
+
 vk_status vk_timing_read(vk_ctx* ctx, int32_t kind, int32_t l, int64_t* launches, double* total_ms) {
   if (!ctx || !launches || !total_ms) return VK_ERR_ARG;
   VK_TRY(hipStreamSynchronize(ctx->stream));
+  if (ctx->setup) VK_TRY(hipStreamSynchronize(ctx->setup));
   int64_t cnt = 0;
   double tot = 0.0;
   for (const vk_timing_rec& r : ctx->recs) {

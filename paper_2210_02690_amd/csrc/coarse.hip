@@ -68,18 +68,52 @@ __global__ void block_to_dense_kernel(int n_blocks, const int64_t* __restrict__ 
   }
 }
 
+// maximum over the 16 lanes of each DPP row, read from lane 15 (row 0's result)
+__device__ inline double row16_max(double v) {
+  const double id = -__builtin_inf();
+  v = fmax(v, dpp_move<0x111, 0xF>(v, id));
+  v = fmax(v, dpp_move<0x112, 0xF>(v, id));
+  v = fmax(v, dpp_move<0x114, 0xF>(v, id));
+  v = fmax(v, dpp_move<0x118, 0xF>(v, id));
+  const int2 a = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_readlane(a.x, 15);
+  r.y = __builtin_amdgcn_readlane(a.y, 15);
+  return __builtin_bit_cast(double, r);
+}
+
+// Pivot keys.  A candidate row i with |a| finite maps to the non-negative double whose bits are
+// those of |a| with the low 14 bits replaced by KEY_MASK - i, so one floating-point maximum picks
+// the largest |a| and, among values equal in all but those bits (relative 2^-38), the lowest
+// row: partial pivoting up to that tolerance, deterministic.  An infinite |a| takes the
+// largest finite magnitude (it wins, and the pivot test then rejects it); NaN and rows already
+// used take -1.
+constexpr int64_t KEY_MASK = (1 << 14) - 1;  // rows per block < 2^14
+__device__ inline double pivot_key(double a, int64_t i) {
+  const double av = fabs(a);
+  if (!(av == av)) return -1.0;
+  const int64_t bits = __builtin_bit_cast(int64_t, av < __builtin_inf() ? av : 1.7976931348623157e308);
+  return __builtin_bit_cast(double, (bits & ~KEY_MASK) | (KEY_MASK - i));
+}
+__device__ inline int key_row(double key) { return (int)(KEY_MASK - (__builtin_bit_cast(int64_t, key) & KEY_MASK)); }
+
 // Panel of columns [k0, k0 + NB) of every block (blockIdx.x), in place.  pcol[i] is
 // 0 for a row not yet used as a pivot, else 1 + the column it was pivot of.  gi: the
 // new pivot rows' old values in the outer block's other columns, laid out [t][c - c0o].
+// Each column step has one barrier: every wave's best candidate row goes to LDS with its key
+// before it, and after it every thread reads the winner's row and scales it itself.
 template <int CTT, int R, int NB>
 __global__ __launch_bounds__(CTT) void block_panel_kernel(const int64_t* __restrict__ rows,
                                                           const int64_t* __restrict__ woff, int64_t k0, int64_t c0o,
                                                           double* W_all, int32_t* __restrict__ q_all,
                                                           int32_t* __restrict__ pcol_all, double* __restrict__ gi_all,
                                                           int32_t* status) {
-  __shared__ double w_abs[CTT / 64];
-  __shared__ int w_idx[CTT / 64];
-  __shared__ double prow[NB];
+  constexpr int NW = CTT / 64;
+  static_assert(NW <= 16, "the cross-wave step reduces over one 16-lane row");
+  // double-buffered by column parity: a thread that runs ahead into column j + 1 writes the
+  // other buffer, and it cannot reach column j + 2 before every thread has left column j
+  __shared__ double w_key[2][NW];
+  __shared__ double w_row[2][NW][NB];
   __shared__ int s_q[NB];
   const int bk = blockIdx.x;
   const int64_t r0 = rows[bk], n = rows[bk + 1] - r0;
@@ -90,7 +124,7 @@ __global__ __launch_bounds__(CTT) void block_panel_kernel(const int64_t* __restr
   int32_t* q_g = q_all + r0;
   int32_t* pcol_g = pcol_all + r0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // P[r][.]: panel row tid + r * CTT; the column loop is unrolled completely
+  // P[r][.]: panel row tid + r * CTT
   double P[R][NB];
   uint32_t used = 0;
 #pragma unroll
@@ -101,65 +135,85 @@ __global__ __launch_bounds__(CTT) void block_panel_kernel(const int64_t* __restr
     for (int c = 0; c < NB; ++c) P[r][c] = (ok && c < nb) ? W[(k0 + c) * n + i] : 0.0;
     if (!ok || pcol_g[i] != 0) used |= 1u << r;
   }
+  // The column loop stays a loop over groups of U columns: the kernel runs as one workgroup per
+  // block, so a fully unrolled body would be fetched from memory once per column.  Inside a
+  // group the columns have compile-time indices; after it the register columns rotate by U, so
+  // group g always finds its columns at P[.][0 .. U); after NB / U groups they are back in order.
+  constexpr int U = NB < 4 ? NB : 4;
+  static_assert(NB % U == 0, "panel width must be a multiple of the group size");
+#pragma unroll 1
+  for (int g = 0; g < NB; g += U) {
 #pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    if (j < nb) {  // uniform
-      double ba = -1.0;
-      int bi = INT_MAX;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const double av = fabs(P[r][j]);
-        if (!((used >> r) & 1u) && av > ba) { ba = av; bi = tid + r * CTT; }
-      }
-      const double m = wave_max(ba);
-      const int wi = wave_min((ba == m && bi != INT_MAX) ? bi : INT_MAX);
-      if (lane == 0) { w_abs[wave] = m; w_idx[wave] = wi; }
-      __syncthreads();
-      double pm = w_abs[0];
-      int p = w_idx[0];
-#pragma unroll
-      for (int w = 1; w < CTT / 64; ++w) {
-        const double om = w_abs[w];
-        const int oi = w_idx[w];
-        if (om > pm || (om == pm && oi < p)) { pm = om; p = oi; }
-      }
-      const bool bad = p == INT_MAX || !(pm > 0.0) || !isfinite(pm);
-      const int owner = bad ? -1 : p % CTT, slot = bad ? -1 : p / CTT;
-      if (tid == owner) {
-        double v[NB];
-#pragma unroll
-        for (int c = 0; c < NB; ++c) {
-          v[c] = P[0][c];
-#pragma unroll
-          for (int r = 1; r < R; ++r) v[c] = (slot == r) ? P[r][c] : v[c];
-        }
-        const double inv = 1.0 / v[j];
-#pragma unroll
-        for (int c = 0; c < NB; ++c) prow[c] = (c == j ? 1.0 : v[c]) * inv;
-        used |= 1u << slot;
-        s_q[j] = p;
-      }
-      if (bad && tid == 0) {
-        atomicMin(&status[0], -1);  // failure path only
-        s_q[j] = 0;
-      }
-      __syncthreads();
-      if (!bad) {
+    for (int u = 0; u < U; ++u) {
+      const int j = g + u;
+      if (j < nb) {  // uniform
+        const int buf = j & 1;
+        double kr[R], key = -1.0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const bool piv = (tid == owner) && (r == slot);
-          const double f = piv ? -1.0 : P[r][j];
-          const double keep = piv ? 0.0 : 1.0;
+          kr[r] = ((used >> r) & 1u) ? -1.0 : pivot_key(P[r][u], tid + r * CTT);
+          key = fmax(key, kr[r]);
+        }
+        const double wk = wave_max(key);
+        // this wave's best candidate row (one row of one lane: keys are distinct)
 #pragma unroll
-          for (int c = 0; c < NB; ++c) {
-            const double pcv = prow[c];
-            P[r][c] = (c == j) ? -f * pcv : fma(-f, pcv, keep * P[r][c]);
+        for (int r = 0; r < R; ++r)
+          if (kr[r] == wk && wk >= 0.0) {
+            w_key[buf][wave] = wk;
+#pragma unroll
+            for (int c = 0; c < NB; ++c) w_row[buf][wave][c] = P[r][c];
           }
+        if (wk < 0.0 && lane == 0) w_key[buf][wave] = -1.0;
+        __syncthreads();
+        const int wl = lane & 15;
+        const double pk = row16_max(wl < NW ? w_key[buf][wl] : -1.0);
+        const int p = key_row(pk);
+        const int otid = p % CTT, oslot = p / CTT, ow = otid >> 6;
+        double pr[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) pr[c] = w_row[buf][ow][c];
+        const double piv = pr[u];
+        const bool bad = pk < 0.0 || !(piv != 0.0) || !isfinite(piv);
+        if (bad && tid == 0) atomicMin(&status[0], -1);  // failure path only
+        if (tid == 0) s_q[j] = bad ? 0 : p;
+        // The update runs whether or not the pivot is usable (a branch around it would keep two
+        // copies of the panel live): after a failure the status word reports the block and its
+        // values are void.
+        const double inv = bad ? 0.0 : 1.0 / piv;
+#pragma unroll
+        for (int c = 0; c < NB; ++c) pr[c] = (c == u ? 1.0 : pr[c]) * inv;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const double f = P[r][u];
+#pragma unroll
+          for (int c = 0; c < NB; ++c) P[r][c] = (c == u) ? -f * pr[c] : fma(-f, pr[c], P[r][c]);
+        }
+        // the pivot row becomes the scaled row
+        if (!bad && tid == otid) {
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            if (r == oslot) {  // uniform
+#pragma unroll
+              for (int c = 0; c < NB; ++c) P[r][c] = pr[c];
+            }
+          used |= 1u << oslot;
         }
       }
-      __syncthreads();
+    }
+    if (U < NB) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        double t[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) t[u] = P[r][u];
+#pragma unroll
+        for (int c = 0; c + U < NB; ++c) P[r][c] = P[r][c + U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) P[r][NB - U + u] = t[u];
+      }
     }
   }
+  __syncthreads();  // s_q complete
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int64_t i = tid + (int64_t)r * CTT;
@@ -174,13 +228,13 @@ __global__ __launch_bounds__(CTT) void block_panel_kernel(const int64_t* __restr
     pcol_g[s_q[tid]] = (int32_t)(k0 + tid + 1);
   }
   // old values of the new pivot rows in the other columns of the outer block (this kernel
-  // writes only the panel's columns)
+  // writes only the panel's columns); nb * gw <= NB * NBO fits an int
   const int64_t ge = (c0o + NBO < n ? c0o + NBO : n);
-  const int64_t gw = ge - c0o;
+  const int gw = (int)(ge - c0o);
   double* gi = gi_all + (int64_t)bk * NB * NBO;
-  for (int64_t e = tid; e < (int64_t)nb * gw; e += CTT) {
-    const int t = (int)(e / gw);
-    const int64_t c = c0o + (e - (int64_t)t * gw);
+  for (int e = tid; e < nb * gw; e += CTT) {
+    const int t = e / gw;
+    const int64_t c = c0o + (e - t * gw);
     if (c < k0 || c >= k0 + nb) gi[t * NBO + (c - c0o)] = W[c * n + s_q[t]];
   }
 }
@@ -210,6 +264,7 @@ __global__ void gather_pivot_rows_kernel(const int64_t* __restrict__ rows, const
 // D(c, i) = sum_t G(t, c) W(i, t): lane l holds A = G(l / 16, c_0 + l % 16) and
 // B = W(i_0 + l % 16, l / 16), and accumulator element v holds D(4 v + l / 16, l % 16), so
 // lanes 0..15 own 16 consecutive rows of one column (contiguous in memory).
+template <int KMAX>
 __global__ __launch_bounds__(256) void gj_update_kernel(const int64_t* __restrict__ rows,
                                                         const int64_t* __restrict__ woff, double* W_all,
                                                         const int32_t* __restrict__ pcol_all, int64_t kc, int32_t K,
@@ -235,18 +290,26 @@ __global__ __launch_bounds__(256) void gj_update_kernel(const int64_t* __restric
   f64x4 acc[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) acc[j] = (f64x4){0.0, 0.0, 0.0, 0.0};
-  for (int64_t ks = 0; ks < kk; ks += 4) {
-    const int64_t k = ks + kq;
+  // all operands of the (at most KMAX-deep) product are loaded before the first product, so the
+  // loads are in flight together
+  constexpr int KS = KMAX / 4;
+  double av[KS], bv[KS][4];
+#pragma unroll
+  for (int s4 = 0; s4 < KS; ++s4) {
+    const int64_t k = 4 * s4 + kq;
     const bool k_ok = k < kk;
-    const double a = (k_ok && ca_ok) ? G[k * lg + (ca - gc0)] : 0.0;
-    const double* wk = W + (kc + k) * n;
+    av[s4] = (k_ok && ca_ok) ? G[k * lg + (ca - gc0)] : 0.0;
+    const double* wk = W + (kc + (k_ok ? k : 0)) * n;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int64_t r = rt + 16 * j + i16;
-      const double b = (k_ok && r < n) ? wk[r] : 0.0;
-      acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
+      bv[s4][j] = (k_ok && r < n) ? wk[r] : 0.0;
     }
   }
+#pragma unroll
+  for (int s4 = 0; s4 < KS; ++s4)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s4], bv[s4][j], acc[j], 0, 0, 0);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int64_t c = ct + 16 * wave + 4 * v + kq;
@@ -334,13 +397,13 @@ hipError_t run_blocked(hipStream_t s, const vk_level& L, int32_t* status) {
                                                          L.cb_used, L.cb_gi, status);
       // the same steps on the outer block's other columns, before and after the panel
       if (n > NB)
-        gj_update_kernel<<<dim3(1, row_tiles, nbk), 256, 0, s>>>(
+        gj_update_kernel<NB><<<dim3(1, row_tiles, nbk), 256, 0, s>>>(
             L.d_cb_rows, L.d_cb_woff, L.cb_a, L.cb_used, k0, NB, L.cb_gi, (int64_t)NB * NBO, NBO, c0o, c0o,
             c0o + NBO, k0, k0 + NB, k0, k0 + NB, c0o);
     }
     gather_pivot_rows_kernel<<<dim3((unsigned)((n + 255) / 256 < 64 ? (n + 255) / 256 : 64), NBO, nbk), 256, 0, s>>>(
         L.d_cb_rows, L.d_cb_woff, c0o, L.cb_a, L.cb_q, L.cb_go);
-    gj_update_kernel<<<dim3(row_tiles, row_tiles, nbk), 256, 0, s>>>(L.d_cb_rows, L.d_cb_woff, L.cb_a, L.cb_used,
+    gj_update_kernel<NBO><<<dim3(row_tiles, row_tiles, nbk), 256, 0, s>>>(L.d_cb_rows, L.d_cb_woff, L.cb_a, L.cb_used,
                                                                      c0o, NBO, L.cb_go, 0, 0, 0, 0, n, c0o,
                                                                      c0o + NBO, c0o, c0o + NBO, 0);
     hipError_t e = hipGetLastError();
@@ -369,7 +432,7 @@ hipError_t launch_block_invert(hipStream_t s, const vk_level& L, int32_t* status
   // panel rows per thread R, panel width NB: R * NB <= 64 doubles in registers (<= 36 at
   // 1024 threads, whose waves may hold 128 registers each)
   const int64_t m = L.cb_max;
-  if (m <= 1024) e = run_blocked<256, 4, 16>(s, L, status);
+  if (m <= 1024) e = run_blocked<512, 2, 16>(s, L, status);
   else if (m <= 2048) e = run_blocked<256, 8, 8>(s, L, status);
   else if (m <= 4096) e = run_blocked<512, 8, 8>(s, L, status);
   else if (m <= 8192) e = run_blocked<1024, 8, 4>(s, L, status);

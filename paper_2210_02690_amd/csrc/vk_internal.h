@@ -123,11 +123,16 @@ struct vk_ctx {
   // per-launch event timing
   bool timing = false;
   int32_t timing_level = -1;
+  uint32_t timing_kinds = ~0u;  // bit k: record launches of vk_kernel_kind k
   std::vector<hipEvent_t> ev;           // 2 * pool size, created on first enable
   std::vector<vk_timing_rec> recs;
   int32_t n_levels = 0;
   hipStream_t stream = nullptr;
   hipStream_t side = nullptr;       // internal stream: coarse inversion during patch setup
+  // internal stream for the patch inversions, masked to all but a few CUs (when the runtime
+  // allows it), so the side stream's one-workgroup kernels always find a free CU
+  hipStream_t setup = nullptr;
+  hipEvent_t setup_ev = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   std::vector<vk_level> lv;
   std::string err;
