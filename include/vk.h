@@ -262,16 +262,19 @@ vk_status vk_set_graphs(vk_ctx* ctx, int32_t enable);
 vk_status vk_graph_stats(const vk_ctx* ctx, int64_t* captures, int64_t* launches);
 
 /* ---- per-launch timing (benchmarks) --------------------------------------
- * With timing enabled, the library brackets every launch of the kernel classes
+ * With timing enabled, the library brackets launches of the kernel classes
  * below with a pair of HIP events on the stream the launch runs on (a pool of
- * 16384 pairs; launches beyond it are not recorded).  vk_timing_enable(ctx, 1, l)
- * clears earlier records and records launches on level l only (l = -1: all
- * levels); enable = 0 stops recording.  vk_timing_kinds restricts recording to
- * the classes whose bit (1 << kind) is set in `mask` (default: all); each
- * recorded launch costs two event records, so a benchmark records only what it
- * reads.  vk_timing_read synchronises the streams and returns the number of
- * recorded launches of class `kind` on level l (l = -1: all levels) and their
- * summed duration in milliseconds. */
+ * 16384 pairs; launches beyond it are not recorded).  The patch GEMV takes the
+ * events in its launch (hipExtLaunchKernel), so its pair holds the kernel's own
+ * start and end; the other classes are bracketed by event records.
+ * vk_timing_enable(ctx, 1, l) clears earlier records and records launches on
+ * level l only (l = -1: all levels); enable = 0 stops recording.
+ * vk_timing_kinds restricts recording to the classes whose bit (1 << kind) is
+ * set in `mask` and to one of every `every` (>= 1) such launches (default: all
+ * classes, every launch); recording slows the stream, so a benchmark records a
+ * sample of what it reads.  vk_timing_read synchronises the streams and returns
+ * the number of recorded launches of class `kind` on level l (l = -1: all
+ * levels) and their summed duration in milliseconds. */
 typedef enum {
   VK_KERNEL_PATCH_APPLY = 0,    /* gather - patch GEMV - scatter, one colour */
   VK_KERNEL_SPMV = 1,           /* level defect b - J d */
@@ -281,7 +284,7 @@ typedef enum {
   VK_KERNEL_DOF_GATHER = 5      /* d += omega z / p from the y_K (additive, DoF gather) */
 } vk_kernel_kind;
 vk_status vk_timing_enable(vk_ctx* ctx, int32_t enable, int32_t level);
-vk_status vk_timing_kinds(vk_ctx* ctx, uint32_t mask);
+vk_status vk_timing_kinds(vk_ctx* ctx, uint32_t mask, int32_t every);
 vk_status vk_timing_read(vk_ctx* ctx, int32_t kind, int32_t l, int64_t* launches, double* total_ms);
 
 #ifdef __cplusplus

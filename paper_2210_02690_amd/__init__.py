@@ -77,7 +77,7 @@ _SIGS = {
                                            _PI64]),
     "vk_set_segments": (ctypes.c_int, [_P, _I32, _PI64]),
     "gmres_solve_batched": (ctypes.c_int, [_P, _P, _P, _I32, _I32, _D, _D, _I32, _I32, _PI32, _PD, _PI32]),
-    "vk_timing_kinds": (ctypes.c_int, [_P, ctypes.c_uint32]),
+    "vk_timing_kinds": (ctypes.c_int, [_P, ctypes.c_uint32, _I32]),
     "vk_timing_read": (ctypes.c_int, [_P, _I32, _I32, _PI64, _PD]),
     # learned initial guess (vk_mlp.h)
     "vk_mlp_create": (ctypes.c_int, [ctypes.POINTER(_P), _I32, _I32, _I32, _I32, _I32, _P]),
@@ -346,10 +346,10 @@ class Solver:
     def vk_timing_enable(self, enable=True, level=-1):
         self._check(_lib.vk_timing_enable(self.ctx, 1 if enable else 0, level))
 
-    def vk_timing_kinds(self, kinds=None):
-        """Record only these kernel classes (names of KERNEL_KINDS); None: all."""
+    def vk_timing_kinds(self, kinds=None, every=1):
+        """Record only these kernel classes (names of KERNEL_KINDS; None: all), one launch in `every`."""
         mask = 0xFFFFFFFF if kinds is None else sum(1 << KERNEL_KINDS[k] for k in kinds)
-        self._check(_lib.vk_timing_kinds(self.ctx, mask))
+        self._check(_lib.vk_timing_kinds(self.ctx, mask, every))
 
     def vk_timing_read(self, kind, l=-1):
         cnt, ms = _I64(0), _D(0.0)

@@ -177,20 +177,28 @@ vk_status upload_tables(vk_ctx* ctx) {
 constexpr int32_t kTimingPool = 16384;
 
 // Brackets one launch with a pair of events when timing is on.
+// Brackets one launch with a pair of timing events.  With `in_launch`, the launch itself takes the
+// events (start() / stop() to hipExtLaunchKernel), which times the kernel alone and adds no
+// packets to the stream.
 struct Timed {
   vk_ctx* ctx;
   hipStream_t stream;
+  bool in_launch;
   int32_t slot = -1;
-  Timed(vk_ctx* c, int32_t kind, int32_t level, hipStream_t s = nullptr) : ctx(c), stream(s ? s : c->stream) {
+  Timed(vk_ctx* c, int32_t kind, int32_t level, hipStream_t s = nullptr, bool launch_events = false)
+      : ctx(c), stream(s ? s : c->stream), in_launch(launch_events) {
     if (!ctx->timing || (int32_t)ctx->recs.size() >= kTimingPool) return;
     if (ctx->timing_level >= 0 && level != ctx->timing_level) return;
     if (!((ctx->timing_kinds >> kind) & 1u)) return;
+    if (ctx->timing_seen++ % ctx->timing_every != 0) return;
     slot = (int32_t)ctx->recs.size();
     ctx->recs.push_back({kind, level, slot});
-    (void)hipEventRecord(ctx->ev[2 * slot], stream);
+    if (!in_launch) (void)hipEventRecord(ctx->ev[2 * slot], stream);
   }
+  hipEvent_t start() const { return slot >= 0 ? ctx->ev[2 * slot] : nullptr; }
+  hipEvent_t stop() const { return slot >= 0 ? ctx->ev[2 * slot + 1] : nullptr; }
   ~Timed() {
-    if (slot >= 0) (void)hipEventRecord(ctx->ev[2 * slot + 1], stream);
+    if (slot >= 0 && !in_launch) (void)hipEventRecord(ctx->ev[2 * slot + 1], stream);
   }
 };
 
@@ -208,8 +216,8 @@ vk_status smooth(vk_ctx* ctx, int l, const double* b, double* d, int32_t sweeps,
       }
       if (ctx->sweep_variant == 0) {
         for (const vk_group& G : L.groups) {
-          Timed t(ctx, VK_KERNEL_PATCH_GEMV, l);
-          VK_TRY(launch_patch_gemv(s, G, ctx->prec, r, ctx->Y));
+          Timed t(ctx, VK_KERNEL_PATCH_GEMV, l, s, true);
+          VK_TRY(launch_patch_gemv(s, G, ctx->prec, r, ctx->Y, 0, t.start(), t.stop()));
         }
         Timed t(ctx, VK_KERNEL_DOF_GATHER, l);
         VK_TRY(launch_dof_gather(s, L, ctx->prec, ctx->Y, ctx->omega, d));
@@ -1099,15 +1107,18 @@ vk_status vk_timing_enable(vk_ctx* ctx, int32_t enable, int32_t level) {
     }
     VK_TRY(hipStreamSynchronize(ctx->stream));
     ctx->recs.clear();
+    ctx->timing_seen = 0;
   }
   ctx->timing = enable != 0;
   ctx->timing_level = level;
   return VK_OK;
 }
 
-vk_status vk_timing_kinds(vk_ctx* ctx, uint32_t mask) {
+vk_status vk_timing_kinds(vk_ctx* ctx, uint32_t mask, int32_t every) {
   if (!ctx) return VK_ERR_ARG;
+  if (every < 1) return fail(ctx, VK_ERR_ARG, "every must be >= 1");
   ctx->timing_kinds = mask;
+  ctx->timing_every = every;
   return VK_OK;
 }
 

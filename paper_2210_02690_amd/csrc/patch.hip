@@ -12,6 +12,8 @@
 // A thread owns VW consecutive rows of a column (one 16-byte load) and walks
 // the columns of its column group, so consecutive threads read consecutive
 // addresses of the same column.
+#include <hip/hip_ext.h>
+
 #include "vk_internal.h"
 
 namespace {
@@ -945,13 +947,20 @@ __global__ void dof_sort_kernel(int64_t n, const int32_t* __restrict__ off, int3
 }
 
 template <int P>
-hipError_t gemv_prec(hipStream_t s, const vk_group& L, int cpb, const double* r, void* Y) {
+hipError_t gemv_prec(hipStream_t s, const vk_group& L, int cpb, const double* r, void* Y, hipEvent_t ev0,
+                     hipEvent_t ev1) {
   using A = typename PT<P>::A;
   constexpr int VW = PT<P>::VW;
   const unsigned grid = (unsigned)((L.n_cells + cpb - 1) / cpb);
   const size_t lds = (size_t)cpb * L.n_K * sizeof(A) + (size_t)VK_NT * VW * sizeof(A);
-  patch_gemv_kernel<P><<<grid, VK_NT, lds, s>>>(L.inv, L.ld, L.cell_stride, L.n_K, L.n_cells, L.cell_dofs, r,
-                                                reinterpret_cast<A*>(Y) + L.y_off, cpb);
+  A* y = reinterpret_cast<A*>(Y) + L.y_off;
+  if (ev0 || ev1)  // the kernel's own start and end times go to the events (no extra packets)
+    hipExtLaunchKernelGGL(patch_gemv_kernel<P>, dim3(grid), dim3(VK_NT), (uint32_t)lds, s, ev0, ev1, 0u,
+                          (const void*)L.inv, (int32_t)L.ld, (int64_t)L.cell_stride, (int32_t)L.n_K,
+                          (int32_t)L.n_cells, (const int32_t*)L.cell_dofs, r, y, (int32_t)cpb);
+  else
+    patch_gemv_kernel<P><<<grid, VK_NT, lds, s>>>(L.inv, L.ld, L.cell_stride, L.n_K, L.n_cells, L.cell_dofs, r, y,
+                                                  cpb);
   return hipGetLastError();
 }
 
@@ -990,14 +999,15 @@ hipError_t launch_dof_map(hipStream_t s, const vk_level& L, int32_t* count) {
   return hipGetLastError();
 }
 
-hipError_t launch_patch_gemv(hipStream_t s, const vk_group& G, vk_prec prec, const double* r, void* Y, int cpb) {
+hipError_t launch_patch_gemv(hipStream_t s, const vk_group& G, vk_prec prec, const double* r, void* Y, int cpb,
+                             hipEvent_t ev0, hipEvent_t ev1) {
   if (G.n_cells == 0) return hipSuccess;
   if (cpb <= 0)
     cpb = G.cpb_override > 0 ? G.cpb_override : (G.cpb_tuned > 0 ? G.cpb_tuned : vk_default_cpb(G.n_K, G.ld, prec));
   switch (prec) {
-    case VK_F64: return gemv_prec<VK_F64>(s, G, cpb, r, Y);
-    case VK_F32: return gemv_prec<VK_F32>(s, G, cpb, r, Y);
-    default: return gemv_prec<VK_BF16>(s, G, cpb, r, Y);
+    case VK_F64: return gemv_prec<VK_F64>(s, G, cpb, r, Y, ev0, ev1);
+    case VK_F32: return gemv_prec<VK_F32>(s, G, cpb, r, Y, ev0, ev1);
+    default: return gemv_prec<VK_BF16>(s, G, cpb, r, Y, ev0, ev1);
   }
 }
 

@@ -124,6 +124,8 @@ struct vk_ctx {
   bool timing = false;
   int32_t timing_level = -1;
   uint32_t timing_kinds = ~0u;  // bit k: record launches of vk_kernel_kind k
+  int32_t timing_every = 1;      // record one of every timing_every eligible launches
+  int64_t timing_seen = 0;       // eligible launches since timing was enabled
   std::vector<hipEvent_t> ev;           // 2 * pool size, created on first enable
   std::vector<vk_timing_rec> recs;
   int32_t n_levels = 0;
@@ -222,7 +224,9 @@ hipError_t launch_patch_apply(hipStream_t s, const vk_group& G, vk_prec prec, in
 hipError_t launch_patch_residual(hipStream_t s, const vk_csr& J, int lpr, const vk_group& G, int32_t colour,
                                  const double* b, const double* d, double* rK);
 hipError_t launch_patch_export(hipStream_t s, const vk_group& G, vk_prec prec, int32_t cell0, int32_t n, double* out);
-hipError_t launch_patch_gemv(hipStream_t s, const vk_group& G, vk_prec prec, const double* r, void* Y, int cpb = 0);
+// ev0 / ev1 (may be null): events that take the kernel's start and end times
+hipError_t launch_patch_gemv(hipStream_t s, const vk_group& G, vk_prec prec, const double* r, void* Y, int cpb = 0,
+                             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_dof_gather(hipStream_t s, const vk_level& L, vk_prec prec, const void* Y, double omega, double* d);
 int vk_default_cpb(int32_t n_K, int32_t ld, vk_prec prec);
 int vk_prec_vw(vk_prec prec);
