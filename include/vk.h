@@ -162,7 +162,7 @@ vk_status vk_set_workspace(vk_ctx* ctx, void* dev, size_t bytes, vk_prec prec, i
  * under-relaxation of Eq. 3.4 (the paper uses 0.7).
  * On a zero pivot in a patch returns VK_ERR_SINGULAR with *bad_level /
  * *bad_cell (host, may be NULL) naming the first failing level and cell.
- * The patch inversions run on an internal stream restricted to 15/16 of the
+ * The patch inversions run on an internal stream restricted to 3/4 of the
  * CUs (when the runtime supports CU masks), which the context's stream waits
  * for; vanka_setup synchronises for them only.  The inversion of the
  * directly solved blocks (the coarse matrix) keeps running on a second internal
