@@ -48,6 +48,22 @@ template <> __device__ inline void load_vec<VK_BF16>(const uint16_t* p, float* a
   a[4] = bf16_lo(v.z); a[5] = bf16_hi(v.z); a[6] = bf16_lo(v.w); a[7] = bf16_hi(v.w);
 }
 
+// the same 16 bytes as load_vec, loaded raw (so the load can stay in flight across a barrier)
+// and converted later
+template <int P> __device__ inline void cvt_vec(uint4 v, typename PT<P>::A* a);
+template <> __device__ inline void cvt_vec<VK_F64>(uint4 v, double* a) {
+  const double2 d = __builtin_bit_cast(double2, v);
+  a[0] = d.x; a[1] = d.y;
+}
+template <> __device__ inline void cvt_vec<VK_F32>(uint4 v, float* a) {
+  const float4 f = __builtin_bit_cast(float4, v);
+  a[0] = f.x; a[1] = f.y; a[2] = f.z; a[3] = f.w;
+}
+template <> __device__ inline void cvt_vec<VK_BF16>(uint4 v, float* a) {
+  a[0] = bf16_lo(v.x); a[1] = bf16_hi(v.x); a[2] = bf16_lo(v.y); a[3] = bf16_hi(v.y);
+  a[4] = bf16_lo(v.z); a[5] = bf16_hi(v.z); a[6] = bf16_lo(v.w); a[7] = bf16_hi(v.w);
+}
+
 template <int P> __device__ inline typename PT<P>::S store_cvt(double v);
 template <> __device__ inline double store_cvt<VK_F64>(double v) { return v; }
 template <> __device__ inline float store_cvt<VK_F32>(double v) { return (float)v; }
@@ -847,19 +863,44 @@ __global__ __launch_bounds__(VK_NT) void patch_gemv_kernel(const void* __restric
   const int slot = threadIdx.x / tpc, t = threadIdx.x - slot * tpc;
   const int64_t K = (int64_t)xcd_block(blockIdx.x, gridDim.x) * cpb + slot;
   const bool valid = K < n_cells;
-  for (int j = t; j < n_K; j += tpc) srk[slot * n_K + j] = valid ? (A)r[cell_dofs[K * n_K + j]] : (A)0;
-  __syncthreads();
   const int vpc = ld / VW;
   const int G = tpc / vpc;
   const int g = t / vpc, v = t - g * vpc;
+  const bool act = valid && g < G;
+  const S* base = reinterpret_cast<const S*>(inv_) + K * cell_stride + v * VW;
+  // The first PF columns of this thread's share of A_K are requested before the defect gather,
+  // so the stream of inverses starts at once instead of after the gather's two dependent
+  // round trips.  Columns past n_K re-read column n_K - 1 (inside the cell's inverse) and are
+  // not used.
+  constexpr int PF = 8;  // 16 measured slower (registers / occupancy)
+  uint4 pre[PF];
+  if (act) {
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int j = g + q * G < n_K ? g + q * G : n_K - 1;
+      pre[q] = *reinterpret_cast<const uint4*>(base + (int64_t)j * ld);
+    }
+  }
+  for (int j = t; j < n_K; j += tpc) srk[slot * n_K + j] = valid ? (A)r[cell_dofs[K * n_K + j]] : (A)0;
+  __syncthreads();
   A acc[VW];
 #pragma unroll
   for (int e = 0; e < VW; ++e) acc[e] = (A)0;
-  if (valid && g < G) {
-    const S* base = reinterpret_cast<const S*>(inv_) + K * cell_stride + v * VW;
+  if (act) {
     const A* rk = srk + slot * n_K;
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int j = g + q * G;
+      if (j < n_K) {
+        A a[VW];
+        cvt_vec<P>(pre[q], a);
+        const A rj = rk[j];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) acc[e] = fma(a[e], rj, acc[e]);
+      }
+    }
 #pragma unroll 4
-    for (int j = g; j < n_K; j += G) {
+    for (int j = g + PF * G; j < n_K; j += G) {
       A a[VW];
       load_vec<P>(base + (int64_t)j * ld, a);
       const A rj = rk[j];
