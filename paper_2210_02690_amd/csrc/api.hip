@@ -205,7 +205,9 @@ struct Timed {
 vk_status smooth(vk_ctx* ctx, int l, const double* b, double* d, int32_t sweeps, bool zero) {
   vk_level& L = ctx->lv[l];
   hipStream_t s = ctx->stream;
-  if (zero) VK_TRY(launch_fill(s, L.J.n_rows, 0.0, d));
+  // from d = 0 the first additive DoF-gather sweep writes d instead of adding to a zeroed d
+  const bool write_first = zero && sweeps > 0 && ctx->mode == VK_ADDITIVE && ctx->sweep_variant == 0;
+  if (zero && !write_first) VK_TRY(launch_fill(s, L.J.n_rows, 0.0, d));
   for (int it = 0; it < sweeps; ++it) {
     if (ctx->mode == VK_ADDITIVE) {
       const double* r = b;
@@ -220,7 +222,7 @@ vk_status smooth(vk_ctx* ctx, int l, const double* b, double* d, int32_t sweeps,
           VK_TRY(launch_patch_gemv(s, G, ctx->prec, r, ctx->Y, 0, t.start(), t.stop()));
         }
         Timed t(ctx, VK_KERNEL_DOF_GATHER, l);
-        VK_TRY(launch_dof_gather(s, L, ctx->prec, ctx->Y, ctx->omega, d));
+        VK_TRY(launch_dof_gather(s, L, ctx->prec, ctx->Y, ctx->omega, d, write_first && it == 0));
       } else {
         for (const vk_group& G : L.groups)
           for (int c = 0; c < G.n_colours; ++c) {

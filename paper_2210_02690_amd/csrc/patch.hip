@@ -923,16 +923,20 @@ __global__ __launch_bounds__(VK_NT) void patch_gemv_kernel(const void* __restric
   }
 }
 
+// d[mu] += omega / p_mu * sum of the cell products at mu; with `overwrite`, d[mu] = that term
+// (the first sweep from d = 0, which then needs no zero fill; DoFs in no cell get 0)
 template <typename TY>
 __global__ __launch_bounds__(256) void dof_gather_kernel(int64_t n, const int32_t* __restrict__ off,
                                                          const int32_t* __restrict__ list,
-                                                         const TY* __restrict__ Y, double omega, double* d) {
+                                                         const TY* __restrict__ Y, double omega, double* d,
+                                                         int32_t overwrite) {
   const int64_t mu = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (mu >= n) return;
   const int32_t e0 = off[mu], e1 = off[mu + 1];
   double z = 0.0;
   for (int32_t e = e0; e < e1; ++e) z += (double)Y[list[e]];
-  if (e1 > e0) d[mu] += omega * z / (double)(e1 - e0);
+  if (overwrite) d[mu] = e1 > e0 ? omega * z / (double)(e1 - e0) : 0.0;
+  else if (e1 > e0) d[mu] += omega * z / (double)(e1 - e0);
 }
 
 // exclusive prefix sum of count[0..n) into off[0..n] by one workgroup
@@ -1053,12 +1057,15 @@ hipError_t launch_patch_gemv(hipStream_t s, const vk_group& G, vk_prec prec, con
 }
 
 hipError_t launch_dof_gather(hipStream_t s, const vk_level& L, vk_prec prec, const void* Y, double omega,
-                             double* d) {
+                             double* d, bool overwrite) {
   const int64_t n = L.J.n_rows;
   const unsigned g = (unsigned)((n + 255) / 256);
+  const int32_t ow = overwrite ? 1 : 0;
   if (prec == VK_F64)
-    dof_gather_kernel<double><<<g, 256, 0, s>>>(n, L.dof_off, L.dof_list, reinterpret_cast<const double*>(Y), omega, d);
+    dof_gather_kernel<double><<<g, 256, 0, s>>>(n, L.dof_off, L.dof_list, reinterpret_cast<const double*>(Y), omega, d,
+                                                 ow);
   else
-    dof_gather_kernel<float><<<g, 256, 0, s>>>(n, L.dof_off, L.dof_list, reinterpret_cast<const float*>(Y), omega, d);
+    dof_gather_kernel<float><<<g, 256, 0, s>>>(n, L.dof_off, L.dof_list, reinterpret_cast<const float*>(Y), omega, d,
+                                                ow);
   return hipGetLastError();
 }

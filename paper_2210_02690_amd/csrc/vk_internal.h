@@ -227,7 +227,9 @@ hipError_t launch_patch_export(hipStream_t s, const vk_group& G, vk_prec prec, i
 // ev0 / ev1 (may be null): events that take the kernel's start and end times
 hipError_t launch_patch_gemv(hipStream_t s, const vk_group& G, vk_prec prec, const double* r, void* Y, int cpb = 0,
                              hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-hipError_t launch_dof_gather(hipStream_t s, const vk_level& L, vk_prec prec, const void* Y, double omega, double* d);
+// d += omega / p * (sum of the cell products); overwrite: d = that term
+hipError_t launch_dof_gather(hipStream_t s, const vk_level& L, vk_prec prec, const void* Y, double omega, double* d,
+                             bool overwrite = false);
 int vk_default_cpb(int32_t n_K, int32_t ld, vk_prec prec);
 int vk_prec_vw(vk_prec prec);
 int vk_prec_bytes(vk_prec prec);
