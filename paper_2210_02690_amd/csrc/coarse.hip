@@ -369,8 +369,19 @@ __global__ __launch_bounds__(256) void block_apply_kernel(int n_blocks, const in
   const int64_t r0 = rows[b], n = rows[b + 1] - r0, k = r - r0;
   const int32_t* q = q_all + r0;
   const double* w = W_ + woff[b] + (int64_t)q[k] * n;
-  double s = 0.0;
-  for (int64_t j = lane; j < n; j += 64) s = fma(w[j], x[r0 + q[j]], s);
+  // four independent (q, x[q], w) load chains in flight per lane
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t j = lane;
+  for (; j + 192 < n; j += 256) {
+    const int32_t q0 = q[j], q1 = q[j + 64], q2 = q[j + 128], q3 = q[j + 192];
+    const double w0 = w[j], w1 = w[j + 64], w2 = w[j + 128], w3 = w[j + 192];
+    s0 = fma(w0, x[r0 + q0], s0);
+    s1 = fma(w1, x[r0 + q1], s1);
+    s2 = fma(w2, x[r0 + q2], s2);
+    s3 = fma(w3, x[r0 + q3], s3);
+  }
+  for (; j < n; j += 64) s0 = fma(w[j], x[r0 + q[j]], s0);
+  double s = (s0 + s1) + (s2 + s3);
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
   if (lane == 0) y[r] = s;
 }
