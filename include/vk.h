@@ -253,8 +253,10 @@ vk_status vk_autotune(vk_ctx* ctx, int32_t reps);
  * on the context's stream afterwards; vcycle records one graph per (b, x,
  * nu_pre, nu_post).  Any call that changes what a graph has baked in (levels,
  * segments, workspace, vanka_setup, tiles, autotuning, sweep variant, timing)
- * makes the next step record again.  Results equal the eager launches bit for
- * bit (the same kernels with the same arguments run in the same order).
+ * makes the next step record again.  A step that starts while the last
+ * vanka_setup's coarse inversion is still running runs eagerly (so it overlaps
+ * the inversion).  Results equal the eager launches bit for bit (the same
+ * kernels with the same arguments run in the same order).
  * Recording needs a second stream, created by the first enable.  While timing
  * is enabled, launches are eager.  vk_graph_stats returns the number of
  * recordings and replays since vk_create. */

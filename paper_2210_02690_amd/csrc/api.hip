@@ -311,7 +311,9 @@ vk_status read_scalars(vk_ctx* ctx, const double* dev, int count, double* out) {
 template <class F>
 vk_status replay(vk_ctx* ctx, size_t slot, const int64_t (&key)[6], F&& enqueue) {
   if (!ctx->graphs || ctx->timing) return enqueue();
-  VK_CHECK(coarse_wait(ctx, false));  // outside the recording: an ordinary wait on the caller's stream
+  // While the last setup's block inversion is still running, the step runs eagerly: its work up to
+  // the coarse solve then overlaps the inversion (a replay would have to wait for it first).
+  if (ctx->coarse_pending) return enqueue();
   if (ctx->gslots.size() <= slot) ctx->gslots.resize(slot + 1);
   vk_ctx::graph_slot& g = ctx->gslots[slot];
   const bool hit = g.exec && g.gen == ctx->gen && std::equal(key, key + 6, g.key);

@@ -131,8 +131,8 @@ struct vk_ctx {
   int32_t n_levels = 0;
   hipStream_t stream = nullptr;
   hipStream_t side = nullptr;       // internal stream: coarse inversion during patch setup
-  // internal stream for the patch inversions, masked to all but a few CUs (when the runtime
-  // allows it), so the side stream's one-workgroup kernels always find a free CU
+  // internal stream for the patch inversions, masked to 3/4 of the CUs (when the runtime allows
+  // it), so they do not hold back the side stream's short block-inversion launches
   hipStream_t setup = nullptr;
   hipEvent_t setup_ev = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;

@@ -76,8 +76,9 @@ def test_graph_gmres_replays_equal_eager(vk, cfg0, prec):
         np.testing.assert_array_equal(hist, hist_e)
         np.testing.assert_array_equal(x.cpu().numpy(), xe)
         eager_noise()
+    # after each setup the first Arnoldi step runs eagerly (it overlaps the coarse inversion)
     captures, launches = S.vk_graph_stats()
-    assert captures == its_e and launches == 4 * its_e, (captures, launches, its_e)
+    assert captures == its_e - 1 and launches == 4 * (its_e - 1), (captures, launches, its_e)
     S.close()
 
 
