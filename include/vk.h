@@ -227,9 +227,17 @@ vk_status vk_patch_layout(const vk_ctx* ctx, int32_t l, int64_t* bytes_per_cell,
  *   cells, a second forms z_mu = sum over the cells containing mu of their y
  *   entry (ascending cell order) and d_mu += omega z_mu / p_mu.  Deterministic;
  *   needs no colouring.
+ *   The per-DoF cell lists are read at a fixed width (4 or 8 entries) when no
+ *   DoF lies in more than 8 cells, else through offsets.
  * VK_SWEEP_COLOURED_SCATTER: one launch per colour, each cell adding
- *   omega y_K / p to its DoFs directly (cells of a colour share no DoF). */
-typedef enum { VK_SWEEP_DOF_GATHER = 0, VK_SWEEP_COLOURED_SCATTER = 1 } vk_sweep_variant;
+ *   omega y_K / p to its DoFs directly (cells of a colour share no DoF).
+ * VK_SWEEP_DOF_GATHER_OFFSETS: as VK_SWEEP_DOF_GATHER, always through the
+ *   offsets (the same sums in the same order; for comparison). */
+typedef enum {
+  VK_SWEEP_DOF_GATHER = 0,
+  VK_SWEEP_COLOURED_SCATTER = 1,
+  VK_SWEEP_DOF_GATHER_OFFSETS = 2
+} vk_sweep_variant;
 vk_status vk_set_sweep_variant(vk_ctx* ctx, int32_t variant);
 
 /* Patch inversion kernel used by vanka_setup: 0 (default) keeps one patch row

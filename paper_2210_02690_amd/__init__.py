@@ -98,7 +98,7 @@ _SIGS = {
 }
 KERNEL_KINDS = {"patch_apply": 0, "spmv": 1, "patch_setup": 2, "patch_residual": 3, "patch_gemv": 4,
                 "dof_gather": 5}
-SWEEP_VARIANTS = {"dof_gather": 0, "coloured_scatter": 1}
+SWEEP_VARIANTS = {"dof_gather": 0, "coloured_scatter": 1, "dof_gather_offsets": 2}
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
     _f.restype = _res

@@ -96,6 +96,7 @@ size_t plan_workspace(vk_ctx* ctx, vk_prec prec, int32_t restart, char* base) {
       L.inv_p = cv.take<double>(n);
       L.dof_off = cv.take<int32_t>(n + 1);
       L.dof_list = cv.take<int32_t>(L.n_items > 0 ? L.n_items : 1);
+      L.dof_ell = cv.take<int32_t>(8 * n);
       if (L.n_items > ycount) ycount = L.n_items;
     }
     for (vk_group& G : L.groups) {
@@ -206,7 +207,8 @@ vk_status smooth(vk_ctx* ctx, int l, const double* b, double* d, int32_t sweeps,
   vk_level& L = ctx->lv[l];
   hipStream_t s = ctx->stream;
   // from d = 0 the first additive DoF-gather sweep writes d instead of adding to a zeroed d
-  const bool write_first = zero && sweeps > 0 && ctx->mode == VK_ADDITIVE && ctx->sweep_variant == 0;
+  const bool gather = ctx->sweep_variant != VK_SWEEP_COLOURED_SCATTER;
+  const bool write_first = zero && sweeps > 0 && ctx->mode == VK_ADDITIVE && gather;
   if (zero && !write_first) VK_TRY(launch_fill(s, L.J.n_rows, 0.0, d));
   for (int it = 0; it < sweeps; ++it) {
     if (ctx->mode == VK_ADDITIVE) {
@@ -216,13 +218,14 @@ vk_status smooth(vk_ctx* ctx, int l, const double* b, double* d, int32_t sweeps,
         VK_TRY(launch_spmv(s, L.J, L.lpr_J, -1.0, d, 1.0, b, L.r));
         r = L.r;
       }
-      if (ctx->sweep_variant == 0) {
+      if (gather) {
         for (const vk_group& G : L.groups) {
           Timed t(ctx, VK_KERNEL_PATCH_GEMV, l, s, true);
           VK_TRY(launch_patch_gemv(s, G, ctx->prec, r, ctx->Y, 0, t.start(), t.stop()));
         }
         Timed t(ctx, VK_KERNEL_DOF_GATHER, l);
-        VK_TRY(launch_dof_gather(s, L, ctx->prec, ctx->Y, ctx->omega, d, write_first && it == 0));
+        VK_TRY(launch_dof_gather(s, L, ctx->prec, ctx->Y, ctx->omega, d, write_first && it == 0,
+                                 ctx->sweep_variant == VK_SWEEP_DOF_GATHER));
       } else {
         for (const vk_group& G : L.groups)
           for (int c = 0; c < G.n_colours; ++c) {
@@ -687,6 +690,7 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
   for (const vk_level& L : ctx->lv) old_W.push_back(L.cb_W);
   hipStream_t s = ctx->stream;
   // status words: [0] directly solved blocks (pivot), [1] block coupling, [64 + l] first singular cell of level l
+  // ([600 + l] the largest DoF multiplicity of level l, [1000] the input validation flag)
   VK_TRY(launch_fill_i32(s, 2, INT_MAX, ctx->status));
   VK_TRY(launch_fill_i32(s, 1, 0, ctx->status + 1));
   VK_TRY(launch_fill_i32(s, 64, INT_MAX, ctx->status + 64));
@@ -706,6 +710,19 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
       for (const vk_group& G : L.groups) VK_TRY(launch_count_add(ps, G.n_cells, G.n_K, G.cell_dofs, count));
       VK_TRY(launch_inv_count(ps, L.J.n_rows, count, L.inv_p));
       VK_TRY(launch_dof_map(ps, L, count));
+    }
+    // fixed-width lists when every DoF lies in at most 8 cells (status words [600 + l]: the
+    // largest multiplicity of level l); read once per mesh
+    VK_TRY(launch_fill_i32(ps, 64, 0, ctx->status + 600));
+    for (int l = 1; l < ctx->n_levels; ++l)
+      if (!ctx->lv[l].groups.empty()) VK_TRY(launch_dof_max_count(ps, ctx->lv[l], ctx->status + 600 + l));
+    VK_TRY(hipStreamSynchronize(ps));
+    int32_t mc[64];
+    VK_CHECK(to_host(ctx, mc, ctx->status + 600, sizeof(mc)));
+    for (int l = 1; l < ctx->n_levels; ++l) {
+      vk_level& L = ctx->lv[l];
+      L.ell_w = L.groups.empty() ? 0 : (mc[l] <= 4 ? 4 : (mc[l] <= 8 ? 8 : 0));
+      if (L.ell_w > 0) VK_TRY(launch_dof_ell(ps, L));
     }
   }
   for (int l = 1; l < ctx->n_levels; ++l) {
@@ -1073,7 +1090,7 @@ vk_status vk_autotune(vk_ctx* ctx, int32_t reps) {
 vk_status vk_set_sweep_variant(vk_ctx* ctx, int32_t variant) {
   if (!ctx) return VK_ERR_ARG;
   ++ctx->gen;
-  if (variant != VK_SWEEP_DOF_GATHER && variant != VK_SWEEP_COLOURED_SCATTER)
+  if (variant != VK_SWEEP_DOF_GATHER && variant != VK_SWEEP_COLOURED_SCATTER && variant != VK_SWEEP_DOF_GATHER_OFFSETS)
     return fail(ctx, VK_ERR_ARG, "unknown sweep variant");
   ctx->sweep_variant = variant;
   return VK_OK;

@@ -276,8 +276,10 @@ __global__ __launch_bounds__(256) void gj_update_kernel(const int64_t* __restric
   const int64_t rb0 = rows[bk], n = rows[bk + 1] - rb0;
   const int64_t kk = (n - kc < K) ? n - kc : K;
   const int64_t ceb = ce < n ? ce : n;
-  const int64_t ct = tile_c0 + (int64_t)blockIdx.x * 64;
-  const int64_t rt = (int64_t)blockIdx.y * 64;
+  // consecutive workgroups take consecutive row tiles of one column tile (adjacent 512-byte
+  // pieces of the same columns)
+  const int64_t rt = (int64_t)blockIdx.x * 64;
+  const int64_t ct = tile_c0 + (int64_t)blockIdx.y * 64;
   if (kk <= 0 || ct >= ceb || rt >= n) return;  // uniform for the workgroup
   double* W = W_all + woff[bk];
   const int32_t* pcol = pcol_all + rb0;
@@ -285,31 +287,58 @@ __global__ __launch_bounds__(256) void gj_update_kernel(const int64_t* __restric
   const int64_t lg = g_stride > 0 ? ldg : n;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i16 = lane & 15, kq = lane >> 4;
-  const int64_t ca = ct + 16 * wave + i16;  // the column of this lane's A operand
-  const bool ca_ok = ca < ceb;
-  f64x4 acc[4];
+  // Both operands of the tile are staged in LDS once per workgroup (each wave needs all 64 rows of
+  // the W panel; loaded per wave from global memory they were read four times): sG[k][c] =
+  // G(k, tile column c), sW[k][r] = W(tile row r, kc + k), zero outside the block and beyond kk.
+  // Every load of the tile (both operands and the tile's old values) is issued before the first
+  // wait: out-of-range elements load a valid address and are replaced by zero.
+  constexpr int LP = 64 + 1;  // padded row length (doubles)
+  constexpr int Q = KMAX / 4; // elements per thread per operand
+  __shared__ double sG[KMAX][LP];
+  __shared__ double sW[KMAX][LP];
+  double gv[Q], wv[Q];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) acc[j] = (f64x4){0.0, 0.0, 0.0, 0.0};
-  // all operands of the (at most KMAX-deep) product are loaded before the first product, so the
-  // loads are in flight together
-  constexpr int KS = KMAX / 4;
-  double av[KS], bv[KS][4];
+  for (int q = 0; q < Q; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    const int k = e >> 6, c = e & 63;
+    const bool okg = k < kk && ct + c < ceb;
+    const bool okw = k < kk && rt + c < n;
+    const double g = G[okg ? k * lg + (ct + c - gc0) : 0];
+    const double w = W[okw ? (kc + k) * n + rt + c : 0];
+    gv[q] = okg ? g : 0.0;
+    wv[q] = okw ? w : 0.0;
+  }
+  // old values of this lane's 16 outputs (column c_v, row r_j), and the rows' pivot records
+  double old[4][4];
+  int32_t prow[4];
 #pragma unroll
-  for (int s4 = 0; s4 < KS; ++s4) {
-    const int64_t k = 4 * s4 + kq;
-    const bool k_ok = k < kk;
-    av[s4] = (k_ok && ca_ok) ? G[k * lg + (ca - gc0)] : 0.0;
-    const double* wk = W + (kc + (k_ok ? k : 0)) * n;
+  for (int j = 0; j < 4; ++j) {
+    const int64_t r = rt + 16 * j + i16;
+    prow[j] = pcol[r < n ? r : 0];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t r = rt + 16 * j + i16;
-      bv[s4][j] = (k_ok && r < n) ? wk[r] : 0.0;
+    for (int v = 0; v < 4; ++v) {
+      const int64_t c = ct + 16 * wave + 4 * v + kq;
+      old[v][j] = W[(c < ceb && r < n) ? c * n + r : 0];
     }
   }
 #pragma unroll
-  for (int s4 = 0; s4 < KS; ++s4)
+  for (int q = 0; q < Q; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    sG[e >> 6][e & 63] = gv[q];
+    sW[e >> 6][e & 63] = wv[q];
+  }
+  __syncthreads();
+  f64x4 acc[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s4], bv[s4][j], acc[j], 0, 0, 0);
+  for (int j = 0; j < 4; ++j) acc[j] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  constexpr int KS = KMAX / 4;
+#pragma unroll
+  for (int s4 = 0; s4 < KS; ++s4) {
+    const int k = 4 * s4 + kq;
+    const double a = sG[k][16 * wave + i16];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sW[k][16 * j + i16], acc[j], 0, 0, 0);
+  }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int64_t c = ct + 16 * wave + 4 * v + kq;
@@ -319,10 +348,9 @@ __global__ __launch_bounds__(256) void gj_update_kernel(const int64_t* __restric
     for (int j = 0; j < 4; ++j) {
       const int64_t r = rt + 16 * j + i16;
       if (r >= n) continue;
-      const int32_t u = pcol[r] - 1;
+      const int32_t u = prow[j] - 1;
       const bool zero = u >= p0 && u < p1;
-      const double old = wc[r];
-      wc[r] = (zero ? 0.0 : old) + acc[j][v];
+      wc[r] = (zero ? 0.0 : old[v][j]) + acc[j][v];
     }
   }
 }
@@ -408,7 +436,7 @@ hipError_t run_blocked(hipStream_t s, const vk_level& L, int32_t* status) {
                                                          L.cb_used, L.cb_gi, status);
       // the same steps on the outer block's other columns, before and after the panel
       if (n > NB)
-        gj_update_kernel<NB><<<dim3(1, row_tiles, nbk), 256, 0, s>>>(
+        gj_update_kernel<NB><<<dim3(row_tiles, 1, nbk), 256, 0, s>>>(
             L.d_cb_rows, L.d_cb_woff, L.cb_a, L.cb_used, k0, NB, L.cb_gi, (int64_t)NB * NBO, NBO, c0o, c0o,
             c0o + NBO, k0, k0 + NB, k0, k0 + NB, c0o);
     }

@@ -939,6 +939,52 @@ __global__ __launch_bounds__(256) void dof_gather_kernel(int64_t n, const int32_
   else if (e1 > e0) d[mu] += omega * z / (double)(e1 - e0);
 }
 
+// the same gather with each DoF's list at a fixed width W (entries -1 beyond its multiplicity):
+// one dependent load fewer than through the offsets
+template <typename TY, int W>
+__global__ __launch_bounds__(256) void dof_gather_ell_kernel(int64_t n, const int32_t* __restrict__ ell,
+                                                             const TY* __restrict__ Y, double omega, double* d,
+                                                             int32_t overwrite) {
+  const int64_t mu = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (mu >= n) return;
+  int32_t e[W];
+#pragma unroll
+  for (int q = 0; q < W / 4; ++q) {
+    const int4 v = reinterpret_cast<const int4*>(ell + mu * W)[q];
+    e[4 * q] = v.x;
+    e[4 * q + 1] = v.y;
+    e[4 * q + 2] = v.z;
+    e[4 * q + 3] = v.w;
+  }
+  double z = 0.0;
+  int cnt = 0;
+#pragma unroll
+  for (int k = 0; k < W; ++k)
+    if (e[k] >= 0) {
+      z += (double)Y[e[k]];
+      ++cnt;
+    }
+  if (overwrite) d[mu] = cnt > 0 ? omega * z / (double)cnt : 0.0;
+  else if (cnt > 0) d[mu] += omega * z / (double)cnt;
+}
+
+__global__ void dof_max_count_kernel(int64_t n, const int32_t* __restrict__ off, int32_t* max_count) {
+  int32_t m = 0;
+  for (int64_t mu = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; mu < n; mu += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t c = off[mu + 1] - off[mu];
+    m = c > m ? c : m;
+  }
+  if (m > 0) atomicMax(max_count, m);
+}
+
+__global__ void dof_ell_kernel(int64_t n, int32_t w, const int32_t* __restrict__ off, const int32_t* __restrict__ list,
+                               int32_t* ell) {
+  for (int64_t mu = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; mu < n; mu += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t e0 = off[mu], c = off[mu + 1] - e0;
+    for (int k = 0; k < w; ++k) ell[mu * w + k] = k < c ? list[e0 + k] : -1;
+  }
+}
+
 // exclusive prefix sum of count[0..n) into off[0..n] by one workgroup
 __global__ __launch_bounds__(1024) void scan_kernel(int64_t n, const int32_t* __restrict__ count, int32_t* off) {
   __shared__ int64_t part[1024];
@@ -1056,11 +1102,35 @@ hipError_t launch_patch_gemv(hipStream_t s, const vk_group& G, vk_prec prec, con
   }
 }
 
+hipError_t launch_dof_max_count(hipStream_t s, const vk_level& L, int32_t* max_count) {
+  const int64_t n = L.J.n_rows;
+  dof_max_count_kernel<<<capped_grid(n, 256, 1024), 256, 0, s>>>(n, L.dof_off, max_count);
+  return hipGetLastError();
+}
+
+hipError_t launch_dof_ell(hipStream_t s, const vk_level& L) {
+  const int64_t n = L.J.n_rows;
+  dof_ell_kernel<<<capped_grid(n, 256, 4096), 256, 0, s>>>(n, L.ell_w, L.dof_off, L.dof_list, L.dof_ell);
+  return hipGetLastError();
+}
+
 hipError_t launch_dof_gather(hipStream_t s, const vk_level& L, vk_prec prec, const void* Y, double omega,
-                             double* d, bool overwrite) {
+                             double* d, bool overwrite, bool fixed_width) {
   const int64_t n = L.J.n_rows;
   const unsigned g = (unsigned)((n + 255) / 256);
   const int32_t ow = overwrite ? 1 : 0;
+  if (fixed_width && (L.ell_w == 4 || L.ell_w == 8)) {
+    const float* yf = reinterpret_cast<const float*>(Y);
+    const double* yd = reinterpret_cast<const double*>(Y);
+    if (prec == VK_F64) {
+      if (L.ell_w == 4) dof_gather_ell_kernel<double, 4><<<g, 256, 0, s>>>(n, L.dof_ell, yd, omega, d, ow);
+      else dof_gather_ell_kernel<double, 8><<<g, 256, 0, s>>>(n, L.dof_ell, yd, omega, d, ow);
+    } else {
+      if (L.ell_w == 4) dof_gather_ell_kernel<float, 4><<<g, 256, 0, s>>>(n, L.dof_ell, yf, omega, d, ow);
+      else dof_gather_ell_kernel<float, 8><<<g, 256, 0, s>>>(n, L.dof_ell, yf, omega, d, ow);
+    }
+    return hipGetLastError();
+  }
   if (prec == VK_F64)
     dof_gather_kernel<double><<<g, 256, 0, s>>>(n, L.dof_off, L.dof_list, reinterpret_cast<const double*>(Y), omega, d,
                                                  ow);

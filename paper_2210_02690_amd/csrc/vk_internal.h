@@ -102,6 +102,8 @@ struct vk_level {
   double* inv_p = nullptr;      // 1 / multiplicity
   int32_t* dof_off = nullptr;   // DoF -> (cell, local) lists: offsets (n + 1)
   int32_t* dof_list = nullptr;  // flat indices, ascending per DoF
+  int32_t* dof_ell = nullptr;   // the same lists at a fixed width ell_w (-1 padded), n x ell_w
+  int32_t ell_w = 0;            // 4 or 8 (largest multiplicity rounded up), 0: use the offset lists
   double* b = nullptr;          // V-cycle right-hand side
   double* d = nullptr;          // V-cycle iterate
   double* r = nullptr;          // defect scratch
@@ -215,6 +217,10 @@ hipError_t launch_fill_i32(hipStream_t s, int64_t n, int32_t v, int32_t* x);
 hipError_t launch_count_add(hipStream_t s, int32_t n_cells, int32_t n_K, const int32_t* cell_dofs, int32_t* count);
 hipError_t launch_inv_count(hipStream_t s, int64_t n, const int32_t* count, double* inv_p);
 hipError_t launch_dof_map(hipStream_t s, const vk_level& L, int32_t* count);
+// largest multiplicity of the level into *max_count (atomic max; *max_count starts at 0)
+hipError_t launch_dof_max_count(hipStream_t s, const vk_level& L, int32_t* max_count);
+// the fixed-width copy of the DoF lists (L.ell_w set)
+hipError_t launch_dof_ell(hipStream_t s, const vk_level& L);
 hipError_t launch_patch_setup(hipStream_t s, const vk_csr& J, const vk_group& G, vk_prec prec, double* big_scratch,
                               int32_t big_chunk, int32_t* status);
 hipError_t launch_patch_setup_fast(hipStream_t s, const vk_csr& J, const vk_group& G, vk_prec prec, int32_t* status,
@@ -229,7 +235,7 @@ hipError_t launch_patch_gemv(hipStream_t s, const vk_group& G, vk_prec prec, con
                              hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // d += omega / p * (sum of the cell products); overwrite: d = that term
 hipError_t launch_dof_gather(hipStream_t s, const vk_level& L, vk_prec prec, const void* Y, double omega, double* d,
-                             bool overwrite = false);
+                             bool overwrite = false, bool fixed_width = true);
 int vk_default_cpb(int32_t n_K, int32_t ld, vk_prec prec);
 int vk_prec_vw(vk_prec prec);
 int vk_prec_bytes(vk_prec prec);

@@ -335,7 +335,7 @@ def test_patch_tiles_agree(vk, tile):
     assert rel(d.cpu().numpy(), H.smooth(l, b, d0, 1)) <= 1e-10
 
 
-@pytest.mark.parametrize("variant", ["dof_gather", "coloured_scatter"])
+@pytest.mark.parametrize("variant", ["dof_gather", "coloured_scatter", "dof_gather_offsets"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_sweep_variants(vk, variant, prec):
     """Both implementations of the averaged additive sweep equal the oracle's Eq. 3.5."""
@@ -352,6 +352,25 @@ def test_sweep_variants(vk, variant, prec):
         d = t(d0)
         S.vanka_smooth(l, t(b), d, 2)
         assert rel(d.cpu().numpy(), Href.smooth(l, b, d0, 2)) <= tol
+
+
+@pytest.mark.parametrize("case", ["cfg0", "box3d"])
+def test_dof_gather_widths_agree(vk, case):
+    """The fixed-width and the offset-list DoF gathers give the same sweep bit for bit (the same
+    sums in the same order); cfg0 has 4-wide lists (2D), the box 8-wide (3D)."""
+    P, _ = problem(case)
+    outs = []
+    for variant in ("dof_gather", "dof_gather_offsets"):
+        S = make_solver(vk, P, prec="f32")
+        S.vk_set_sweep_variant(variant)
+        rng = np.random.default_rng(8)
+        l = len(P.levels) - 1
+        b = rng.standard_normal(P.finest.n)
+        d = t(rng.standard_normal(P.finest.n))
+        S.vanka_smooth(l, t(b), d, 2)
+        outs.append(d.cpu().numpy())
+        S.close()
+    np.testing.assert_array_equal(outs[0], outs[1])
 
 
 @pytest.mark.parametrize("case", ["cfg0", "ragged_k2", "k3", "box3d"])
