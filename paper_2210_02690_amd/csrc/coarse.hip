@@ -110,6 +110,7 @@ __global__ __launch_bounds__(CTT) void block_panel_kernel(const int64_t* __restr
                                                           int32_t* status) {
   constexpr int NW = CTT / 64;
   static_assert(NW <= 16, "the cross-wave step reduces over one 16-lane row");
+  static_assert(R <= 32, "the used-row mask has 32 bits");
   // double-buffered by column parity: a thread that runs ahead into column j + 1 writes the
   // other buffer, and it cannot reach column j + 2 before every thread has left column j
   __shared__ double w_key[2][NW];
