@@ -79,7 +79,7 @@ template <int MB>
 __global__ __launch_bounds__(RB) void maxpy_kernel(int64_t n, const double* __restrict__ V, int64_t ldv, int32_t m,
                                                    const double* __restrict__ h, double sign, double* w) {
   __shared__ double sh[MB];
-  if (threadIdx.x < MB) sh[threadIdx.x] = threadIdx.x < m ? h[threadIdx.x] : 0.0;
+  if (threadIdx.x < MB) sh[threadIdx.x] = (int)threadIdx.x < m ? h[threadIdx.x] : 0.0;
   __syncthreads();
   for (int64_t r = (int64_t)blockIdx.x * RB + threadIdx.x; r < n; r += (int64_t)gridDim.x * RB) {
     double s = 0.0;
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(RB) void seg_maxpy_kernel(const int64_t* __restrict
                                                        double* w) {
   __shared__ double sh[MB];
   const int sg = blockIdx.y, c = blockIdx.x;
-  if (threadIdx.x < MB) sh[threadIdx.x] = threadIdx.x < m ? h[(int64_t)sg * ldh + threadIdx.x] : 0.0;
+  if (threadIdx.x < MB) sh[threadIdx.x] = (int)threadIdx.x < m ? h[(int64_t)sg * ldh + threadIdx.x] : 0.0;
   __syncthreads();
   const int64_t e = seg[sg + 1];
   for (int64_t r = seg[sg] + (int64_t)c * RB + threadIdx.x; r < e; r += (int64_t)nc * RB) {

@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void mse_kernel(int32_t batch, int32_t n_out, 
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(256) void colsum_kernel(int32_t batch, int32_t N, c
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) out[n] = red[0];

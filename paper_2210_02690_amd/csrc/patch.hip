@@ -510,7 +510,6 @@ __global__ __launch_bounds__(64 * RowCfg<N>::W) void patch_setup_rows_kernel(
   __shared__ double prow_s[N];
   __shared__ double red_abs[W];
   __shared__ int red_idx[W];
-  __shared__ int s_p;
   const int K = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int i = tid; i < N; i += NT) {

@@ -318,6 +318,33 @@ def test_timing_counts(vk):
     S.vk_timing_enable(False)
 
 
+def test_timing_kinds_and_sampling(vk):
+    """vk_timing_kinds records only the chosen classes, one launch in `every` (counting from the
+    first), and timing does not change the result."""
+    P, _ = problem("cfg0")
+    S = make_solver(vk, P)
+    l = len(P.levels) - 1
+    L = P.finest
+    d = torch.zeros(L.n, dtype=torch.float64, device=DEV)
+    S.vanka_smooth(l, t(P.b), d, 7, d_is_zero=True)
+    ref = d.cpu().numpy()
+    for every, expect in ((1, 7), (3, 3), (7, 1)):
+        S.vk_timing_kinds(["patch_gemv"], every)
+        S.vk_timing_enable(True, l)
+        d.zero_()
+        S.vanka_smooth(l, t(P.b), d, 7, d_is_zero=True)
+        n, ms = S.vk_timing_read("patch_gemv", l)
+        assert n == expect and ms > 0, (every, n)
+        assert S.vk_timing_read("spmv", l)[0] == 0 and S.vk_timing_read("dof_gather", l)[0] == 0
+        S.vk_timing_enable(False)
+        np.testing.assert_array_equal(d.cpu().numpy(), ref)
+    with pytest.raises(vk.VkError) as e:
+        S.vk_timing_kinds(["patch_gemv"], 0)
+    assert e.value.status == vk.VK_ERR_ARG
+    S.vk_timing_kinds(None)
+    S.close()
+
+
 @pytest.mark.parametrize("tile", [1, 2, 4, 8])
 def test_patch_tiles_agree(vk, tile):
     P, H = problem("ragged_k2")
