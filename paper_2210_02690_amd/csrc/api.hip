@@ -359,6 +359,7 @@ vk_status coarse_check(vk_ctx* ctx);
 vk_status coarse_wait(vk_ctx* ctx, bool check_now) {
   if (ctx->coarse_pending) {
     VK_TRY(hipStreamWaitEvent(ctx->stream, ctx->join_ev, 0));
+    for (int i = 0; i < ctx->n_xside; ++i) VK_TRY(hipStreamWaitEvent(ctx->stream, ctx->xjoin[i], 0));
     ctx->coarse_pending = false;
     ctx->coarse_check_due = true;
   }
@@ -473,6 +474,11 @@ void vk_destroy(vk_ctx* ctx) {
   }
   if (ctx->setup_ev) (void)hipEventDestroy(ctx->setup_ev);
   if (ctx->side) (void)hipStreamSynchronize(ctx->side);
+  for (size_t i = 0; i < ctx->xside.size(); ++i) {
+    (void)hipStreamSynchronize(ctx->xside[i]);
+    (void)hipStreamDestroy(ctx->xside[i]);
+    (void)hipEventDestroy(ctx->xjoin[i]);
+  }
   if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
   if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
   if (ctx->side) (void)hipStreamDestroy(ctx->side);
@@ -489,6 +495,7 @@ vk_status vk_set_level_groups(vk_ctx* ctx, int32_t l, const vk_csr* J, const vk_
   if (!ctx) return VK_ERR_ARG;
   ++ctx->gen;
   if (ctx->side) (void)hipStreamSynchronize(ctx->side);  // block inversions still reading the old setup
+  for (hipStream_t x : ctx->xside) (void)hipStreamSynchronize(x);
   if (ctx->setup) (void)hipStreamSynchronize(ctx->setup);  // and patch inversions after a failed setup
   ctx->coarse_pending = false;
   ctx->coarse_check_due = false;
@@ -633,6 +640,7 @@ vk_status vk_set_workspace(vk_ctx* ctx, void* dev, size_t bytes, vk_prec prec, i
   if (!ctx) return VK_ERR_ARG;
   ++ctx->gen;
   if (ctx->side) (void)hipStreamSynchronize(ctx->side);  // block inversions still reading the old setup
+  for (hipStream_t x : ctx->xside) (void)hipStreamSynchronize(x);
   if (ctx->setup) (void)hipStreamSynchronize(ctx->setup);  // and patch inversions after a failed setup
   ctx->coarse_pending = false;
   ctx->coarse_check_due = false;
@@ -739,11 +747,40 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
     VK_TRY(hipEventRecord(ctx->setup_ev, ps));
     VK_TRY(hipStreamWaitEvent(s, ctx->setup_ev, 0));
   }
-  // Block inversions on the side stream, concurrent with the patch inversions (enqueued after
-  // them, so the host's launch work does not hold the patch kernels back).
-  for (int l = 0; l < ctx->n_levels; ++l) {
-    vk_level& L = ctx->lv[l];
-    if (L.cb_rows.size() > 1) VK_TRY(launch_block_invert(ctx->side, L, ctx->status, &L.cb_W));
+  // Block inversions on the side streams, concurrent with the patch inversions (enqueued after
+  // them, so the host's launch work does not hold the patch kernels back).  The levels' chains are
+  // independent: one stream each, the level with the largest blocks (the longest chain) first.
+  std::vector<int> blevels;
+  for (int l = 0; l < ctx->n_levels; ++l)
+    if (ctx->lv[l].cb_rows.size() > 1) blevels.push_back(l);
+  std::stable_sort(blevels.begin(), blevels.end(),
+                   [&](int a, int b) { return ctx->lv[a].cb_max > ctx->lv[b].cb_max; });
+  ctx->n_xside = 0;
+  for (size_t k = 0; k < blevels.size(); ++k) {
+    hipStream_t st = ctx->side;
+    if (k > 0) {
+      const size_t i = k - 1;
+      if (ctx->xside.size() <= i) {
+        hipStream_t ns = nullptr;
+        hipEvent_t ne = nullptr;
+        VK_TRY(hipStreamCreateWithFlags(&ns, hipStreamNonBlocking));
+        const hipError_t e = hipEventCreateWithFlags(&ne, hipEventDisableTiming);
+        if (e != hipSuccess) {
+          (void)hipStreamDestroy(ns);
+          return fail_hip(ctx, e, "hipEventCreateWithFlags");
+        }
+        ctx->xside.push_back(ns);
+        ctx->xjoin.push_back(ne);
+      }
+      st = ctx->xside[i];
+      VK_TRY(hipStreamWaitEvent(st, ctx->fork_ev, 0));
+    }
+    vk_level& L = ctx->lv[blevels[k]];
+    VK_TRY(launch_block_invert(st, L, ctx->status, &L.cb_W));
+    if (k > 0) {
+      VK_TRY(hipEventRecord(ctx->xjoin[k - 1], st));
+      ctx->n_xside = (int)k;
+    }
   }
   VK_TRY(hipEventRecord(ctx->join_ev, ctx->side));
   for (int l = 0; l < ctx->n_levels; ++l)

@@ -138,6 +138,11 @@ struct vk_ctx {
   hipStream_t setup = nullptr;
   hipEvent_t setup_ev = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  // further side streams: the block inversions of different levels are independent chains, one
+  // stream each (created when a setup first needs them); n_xside of them belong to the last setup
+  std::vector<hipStream_t> xside;
+  std::vector<hipEvent_t> xjoin;
+  int n_xside = 0;
   std::vector<vk_level> lv;
   std::string err;
   int32_t* status = nullptr;   // device status block (4 KiB)
