@@ -295,8 +295,11 @@ __global__ __launch_bounds__(256) void gj_update_kernel(const int64_t* __restric
   // wait: out-of-range elements load a valid address and are replaced by zero.
   constexpr int LP = 64 + 1;  // padded row length (doubles)
   constexpr int Q = KMAX / 4; // elements per thread per operand
-  __shared__ double sG[KMAX][LP];
-  __shared__ double sW[KMAX][LP];
+  // the operands go through LDS in chunks of KC steps (half the LDS of the whole depth: more
+  // workgroups per CU)
+  constexpr int KC = KMAX < 32 ? KMAX : 32, QC = KC / 4;
+  __shared__ double sG[KC][LP];
+  __shared__ double sW[KC][LP];
   double gv[Q], wv[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -322,23 +325,26 @@ __global__ __launch_bounds__(256) void gj_update_kernel(const int64_t* __restric
       old[v][j] = W[(c < ceb && r < n) ? c * n + r : 0];
     }
   }
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int e = threadIdx.x + 256 * q;
-    sG[e >> 6][e & 63] = gv[q];
-    sW[e >> 6][e & 63] = wv[q];
-  }
-  __syncthreads();
   f64x4 acc[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) acc[j] = (f64x4){0.0, 0.0, 0.0, 0.0};
-  constexpr int KS = KMAX / 4;
 #pragma unroll
-  for (int s4 = 0; s4 < KS; ++s4) {
-    const int k = 4 * s4 + kq;
-    const double a = sG[k][16 * wave + i16];
+  for (int k0 = 0; k0 < KMAX; k0 += KC) {
+    if (k0 > 0) __syncthreads();  // the previous chunk's products have read the LDS
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sW[k][16 * j + i16], acc[j], 0, 0, 0);
+    for (int q = 0; q < QC; ++q) {
+      const int e = threadIdx.x + 256 * q;  // element (k0 + e / 64, e % 64)
+      sG[e >> 6][e & 63] = gv[k0 / 4 + q];
+      sW[e >> 6][e & 63] = wv[k0 / 4 + q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s4 = 0; s4 < KC / 4; ++s4) {
+      const int k = 4 * s4 + kq;
+      const double a = sG[k][16 * wave + i16];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sW[k][16 * j + i16], acc[j], 0, 0, 0);
+    }
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
