@@ -476,6 +476,28 @@ def test_coarse_solve_3d_box_size(vk):
     S.close()
 
 
+@pytest.mark.parametrize("n", [64, 256, 1024, 2048, 4096])
+def test_coarse_inverse_with_tied_pivots(vk, n):
+    """A Hadamard matrix (all entries +-1: every column's candidates tie in |a| at the first step,
+    and ties recur) through the blocked Gauss-Jordan path of each block size: its inverse is H^T / n.
+    Sizes cover one panel width and several outer blocks (64 columns each) per block kernel shape."""
+    import types
+    import scipy.linalg
+    import scipy.sparse as sp
+    H = scipy.linalg.hadamard(n).astype(np.float64)
+    lv = types.SimpleNamespace(J=sp.csr_matrix(H), P=None, R=None, cell_dofs=np.zeros((1, 1), np.int32),
+                               colours=np.zeros(1, np.int32))
+    S = vk.Solver([vk.upload_level(lv, DEV)])
+    S.vk_set_workspace("f64", 30, device=DEV)
+    S.vanka_setup(0.7, "additive")
+    out = torch.empty((n, n), dtype=torch.float64, device=DEV)
+    S.vk_get_coarse_inverse(out)
+    # H is orthogonal up to the factor n (condition number 1): a wrong or inconsistent pivot choice
+    # shows as an O(1) error or a singular-block report, rounding stays far below this bound
+    assert rel(out.cpu().numpy(), H.T / n) <= 1e-10
+    S.close()
+
+
 def test_singular_coarse_block_reported_by_the_solve(vk):
     """The block inversion overlaps the next solve: a singular coarse matrix is reported by the first
     call that applies it, and setup must run again before the next solve."""
