@@ -12,8 +12,9 @@
 // columns are contiguous; a final in-place transpose leaves W row-major for the
 // solve.
 //
-// Two levels of blocking.  The columns are taken in outer blocks of NBO = 64;
-// within an outer block, inner panels of NB columns:
+// Two levels of blocking.  The columns are taken in outer blocks of NBO = 128
+// (levels with one or a few blocks) or 64 columns; within an outer block, inner
+// panels of NB columns:
 //   panel kernel  (one workgroup per block, the panel rows in registers): the
 //                 NB elimination steps restricted to the panel's columns; it
 //                 records each new pivot row's column and copies the pivot
@@ -33,7 +34,6 @@ namespace {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-constexpr int NBO = VK_GJ_NBO;
 
 __device__ inline int block_of(const int64_t* __restrict__ rows, int nb, int64_t r) {
   int lo = 0, hi = nb;  // last block with rows[b] <= r
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(CTT) void block_panel_kernel(const int64_t* __restr
                                                           const int64_t* __restrict__ woff, int64_t k0, int64_t c0o,
                                                           double* W_all, int32_t* __restrict__ q_all,
                                                           int32_t* __restrict__ pcol_all, double* __restrict__ gi_all,
-                                                          int32_t* status) {
+                                                          int32_t nbo, int32_t* status) {
   constexpr int NW = CTT / 64;
   static_assert(NW <= 16, "the cross-wave step reduces over one 16-lane row");
   static_assert(R <= 32, "the used-row mask has 32 bits");
@@ -229,29 +229,29 @@ __global__ __launch_bounds__(CTT) void block_panel_kernel(const int64_t* __restr
     pcol_g[s_q[tid]] = (int32_t)(k0 + tid + 1);
   }
   // old values of the new pivot rows in the other columns of the outer block (this kernel
-  // writes only the panel's columns); nb * gw <= NB * NBO fits an int
-  const int64_t ge = (c0o + NBO < n ? c0o + NBO : n);
+  // writes only the panel's columns); nb * gw <= NB * nbo fits an int
+  const int64_t ge = (c0o + nbo < n ? c0o + nbo : n);
   const int gw = (int)(ge - c0o);
-  double* gi = gi_all + (int64_t)bk * NB * NBO;
+  double* gi = gi_all + (int64_t)bk * NB * nbo;
   for (int e = tid; e < nb * gw; e += CTT) {
     const int t = e / gw;
     const int64_t c = c0o + (e - t * gw);
-    if (c < k0 || c >= k0 + nb) gi[t * NBO + (c - c0o)] = W[c * n + s_q[t]];
+    if (c < k0 || c >= k0 + nb) gi[t * nbo + (c - c0o)] = W[c * n + s_q[t]];
   }
 }
 
 // old values of the outer block's pivot rows in every column: go[t][c] = W[q[c0o + t]][c]
 __global__ void gather_pivot_rows_kernel(const int64_t* __restrict__ rows, const int64_t* __restrict__ woff,
-                                         int64_t c0o, const double* __restrict__ W_all,
+                                         int64_t c0o, int32_t nbo, const double* __restrict__ W_all,
                                          const int32_t* __restrict__ q_all, double* __restrict__ go_all) {
   const int bk = blockIdx.z;
   const int64_t r0 = rows[bk], n = rows[bk + 1] - r0;
-  const int64_t kk = n - c0o < NBO ? n - c0o : NBO;
+  const int64_t kk = n - c0o < nbo ? n - c0o : nbo;
   const int t = blockIdx.y;
   if (t >= kk) return;
   const double* W = W_all + woff[bk];
   const int64_t q = q_all[r0 + c0o + t];
-  double* go = go_all + (int64_t)NBO * (r0 - rows[0]) + (int64_t)t * n;
+  double* go = go_all + (int64_t)nbo * (r0 - rows[0]) + (int64_t)t * n;
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
     go[c] = W[c * n + q];
 }
@@ -259,14 +259,16 @@ __global__ void gather_pivot_rows_kernel(const int64_t* __restrict__ rows, const
 // In-place update of columns [cb, ce) \ [sk0, sk1) of every block (blockIdx.z), W column-major:
 //   W[i, c] = (pcol[i] - 1 in [p0, p1) ? 0 : W[i, c]) + sum_{t < K} W[i, kc + t] G[t][c - gc0]
 // with K clipped to the block.  G: inner mode (g_stride > 0) block b at b * g_stride with
-// leading dimension ldg; outer mode (g_stride == 0) block b at NBO * (rows[b] - rows[0]) with
+// leading dimension ldg; outer mode (g_stride == 0) block b at K * (rows[b] - rows[0]) with
 // leading dimension n_b.  Workgroup tile 64 rows x 64 columns, wavefront w the columns
 // [16 w, 16 w + 16).  The FP64 matrix cores (16 x 16 x 4) compute the transposed tile
 // D(c, i) = sum_t G(t, c) W(i, t): lane l holds A = G(l / 16, c_0 + l % 16) and
 // B = W(i_0 + l % 16, l / 16), and accumulator element v holds D(4 v + l / 16, l % 16), so
 // lanes 0..15 own 16 consecutive rows of one column (contiguous in memory).
+// At least three workgroups per CU (three waves per SIMD) caps the registers at 168: the
+// 128-step update then spills a few bytes per lane and still runs faster than with two.
 template <int KMAX>
-__global__ __launch_bounds__(256) void gj_update_kernel(const int64_t* __restrict__ rows,
+__global__ __launch_bounds__(256, 3) void gj_update_kernel(const int64_t* __restrict__ rows,
                                                         const int64_t* __restrict__ woff, double* W_all,
                                                         const int32_t* __restrict__ pcol_all, int64_t kc, int32_t K,
                                                         const double* __restrict__ G_all, int64_t g_stride,
@@ -284,34 +286,39 @@ __global__ __launch_bounds__(256) void gj_update_kernel(const int64_t* __restric
   if (kk <= 0 || ct >= ceb || rt >= n) return;  // uniform for the workgroup
   double* W = W_all + woff[bk];
   const int32_t* pcol = pcol_all + rb0;
-  const double* G = g_stride > 0 ? G_all + (int64_t)bk * g_stride : G_all + (int64_t)NBO * (rb0 - rows[0]);
+  const double* G = g_stride > 0 ? G_all + (int64_t)bk * g_stride : G_all + (int64_t)K * (rb0 - rows[0]);
   const int64_t lg = g_stride > 0 ? ldg : n;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i16 = lane & 15, kq = lane >> 4;
   // Both operands of the tile are staged in LDS once per workgroup (each wave needs all 64 rows of
   // the W panel; loaded per wave from global memory they were read four times): sG[k][c] =
   // G(k, tile column c), sW[k][r] = W(tile row r, kc + k), zero outside the block and beyond kk.
-  // Every load of the tile (both operands and the tile's old values) is issued before the first
+  // The first chunk's operand loads and the tile's old values are all issued before the first
   // wait: out-of-range elements load a valid address and are replaced by zero.
   constexpr int LP = 64 + 1;  // padded row length (doubles)
-  constexpr int Q = KMAX / 4; // elements per thread per operand
-  // the operands go through LDS in chunks of KC steps (half the LDS of the whole depth: more
-  // workgroups per CU)
-  constexpr int KC = KMAX < 32 ? KMAX : 32, QC = KC / 4;
+  // The operands go through LDS in chunks of KC steps (more workgroups per CU than the whole
+  // depth would allow).  Up to 64 steps all operand loads are issued up front (QL = Q); deeper
+  // updates load each chunk while the previous one is multiplied (QL = QC registers per operand).
+  constexpr int KC = KMAX < 32 ? KMAX : 32, QC = KC / 4;  // QC: elements per thread per operand
+  constexpr bool PIPE = KMAX > 64;
+  constexpr int QL = PIPE ? QC : KMAX / 4;
   __shared__ double sG[KC][LP];
   __shared__ double sW[KC][LP];
-  double gv[Q], wv[Q];
+  double gv[QL], wv[QL];
+  auto load = [&](int k0, int nq) {  // elements k0 * 64 + threadIdx.x + 256 q, q < nq
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int e = threadIdx.x + 256 * q;
-    const int k = e >> 6, c = e & 63;
-    const bool okg = k < kk && ct + c < ceb;
-    const bool okw = k < kk && rt + c < n;
-    const double g = G[okg ? k * lg + (ct + c - gc0) : 0];
-    const double w = W[okw ? (kc + k) * n + rt + c : 0];
-    gv[q] = okg ? g : 0.0;
-    wv[q] = okw ? w : 0.0;
-  }
+    for (int q = 0; q < nq; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      const int k = k0 + (e >> 6), c = e & 63;
+      const bool okg = k < kk && ct + c < ceb;
+      const bool okw = k < kk && rt + c < n;
+      const double g = G[okg ? k * lg + (ct + c - gc0) : 0];
+      const double w = W[okw ? (kc + k) * n + rt + c : 0];
+      gv[q] = okg ? g : 0.0;
+      wv[q] = okw ? w : 0.0;
+    }
+  };
+  load(0, QL);
   // old values of this lane's 16 outputs (column c_v, row r_j), and the rows' pivot records
   double old[4][4];
   int32_t prow[4];
@@ -334,10 +341,11 @@ __global__ __launch_bounds__(256) void gj_update_kernel(const int64_t* __restric
 #pragma unroll
     for (int q = 0; q < QC; ++q) {
       const int e = threadIdx.x + 256 * q;  // element (k0 + e / 64, e % 64)
-      sG[e >> 6][e & 63] = gv[k0 / 4 + q];
-      sW[e >> 6][e & 63] = wv[k0 / 4 + q];
+      sG[e >> 6][e & 63] = gv[PIPE ? q : k0 / 4 + q];
+      sW[e >> 6][e & 63] = wv[PIPE ? q : k0 / 4 + q];
     }
     __syncthreads();
+    if (PIPE && k0 + KC < KMAX) load(k0 + KC, QC);
 #pragma unroll
     for (int s4 = 0; s4 < KC / 4; ++s4) {
       const int k = 4 * s4 + kq;
@@ -431,24 +439,25 @@ __global__ void block_export_kernel(int64_t n, const double* __restrict__ W, con
   }
 }
 
-template <int CTT, int R, int NB>
+template <int CTT, int R, int NB, int NBO>
 hipError_t run_blocked(hipStream_t s, const vk_level& L, int32_t* status) {
-  static_assert(NBO % NB == 0 && NB <= VK_GJ_NBI_MAX, "inner panels must tile the outer block");
+  static_assert(NBO % NB == 0 && NB <= VK_GJ_NBI_MAX && NBO % 64 == 0 && NBO <= VK_GJ_NBO,
+                "inner panels must tile the outer block, whose columns come in whole 64-column tiles");
   const int nbk = (int)L.cb_rows.size() - 1;
   const int64_t n = L.cb_max;
   const unsigned row_tiles = (unsigned)((n + 63) / 64);
   for (int64_t c0o = 0; c0o < n; c0o += NBO) {
     for (int64_t k0 = c0o; k0 < c0o + NBO && k0 < n; k0 += NB) {
       block_panel_kernel<CTT, R, NB><<<nbk, CTT, 0, s>>>(L.d_cb_rows, L.d_cb_woff, k0, c0o, L.cb_a, L.cb_q,
-                                                         L.cb_used, L.cb_gi, status);
+                                                         L.cb_used, L.cb_gi, NBO, status);
       // the same steps on the outer block's other columns, before and after the panel
       if (n > NB)
-        gj_update_kernel<NB><<<dim3(row_tiles, 1, nbk), 256, 0, s>>>(
+        gj_update_kernel<NB><<<dim3(row_tiles, NBO / 64, nbk), 256, 0, s>>>(
             L.d_cb_rows, L.d_cb_woff, L.cb_a, L.cb_used, k0, NB, L.cb_gi, (int64_t)NB * NBO, NBO, c0o, c0o,
             c0o + NBO, k0, k0 + NB, k0, k0 + NB, c0o);
     }
     gather_pivot_rows_kernel<<<dim3((unsigned)((n + 255) / 256 < 64 ? (n + 255) / 256 : 64), NBO, nbk), 256, 0, s>>>(
-        L.d_cb_rows, L.d_cb_woff, c0o, L.cb_a, L.cb_q, L.cb_go);
+        L.d_cb_rows, L.d_cb_woff, c0o, NBO, L.cb_a, L.cb_q, L.cb_go);
     gj_update_kernel<NBO><<<dim3(row_tiles, row_tiles, nbk), 256, 0, s>>>(L.d_cb_rows, L.d_cb_woff, L.cb_a, L.cb_used,
                                                                      c0o, NBO, L.cb_go, 0, 0, 0, 0, n, c0o,
                                                                      c0o + NBO, c0o, c0o + NBO, 0);
@@ -477,12 +486,16 @@ hipError_t launch_block_invert(hipStream_t s, const vk_level& L, int32_t* status
   if ((e = launch_fill_i32(s, L.J.n_rows, 0, L.cb_used)) != hipSuccess) return e;
   // panel rows per thread R, panel width NB: R * NB <= 64 doubles in registers (<= 36 at
   // 1024 threads, whose waves may hold 128 registers each)
+  // outer blocks of 128 columns halve the passes of the rank-NBO updates over the blocks (HBM
+  // traffic) at twice the inner updates' width: worth it for one or a few blocks, whose updates
+  // are few workgroups wide; many blocks per level keep 64
   const int64_t m = L.cb_max;
-  if (m <= 1024) e = run_blocked<512, 2, 16>(s, L, status);
-  else if (m <= 2048) e = run_blocked<256, 8, 8>(s, L, status);
-  else if (m <= 4096) e = run_blocked<512, 8, 8>(s, L, status);
-  else if (m <= 8192) e = run_blocked<1024, 8, 4>(s, L, status);
-  else e = run_blocked<1024, 9, 4>(s, L, status);
+  const bool wide = nbk <= 8;
+  if (m <= 1024) e = wide ? run_blocked<512, 2, 16, 128>(s, L, status) : run_blocked<512, 2, 16, 64>(s, L, status);
+  else if (m <= 2048) e = wide ? run_blocked<256, 8, 8, 128>(s, L, status) : run_blocked<256, 8, 8, 64>(s, L, status);
+  else if (m <= 4096) e = wide ? run_blocked<512, 8, 8, 128>(s, L, status) : run_blocked<512, 8, 8, 64>(s, L, status);
+  else if (m <= 8192) e = wide ? run_blocked<1024, 8, 4, 128>(s, L, status) : run_blocked<1024, 8, 4, 64>(s, L, status);
+  else e = wide ? run_blocked<1024, 9, 4, 128>(s, L, status) : run_blocked<1024, 9, 4, 64>(s, L, status);
   return e;
 }
 

@@ -19,7 +19,7 @@
 #define VK_MAX_NK 512
 #define VK_MAX_RESTART 64
 // blocked Gauss-Jordan of the directly solved blocks: outer block width, widest inner panel
-#define VK_GJ_NBO 64
+#define VK_GJ_NBO 128  // widest outer block of the blocked Gauss-Jordan inversion (buffer sizes)
 #define VK_GJ_NBI_MAX 16
 
 // ---- wavefront reductions through DPP (row shifts, then row broadcasts);
