@@ -41,6 +41,12 @@ CASES = {
     "k3": ("channel2d_44x8_k1", dict(shape=(12, 4), levels=2, k=3)),
     # 3D box, Q2/P1disc hexahedra, dG(1): n_K = 170 (the box's patch width) on a small mesh
     "box3d": ("box3d_100x16x16_k1", dict(shape=(8, 4, 4), levels=2)),
+    # the other time degrees of the robustness-in-k study: 2D n_K = 21 (dG(0)) and 105 (dG(4)),
+    # 3D n_K = 85 (dG(0)) and 255 (dG(2), patches inverted through global memory)
+    "k0": ("channel2d_44x8_k1", dict(shape=(12, 4), levels=2, k=0)),
+    "k4": ("channel2d_44x8_k1", dict(shape=(12, 4), levels=2, k=4)),
+    "box3d_k0": ("box3d_100x16x16_k1", dict(shape=(8, 4, 4), levels=2, k=0)),
+    "box3d_k2": ("box3d_100x16x16_k1", dict(shape=(4, 2, 2), levels=2, k=2)),
 }
 
 _cache = {}
