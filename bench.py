@@ -365,6 +365,49 @@ def _threads():
         return 1
 
 
+def run_robustness(args, torch, vk, dev):
+    """Robustness in the time degree: one Newton linearisation per dG(k), k = 0..4 on the 88 x 16
+    channel (Q2/P1disc, n_K = 21 (k + 1)) and k = 0..2 on a 48 x 8 x 8 box (n_K = 85 (k + 1)),
+    each solved by GMRES(30) to 1e-8 with the two-plus-two-sweep V-cycle, FP64 and FP32 patch
+    inverses.  The iteration counts are what the time degree should not change."""
+    from synth import build_problem
+    cases = [("channel2d_88x16", "channel2d_88x16_k1", dict(k=k)) for k in range(5)]
+    cases += [("box3d_48x8x8", "box3d_100x16x16_k1", dict(shape=(48, 8, 8), levels=4, k=k)) for k in range(3)]
+    restart, max_iter, nu = 30, 300, (2, 2)
+    rows = []
+    for name, cfg, over in cases:
+        t0 = time.perf_counter()
+        P = build_problem(cfg, **over)
+        levels = [vk.upload_level(L, dev) for L in P.levels]
+        b = torch.from_numpy(P.b).to(dev)
+        x = torch.zeros_like(b)
+        row = {"mesh": name, "k": over["k"], "n_K": int(P.finest.mesh.n_K), "unknowns": int(P.finest.n),
+               "levels": len(P.levels), "coarse_unknowns": int(P.levels[0].n)}
+        for prec in ("f64", "f32"):
+            S = vk.Solver(levels)
+            S.vk_set_workspace(prec, restart, device=dev)
+            run_step(S, b, x, nu, restart, max_iter)  # warmup
+            setup_ms, gmres_ms, its, rel = phase_times(torch, S, b, x, nu, restart, max_iter)
+            xg = x.cpu().numpy()
+            true_rel = float(np.linalg.norm(P.b - P.finest.J @ xg) / np.linalg.norm(P.b))
+            row[prec] = {"gmres_iterations": int(its), "true_rel_residual": true_rel, "setup_ms": setup_ms,
+                         "gmres_ms_to_1e-8": gmres_ms}
+            S.close()
+        rows.append(row)
+        log(f"[bench] {name} k={over['k']} n_K={row['n_K']} n={row['unknowns']}: its f64 "
+            f"{row['f64']['gmres_iterations']} f32 {row['f32']['gmres_iterations']} "
+            f"({time.perf_counter() - t0:.1f} s)")
+        del levels, b, x
+        torch.cuda.empty_cache()
+    out = {"metric": "GMRES(30) iterations to 1e-8 rel. residual per dG(k) linearisation, Vanka V-cycle "
+                     "preconditioner (2+2 sweeps, omega 0.7)",
+           "unit": "iterations", "n_gpus": 1, "higher_is_better": False, "data": "synthetic (seeded Newton "
+           "linearisations of channel flows; no dataset)",
+           "config": {"workload": "robustness_k", "restart": restart, "nu_pre": nu[0], "nu_post": nu[1]},
+           "study": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -393,6 +436,8 @@ def main():
         return run_batch(args, torch, vk, dev)
     if args.config == "learned_guess_88x16":
         return run_learned(args, torch, vk, dev)
+    if args.config == "robustness_k":
+        return run_robustness(args, torch, vk, dev)
     if args.pmc_probe:
         return run_pmc_probe(args, torch, vk, dev)
     restart, max_iter, nu = 30, 300, (2, 2)
