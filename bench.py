@@ -408,6 +408,45 @@ def run_robustness(args, torch, vk, dev):
     print(json.dumps(out), flush=True)
 
 
+def run_newton_march(args, torch, vk, dev):
+    """Damped-Newton time marching with absolute tolerances (||F|| < 1e-8 per slab, GMRES to an
+    absolute residual of 1e-9), dG(k) for k = 0..4 on the 88 x 16 channel with the periodic
+    inflow, 20 slabs each from the extrapolated guess: Newton steps per slab and GMRES iterations
+    per Newton step, the statistics of the paper's robustness tables."""
+    from synth.march import ChannelMarch
+    from paper_2210_02690_amd.guess import NewtonMarch, ExtrapolationGuess, march
+    n_slabs = 20
+    rows = []
+    for k in range(5):
+        t0 = time.perf_counter()
+        pr = ChannelMarch(shape=(88, 16), levels=4, k=k)
+        nm = NewtonMarch(pr, device=dev, prec=args.prec, tol=1e-8, rtol=0.0, atol=1e-9)
+        slabs = [pr.initial_slab()]
+        st = march(nm, 1, n_slabs, slabs, ExtrapolationGuess(pr, dev))
+        nm.close()
+        newton = sum(s["newton"] for s in st)
+        gm = sum(s["gmres"] for s in st)
+        row = {"k": k, "n_K": int(pr.fine.mesh.n_K), "unknowns": int(pr.n), "slabs": n_slabs,
+               "newton_per_slab": newton / n_slabs, "gmres_per_newton": gm / max(newton, 1),
+               "max_newton_per_slab": max(s["newton"] for s in st),
+               "max_gmres_per_slab": max(s["gmres"] for s in st),
+               "all_converged": all(s["converged"] for s in st),
+               "final_residual_max": max(s["hist"][-1] for s in st),
+               "seconds_solve": sum(s["t_solve"] for s in st), "seconds_total": time.perf_counter() - t0}
+        rows.append(row)
+        log(f"[bench] dG({k}) n_K={row['n_K']}: {row['newton_per_slab']:.2f} Newton/slab, "
+            f"{row['gmres_per_newton']:.2f} GMRES/Newton, converged {row['all_converged']} "
+            f"({row['seconds_total']:.1f} s)")
+    out = {"metric": "Newton steps per slab and GMRES(30) iterations per Newton step, damped Newton with "
+                     "absolute tolerances (||F|| < 1e-8, GMRES 1e-9)",
+           "unit": "iterations", "n_gpus": 1, "higher_is_better": False,
+           "data": "synthetic (88 x 16 channel with a periodic inflow, marched from Poiseuille flow)",
+           "config": {"workload": "newton_march_k", "patch_precision": args.prec, "nu_pre": 2, "nu_post": 2,
+                      "omega": 0.7, "tau": 0.01},
+           "study": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -438,6 +477,8 @@ def main():
         return run_learned(args, torch, vk, dev)
     if args.config == "robustness_k":
         return run_robustness(args, torch, vk, dev)
+    if args.config == "newton_march_k":
+        return run_newton_march(args, torch, vk, dev)
     if args.pmc_probe:
         return run_pmc_probe(args, torch, vk, dev)
     restart, max_iter, nu = 30, 300, (2, 2)
