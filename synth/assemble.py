@@ -16,11 +16,14 @@ Readings of the printed formulas (all generator-side):
   * time integrals use the (k+1)-point right Radau rule of the Lagrange nodes,
     so spatial operators are diagonal in time and the blocks a != b hold only
     Kt[a, b] times the velocity mass matrix;
-  * space integrals use the 3-point Gauss rule per direction.
+  * space integrals use the 3-point Gauss rule per direction for r = 2 (exact
+    for the convection integrand, of degree 3 r - 1 per direction) and the
+    ceil(3 r / 2)-point rule for higher r.
 """
 import numpy as np
 import scipy.sparse as sp
 
+from .mesh import pressure_exponents
 from .radau import dg_time_matrices
 
 GAUSS3_S = np.array([0.5 - 0.5 * np.sqrt(0.6), 0.5, 0.5 + 0.5 * np.sqrt(0.6)])
@@ -35,6 +38,32 @@ def _q2_1d(s):
     return val, der
 
 
+def _lagrange_1d(s, r):
+    """Degree-r Lagrange basis at the equispaced nodes j / r of [0, 1] and derivatives, at s."""
+    if r == 2:
+        return _q2_1d(s)
+    s = np.asarray(s, dtype=np.float64)
+    t = np.arange(r + 1) / r
+    val = np.ones(s.shape + (r + 1,))
+    der = np.zeros(s.shape + (r + 1,))
+    for j in range(r + 1):
+        for m in range(r + 1):
+            if m == j:
+                continue
+            f = (s - t[m]) / (t[j] - t[m])
+            der[..., j] = der[..., j] * f + val[..., j] / (t[j] - t[m])
+            val[..., j] = val[..., j] * f
+    return val, der
+
+
+def gauss_rule_01(r):
+    """Gauss points and weights on [0, 1] for velocity degree r (3 points for r = 2)."""
+    if r == 2:
+        return GAUSS3_S, GAUSS3_W
+    x, w = np.polynomial.legendre.leggauss((3 * r + 1) // 2)
+    return 0.5 * (x + 1.0), 0.5 * w
+
+
 def _tensor_points(point_sets):
     """Cartesian product of per-direction point sets, first direction fastest."""
     grids = np.meshgrid(*point_sets, indexing="ij")
@@ -47,7 +76,7 @@ def tensor_basis(mesh, pts):
     off = mesh.local_node_offsets()
     vals, ders = [], []
     for i in range(d):
-        v, dv = _q2_1d(pts[:, i])
+        v, dv = _lagrange_1d(pts[:, i], mesh.r)
         vals.append(v)
         ders.append(dv / mesh.h[i])
     nq, nl = pts.shape[0], mesh.n_loc_nodes
@@ -61,23 +90,30 @@ def tensor_basis(mesh, pts):
     return phi, dphi
 
 
-def pressure_basis(pts):
-    """P1disc basis {1, x^, y^(, z^)} with x^ = 2 s - 1 on [-1, 1]^d."""
-    return np.concatenate([np.ones((pts.shape[0], 1)), 2 * pts - 1], axis=1)
+def pressure_basis(pts, r=2):
+    """P_{r-1}disc monomials in x^ = 2 s - 1 on [-1, 1]^d (numbering of `mesh.py`):
+    {1, x^, y^(, z^)} for r = 2."""
+    if r == 2:
+        return np.concatenate([np.ones((pts.shape[0], 1)), 2 * pts - 1], axis=1)
+    x = 2 * pts - 1
+    return np.stack([np.prod(x ** np.array(e)[None, :], axis=1) for e in pressure_exponents(pts.shape[1], r)],
+                    axis=1)
 
 
 def volume_rule(mesh):
-    pts = _tensor_points([GAUSS3_S] * mesh.d)
-    w = np.prod(_tensor_points([GAUSS3_W] * mesh.d), axis=1) * np.prod(mesh.h)
+    gs, gw = gauss_rule_01(mesh.r)
+    pts = _tensor_points([gs] * mesh.d)
+    w = np.prod(_tensor_points([gw] * mesh.d), axis=1) * np.prod(mesh.h)
     return pts, w
 
 
 def face_rule(mesh, axis, side):
-    sets = [GAUSS3_S] * mesh.d
+    gs, gw = gauss_rule_01(mesh.r)
+    sets = [gs] * mesh.d
     sets = list(sets)
     sets[axis] = np.array([float(side)])
     pts = _tensor_points(sets)
-    wsets = [GAUSS3_W * mesh.h[j] if j != axis else np.array([1.0]) for j in range(mesh.d)]
+    wsets = [gw * mesh.h[j] if j != axis else np.array([1.0]) for j in range(mesh.d)]
     w = np.prod(_tensor_points(wsets), axis=1)
     return pts, w
 
@@ -123,7 +159,8 @@ def element_matrices(mesh, V, nu, tau, gamma1=35.0, gamma2=35.0):
 
     pts, wq = volume_rule(mesh)
     phi, dphi = tensor_basis(mesh, pts)
-    pib = pressure_basis(pts)
+    pib = pressure_basis(pts, mesh.r)
+    npm = mesh.n_pmodes
     Mel = np.einsum("q,qn,qm->nm", wq, phi, phi)
     Sel = np.einsum("q,qni,qmi->nm", wq, dphi, dphi)
     Gel = -np.einsum("q,qp,qnc->ncp", wq, pib, dphi)       # [n, c, q]
@@ -133,7 +170,7 @@ def element_matrices(mesh, V, nu, tau, gamma1=35.0, gamma2=35.0):
     for axis, side in dirichlet_faces(mesh):
         fp, fw = face_rule(mesh, axis, side)
         fphi, fdphi = tensor_basis(mesh, fp)
-        fpi = pressure_basis(fp)
+        fpi = pressure_basis(fp, mesh.r)
         nrm = np.zeros(d)
         nrm[axis] = 2.0 * side - 1.0
         hF = mesh.h[axis]
@@ -141,7 +178,7 @@ def element_matrices(mesh, V, nu, tau, gamma1=35.0, gamma2=35.0):
         Fdn = np.einsum("q,qn,qmi,i->nm", fw, fphi, fdphi, nrm)    # int (grad phi_m . n) phi_n
         vv = (np.kron(-nu * Fdn - nu * Fdn.T + gamma1 * nu / hF * Fpen, I_d)
               + gamma2 / hF * np.kron(Fpen, np.outer(nrm, nrm)))
-        vp = np.einsum("q,qp,qn,c->ncp", fw, fpi, fphi, nrm).reshape(nv, d + 1)
+        vp = np.einsum("q,qp,qn,c->ncp", fw, fpi, fphi, nrm).reshape(nv, npm)
         face_terms.append((boundary_cells(mesh, axis, side), vv, vp))
 
     cn = mesh.cell_nodes()
@@ -155,7 +192,7 @@ def element_matrices(mesh, V, nu, tau, gamma1=35.0, gamma2=35.0):
         C1 = np.einsum("q,qn,kqi,qmi->knm", wq, phi, vq, dphi)
         C2 = np.einsum("q,qn,qm,kqce->kncme", wq, phi, phi, gv).reshape(nc, nv, nv)
         Aa = nu * Sv[None] + np.einsum("knm,ce->kncme", C1, I_d).reshape(nc, nv, nv) + C2
-        Ga = np.broadcast_to(Gel.reshape(nv, d + 1), (nc, nv, d + 1)).copy()
+        Ga = np.broadcast_to(Gel.reshape(nv, npm), (nc, nv, npm)).copy()
         for cells, vv, vp in face_terms:
             Aa[cells] += vv
             Ga[cells] += vp

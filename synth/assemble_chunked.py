@@ -32,6 +32,8 @@ from .radau import dg_time_matrices
 
 class ChunkedJacobian:
     def __init__(self, mesh, nu, tau, gamma1=35.0, gamma2=35.0, chunk=512, threads=8):
+        if mesh.r != 2:
+            raise NotImplementedError("the chunked assembler is written for Q2 x P1disc (r = 2)")
         self.mesh, self.nu, self.tau, self.chunk = mesh, float(nu), float(tau), int(chunk)
         self.threads = int(threads)
         d, nl = mesh.d, mesh.n_loc_nodes

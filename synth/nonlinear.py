@@ -42,6 +42,8 @@ class SlabOperator:
     """F(X), J(X) of one slab on one mesh (2D or 3D channel, inflow at x = 0)."""
 
     def __init__(self, mesh, nu, tau, gamma1=35.0, gamma2=35.0):
+        if mesh.r != 2:
+            raise NotImplementedError("the slab operator is written for Q2 x P1disc (r = 2)")
         self.mesh, self.nu, self.tau = mesh, float(nu), float(tau)
         d, nl, nt, ns = mesh.d, mesh.n_loc_nodes, mesh.n_time, mesh.n_loc_space
         nv = d * nl

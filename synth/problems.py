@@ -86,12 +86,13 @@ def inflow_state(mesh, U, rng, noise=0.05):
     return V
 
 
-def build_hierarchy(d, shape, lengths, levels, k, nu, tau, U, seed=0, noise=0.05, state=None, shapes=None):
-    """Levels 0 (coarsest) .. levels-1 of one problem; `shapes` overrides the coarsening rule."""
+def build_hierarchy(d, shape, lengths, levels, k, nu, tau, U, seed=0, noise=0.05, state=None, shapes=None, r=2):
+    """Levels 0 (coarsest) .. levels-1 of one problem (velocity degree r); `shapes` overrides the
+    coarsening rule."""
     if shapes is None:
         shapes = hierarchy_shapes(shape, levels)
     levels = len(shapes)
-    meshes = [StructuredMesh(s, lengths, k) for s in shapes]
+    meshes = [StructuredMesh(s, lengths, k, r) for s in shapes]
     fine = meshes[-1]
     if state is None:
         state = inflow_state(fine, U, np.random.default_rng(1000 + seed), noise)
@@ -101,7 +102,7 @@ def build_hierarchy(d, shape, lengths, levels, k, nu, tau, U, seed=0, noise=0.05
         states[l] = states[l + 1][:, inject_nodes(meshes[l], meshes[l + 1]), :]
     out = []
     for l, m in enumerate(meshes):
-        if m.n_cells * m.n_K ** 2 > CHUNKED_ASSEMBLY_ENTRIES:
+        if m.r == 2 and m.n_cells * m.n_K ** 2 > CHUNKED_ASSEMBLY_ENTRIES:
             J = assemble_jacobian_chunked(m, states[l], nu, tau)
         else:
             J = assemble_jacobian(m, states[l], nu, tau)

@@ -219,3 +219,93 @@ def test_nnz_counts_match_structure(cfg0):
     assert [L.J.nnz for L in cfg0.levels] == [22908, 89100, 351372]
     pat = local_pattern(cfg0.levels[0].mesh)
     assert pat.shape == (42, 42)
+
+
+# ---- velocity degree r = 4: (Q4)^2 x P3disc, the element of the paper's 2D study (Sec. 4) ----
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 4])
+def test_q4_patch_width_and_counts(k):
+    """n_K = (k + 1)(2 * 25 + 10) = 60 (k + 1); spatial DoFs 2 (4 nx + 1)(4 ny + 1) + 10 nx ny."""
+    m = StructuredMesh((5, 3), (1.0, 0.6), k, r=4)
+    assert m.n_K == 60 * (k + 1) and m.cell_dofs().shape == (15, m.n_K)
+    assert m.n == (k + 1) * (2 * 21 * 13 + 10 * 15)
+    assert np.array_equal(np.unique(m.cell_dofs()), np.arange(m.n))  # every DoF is in some patch
+
+
+def test_q4_lagrange_basis_and_gauss_rule():
+    from synth.assemble import _lagrange_1d, gauss_rule_01
+    nodes = np.arange(5) / 4
+    v, dv = _lagrange_1d(nodes, 4)
+    np.testing.assert_allclose(v, np.eye(5), atol=1e-15)               # nodal
+    s = np.random.default_rng(3).uniform(0, 1, 7)
+    v, dv = _lagrange_1d(s, 4)
+    np.testing.assert_allclose(v.sum(axis=1), 1.0, atol=1e-14)          # reproduces 1 ...
+    np.testing.assert_allclose(dv.sum(axis=1), 0.0, atol=1e-12)
+    np.testing.assert_allclose(v @ nodes ** 4, s ** 4, atol=1e-14)       # ... and s^4
+    np.testing.assert_allclose(dv @ nodes ** 4, 4 * s ** 3, atol=1e-12)
+    g, w = gauss_rule_01(4)                                             # 6 points: exact to degree 11
+    assert len(g) == 6
+    for p in range(12):
+        assert abs(w @ g ** p - 1.0 / (p + 1)) < 1e-15
+
+
+def test_q4_prolongation_reproduces_q4_and_p3():
+    """Nested spaces: a degree-4 velocity field and a cubic pressure field pass unchanged."""
+    from synth.assemble import pressure_basis
+    c = StructuredMesh((3, 2), (1.5, 1.0), 0, r=4)
+    f = StructuredMesh((6, 4), (1.5, 1.0), 0, r=4)
+    P = prolongation(c, f)
+    u = lambda x: x[:, 0] ** 4 - 2 * x[:, 0] ** 2 * x[:, 1] ** 2 + x[:, 1] ** 3 + 0.5
+    vc = np.zeros(c.n)
+    vc[0:c.n_vel:2] = u(c.node_coords())
+    vc[1:c.n_vel:2] = -u(c.node_coords())
+    vf = P @ vc
+    np.testing.assert_allclose(vf[0:f.n_vel:2], u(f.node_coords()), atol=1e-13)
+    np.testing.assert_allclose(vf[1:f.n_vel:2], -u(f.node_coords()), atol=1e-13)
+
+    def coeffs(m, p):
+        """Per-cell P3 coefficients of p, fitted on sample points of each cell."""
+        s = np.random.default_rng(1).uniform(0, 1, size=(30, 2))
+        B = pressure_basis(s, 4)
+        ci = m.cell_index()
+        return np.concatenate([np.linalg.lstsq(B, p((ci[K] + s) * np.array(m.h)), rcond=None)[0]
+                               for K in range(m.n_cells)])
+    p = lambda X: X[:, 0] ** 3 - X[:, 0] * X[:, 1] ** 2 + 2 * X[:, 1] - 1
+    pc = np.zeros(c.n)
+    pc[c.n_vel:] = coeffs(c, p)
+    np.testing.assert_allclose((P @ pc)[f.n_vel:], coeffs(f, p), atol=1e-12)
+    np.testing.assert_allclose(f.node_coords()[inject_nodes(c, f)], c.node_coords())
+
+
+def test_q4_element_integrals():
+    m = StructuredMesh((3, 2), (0.6, 0.5), 0, r=4)
+    pts, w = volume_rule(m)
+    phi, dphi = tensor_basis(m, pts)
+    M = np.einsum("q,qn,qm->nm", w, phi, phi)
+    assert abs(M.sum() - np.prod(m.h)) < 1e-14
+    S = np.einsum("q,qni,qmi->nm", w, dphi, dphi)
+    np.testing.assert_allclose(S.sum(axis=1), 0.0, atol=1e-11)
+    # int grad(x^2 y^2) . grad(x^2 y^2) over the cell [0, hx] x [0, hy], from the nodal interpolant
+    hx, hy = m.h
+    xn = m.local_node_offsets() * np.array(m.h) / 4.0
+    g = xn[:, 0] ** 2 * xn[:, 1] ** 2
+    exact = 4 * (hx ** 3 / 3) * (hy ** 5 / 5) + 4 * (hx ** 5 / 5) * (hy ** 3 / 3)
+    assert abs(g @ S @ g - exact) < 1e-14
+
+
+def test_q4_jacobian_zero_state_symmetric():
+    """As for Q2: with v^m = 0 the same-time velocity block minus Kt[a,a] M is symmetric, and the
+    pressure rows are the negated transposed divergence columns."""
+    from synth.assemble import assemble_jacobian
+    m = StructuredMesh((3, 2), (0.9, 0.41), 1, r=4)
+    J = assemble_jacobian(m, np.zeros((m.n_time, m.n_nodes, m.d)), 1e-2, 0.01).toarray()
+    _, _, Kt, _ = dg_time_matrices(1)
+    ns, nv = m.n_space, m.n_vel
+    Mv = J[0:nv, ns:ns + nv] / Kt[0, 1]
+    assert abs(Mv[::2, ::2].sum() - np.prod(m.lengths)) < 1e-12
+    for a in range(2):
+        blk = J[a * ns:a * ns + nv, a * ns:a * ns + nv] - Kt[a, a] * Mv
+        np.testing.assert_allclose(blk, blk.T, atol=1e-13)
+        pa, va = slice(a * ns + nv, (a + 1) * ns), slice(a * ns, a * ns + nv)
+        assert np.all(J[pa, pa] == 0.0)
+        np.testing.assert_allclose(J[pa, va], J[va, pa].T, atol=1e-15)
