@@ -367,11 +367,13 @@ def _threads():
 
 def run_robustness(args, torch, vk, dev):
     """Robustness in the time degree: one Newton linearisation per dG(k), k = 0..4 on the 88 x 16
-    channel (Q2/P1disc, n_K = 21 (k + 1)) and k = 0..2 on a 48 x 8 x 8 box (n_K = 85 (k + 1)),
-    each solved by GMRES(30) to 1e-8 with the two-plus-two-sweep V-cycle, FP64 and FP32 patch
-    inverses.  The iteration counts are what the time degree should not change."""
+    channel (Q2/P1disc, n_K = 21 (k + 1), and (Q4)^2/P3disc, the element of the paper's 2D study,
+    n_K = 60 (k + 1)) and k = 0..2 on a 48 x 8 x 8 box (Q2/P1disc, n_K = 85 (k + 1)), each solved
+    by GMRES(30) to 1e-8 with the two-plus-two-sweep V-cycle, FP64 and FP32 patch inverses.  The
+    iteration counts are what the time degree should not change."""
     from synth import build_problem
     cases = [("channel2d_88x16", "channel2d_88x16_k1", dict(k=k)) for k in range(5)]
+    cases += [("channel2d_88x16_q4", "channel2d_88x16_k1", dict(k=k, r=4)) for k in range(5)]
     cases += [("box3d_48x8x8", "box3d_100x16x16_k1", dict(shape=(48, 8, 8), levels=4, k=k)) for k in range(3)]
     restart, max_iter, nu = 30, 300, (2, 2)
     rows = []
@@ -381,7 +383,8 @@ def run_robustness(args, torch, vk, dev):
         levels = [vk.upload_level(L, dev) for L in P.levels]
         b = torch.from_numpy(P.b).to(dev)
         x = torch.zeros_like(b)
-        row = {"mesh": name, "k": over["k"], "n_K": int(P.finest.mesh.n_K), "unknowns": int(P.finest.n),
+        row = {"mesh": name, "r": int(P.finest.mesh.r), "k": over["k"], "n_K": int(P.finest.mesh.n_K),
+               "unknowns": int(P.finest.n),
                "levels": len(P.levels), "coarse_unknowns": int(P.levels[0].n)}
         for prec in ("f64", "f32"):
             S = vk.Solver(levels)

@@ -47,6 +47,9 @@ CASES = {
     "k4": ("channel2d_44x8_k1", dict(shape=(12, 4), levels=2, k=4)),
     "box3d_k0": ("box3d_100x16x16_k1", dict(shape=(8, 4, 4), levels=2, k=0)),
     "box3d_k2": ("box3d_100x16x16_k1", dict(shape=(4, 2, 2), levels=2, k=2)),
+    # (Q4)^2 x P3disc, the element of the paper's 2D study: n_K = 60 (k + 1)
+    "r4_k0": ("channel2d_44x8_k1", dict(shape=(8, 4), levels=2, k=0, r=4)),
+    "r4_k1": ("channel2d_44x8_k1", dict(shape=(8, 4), levels=2, k=1, r=4)),
 }
 
 _cache = {}
