@@ -640,10 +640,11 @@ __global__ __launch_bounds__(64 * RowCfg<N>::W) void patch_setup_rows_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Wide patches (n_K up to 8 x 22 = 176, e.g. 170 for the 3D Q2/P1disc dG(1)
-// patch): the FP64 matrix does not fit one row per lane, so it is spread over
-// a 512-thread workgroup in registers: wavefront w holds the columns
-// [w CW, (w + 1) CW), lane l the rows l, l + 64, l + 128.  Step k of the same
+// Wide patches (compiled for n_K = 85, 105, 120, 170, 180: the 3D Q2/P1disc
+// dG(0), dG(1) patches, 2D Q2/P1disc dG(4) and (Q4)^2/P3disc dG(1), dG(2)): the
+// FP64 matrix does not fit one row per lane, so it is spread over a 512-thread
+// workgroup in registers: wavefront w holds the columns [w CW, (w + 1) CW),
+// lane l the rows l, l + 64, l + 128 (up to 3 x 64 rows).  Step k of the same
 // implicit-pivoting Gauss-Jordan elimination: the wavefront owning column k
 // finds the pivot (DPP reductions) and publishes the column through LDS (two
 // buffers, so one barrier per step suffices); every wavefront reads the pivot
@@ -827,10 +828,17 @@ hipError_t setup_rows(hipStream_t s, const vk_csr& J, const vk_group& L, int32_t
     VK_ROWS_CASE(63)
     VK_ROWS_CASE(84)
 #undef VK_ROWS_CASE
-    case 170:
-      patch_setup_wide_kernel<P, 170><<<L.n_cells, 64 * WideCfg<170>::NW, 0, s>>>(
-          J.row_ptr, J.col, J.val, L.cell_dofs, L.inv, L.ld, L.cell_stride, status);
-      return hipGetLastError();
+#define VK_WIDE_CASE(NN)                                                                                \
+  case NN:                                                                                              \
+    patch_setup_wide_kernel<P, NN><<<L.n_cells, 64 * WideCfg<NN>::NW, 0, s>>>(                          \
+        J.row_ptr, J.col, J.val, L.cell_dofs, L.inv, L.ld, L.cell_stride, status);                     \
+    return hipGetLastError();
+    VK_WIDE_CASE(85)
+    VK_WIDE_CASE(105)
+    VK_WIDE_CASE(120)
+    VK_WIDE_CASE(170)
+    VK_WIDE_CASE(180)
+#undef VK_WIDE_CASE
     default:
       *handled = false;
       return hipSuccess;

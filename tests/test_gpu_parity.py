@@ -50,6 +50,7 @@ CASES = {
     # (Q4)^2 x P3disc, the element of the paper's 2D study: n_K = 60 (k + 1)
     "r4_k0": ("channel2d_44x8_k1", dict(shape=(8, 4), levels=2, k=0, r=4)),
     "r4_k1": ("channel2d_44x8_k1", dict(shape=(8, 4), levels=2, k=1, r=4)),
+    "r4_k2": ("channel2d_44x8_k1", dict(shape=(8, 4), levels=2, k=2, r=4)),
 }
 
 _cache = {}
@@ -409,7 +410,7 @@ def test_dof_gather_widths_agree(vk, case):
     np.testing.assert_array_equal(outs[0], outs[1])
 
 
-@pytest.mark.parametrize("case", ["cfg0", "ragged_k2", "k3", "box3d"])
+@pytest.mark.parametrize("case", ["cfg0", "ragged_k2", "k3", "box3d", "k4", "box3d_k0", "r4_k1", "r4_k2"])
 def test_setup_variants_agree(vk, case):
     """The register-resident and the LDS Gauss-Jordan kernels give the same inverses."""
     P, H = problem(case)
