@@ -240,10 +240,12 @@ typedef enum {
 } vk_sweep_variant;
 vk_status vk_set_sweep_variant(vk_ctx* ctx, int32_t variant);
 
-/* Patch inversion kernel used by vanka_setup: 0 (default) keeps one patch row
- * per lane in registers where a kernel for the patch width is compiled
- * (n_K = 42, 63, 84), 1 always uses the LDS / global-memory kernel.  Both
- * compute the same Gauss-Jordan inverse; setup must run again after a change. */
+/* Patch inversion kernel used by vanka_setup: 0 (default) keeps the patch
+ * matrix in registers where a kernel for the patch width is compiled (one row
+ * per lane for n_K = 42, 63, 84; spread over a 512-thread workgroup for
+ * n_K = 85, 105, 120, 170, 180), 1 always uses the LDS / global-memory kernel.
+ * Both compute the same Gauss-Jordan inverse; setup must run again after a
+ * change. */
 vk_status vk_set_setup_variant(vk_ctx* ctx, int32_t variant);
 
 /* Autotuner: after vanka_setup, times each level's SpMV kernels (J, P, R)
