@@ -121,6 +121,7 @@ size_t plan_workspace(vk_ctx* ctx, vk_prec prec, int32_t restart, char* base) {
       L.cb_used = cv.take<int32_t>(n);
     }
   }
+  ctx->blocked = vk_blocked_ws();
   if (big_nk > 0) {
     const int64_t per = (int64_t)big_nk * big_nk;
     int64_t chunk = (int64_t)(512ll << 20) / (per * 8);
@@ -128,6 +129,25 @@ size_t plan_workspace(vk_ctx* ctx, vk_prec prec, int32_t restart, char* base) {
     if (chunk > big_cells) chunk = big_cells;
     ctx->big_chunk = (int32_t)chunk;
     ctx->big_scratch = cv.take<double>(chunk * per);
+    // the blocked inversion of the wide patches: the scratch holds a chunk of dense blocks,
+    // at most cap / n_K^2 cells of a group at a time
+    vk_blocked_ws& bw = ctx->blocked;
+    bw.a = ctx->big_scratch;
+    bw.cap = chunk * per;
+    for (int l = 0; l < nl; ++l)
+      for (const vk_group& G : ctx->lv[l].groups) {
+        if (G.n_K <= VK_LDS_SETUP_MAX_NK) continue;
+        int64_t cg = bw.cap / ((int64_t)G.n_K * G.n_K);
+        if (cg > G.n_cells) cg = G.n_cells;
+        if (cg * G.n_K > bw.rows_cap) bw.rows_cap = cg * G.n_K;
+        if (cg > bw.blocks_cap) bw.blocks_cap = cg;
+      }
+    bw.q = cv.take<int32_t>(bw.rows_cap);
+    bw.used = cv.take<int32_t>(bw.rows_cap);
+    bw.gi = cv.take<double>(bw.blocks_cap * VK_GJ_NBI_MAX * 64);
+    bw.go = cv.take<double>(64 * bw.rows_cap);
+    bw.rows = cv.take<int64_t>(bw.blocks_cap + 1);
+    bw.woff = cv.take<int64_t>(bw.blocks_cap);
   } else {
     ctx->big_chunk = 0;
     ctx->big_scratch = nullptr;
@@ -739,6 +759,12 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
     for (const vk_group& G : L.groups) {
       bool handled = false;
       if (ctx->fast_setup) VK_TRY(launch_patch_setup_fast(ps, L.J, G, ctx->prec, ctx->status + 64 + l, &handled));
+      // wider than LDS and no register-resident kernel: the blocked kernels of the directly
+      // solved blocks, one block per cell
+      if (!handled && ctx->fast_setup && G.n_K > VK_LDS_SETUP_MAX_NK && G.n_K <= 512 && ctx->blocked.cap > 0) {
+        VK_TRY(launch_patch_setup_blocked(ps, L.J, G, ctx->prec, ctx->blocked, ctx->status + 64 + l));
+        handled = true;
+      }
       if (!handled)
         VK_TRY(launch_patch_setup(ps, L.J, G, ctx->prec, ctx->big_scratch, ctx->big_chunk, ctx->status + 64 + l));
     }

@@ -107,7 +107,7 @@ __global__ __launch_bounds__(CTT) void block_panel_kernel(const int64_t* __restr
                                                           const int64_t* __restrict__ woff, int64_t k0, int64_t c0o,
                                                           double* W_all, int32_t* __restrict__ q_all,
                                                           int32_t* __restrict__ pcol_all, double* __restrict__ gi_all,
-                                                          int32_t nbo, int32_t* status) {
+                                                          int32_t nbo, int32_t bad_base, int32_t* status) {
   constexpr int NW = CTT / 64;
   static_assert(NW <= 16, "the cross-wave step reduces over one 16-lane row");
   static_assert(R <= 32, "the used-row mask has 32 bits");
@@ -175,7 +175,8 @@ __global__ __launch_bounds__(CTT) void block_panel_kernel(const int64_t* __restr
         for (int c = 0; c < NB; ++c) pr[c] = w_row[buf][ow][c];
         const double piv = pr[u];
         const bool bad = pk < 0.0 || !(piv != 0.0) || !isfinite(piv);
-        if (bad && tid == 0) atomicMin(&status[0], -1);  // failure path only
+        // failure path only: -1, or the first failing block's number from bad_base on
+        if (bad && tid == 0) atomicMin(&status[0], bad_base < 0 ? -1 : bad_base + bk);
         if (tid == 0) s_q[j] = bad ? 0 : p;
         // The update runs whether or not the pivot is usable (a branch around it would keep two
         // copies of the panel live): after a failure the status word reports the block and its
@@ -440,7 +441,7 @@ __global__ void block_export_kernel(int64_t n, const double* __restrict__ W, con
 }
 
 template <int CTT, int R, int NB, int NBO>
-hipError_t run_blocked(hipStream_t s, const vk_level& L, int32_t* status) {
+hipError_t run_blocked(hipStream_t s, const vk_level& L, int32_t* status, int32_t bad_base = -1) {
   static_assert(NBO % NB == 0 && NB <= VK_GJ_NBI_MAX && NBO % 64 == 0 && NBO <= VK_GJ_NBO,
                 "inner panels must tile the outer block, whose columns come in whole 64-column tiles");
   const int nbk = (int)L.cb_rows.size() - 1;
@@ -449,7 +450,7 @@ hipError_t run_blocked(hipStream_t s, const vk_level& L, int32_t* status) {
   for (int64_t c0o = 0; c0o < n; c0o += NBO) {
     for (int64_t k0 = c0o; k0 < c0o + NBO && k0 < n; k0 += NB) {
       block_panel_kernel<CTT, R, NB><<<nbk, CTT, 0, s>>>(L.d_cb_rows, L.d_cb_woff, k0, c0o, L.cb_a, L.cb_q,
-                                                         L.cb_used, L.cb_gi, NBO, status);
+                                                         L.cb_used, L.cb_gi, NBO, bad_base, status);
       // the same steps on the outer block's other columns, before and after the panel
       if (n > NB)
         gj_update_kernel<NB><<<dim3(row_tiles, NBO / 64, nbk), 256, 0, s>>>(
@@ -497,6 +498,17 @@ hipError_t launch_block_invert(hipStream_t s, const vk_level& L, int32_t* status
   else if (m <= 8192) e = wide ? run_blocked<1024, 8, 4, 128>(s, L, status) : run_blocked<1024, 8, 4, 64>(s, L, status);
   else e = wide ? run_blocked<1024, 9, 4, 128>(s, L, status) : run_blocked<1024, 9, 4, 64>(s, L, status);
   return e;
+}
+
+hipError_t launch_blocks_invert_dense(hipStream_t s, const vk_level& L, int32_t* status, int32_t bad_base) {
+  const int nbk = (int)L.cb_rows.size() - 1;
+  if (nbk <= 0) return hipSuccess;
+  if (L.cb_max > 512) return hipErrorInvalidValue;
+  const hipError_t e = launch_fill_i32(s, L.cb_rows[nbk] - L.cb_rows[0], 0, L.cb_used);
+  if (e != hipSuccess) return e;
+  // blocks of at most 512 rows: 256 threads x 2 rows hold a 16-column panel; 64-column outer
+  // blocks (the buffers of the blocked patch inversion are sized for them)
+  return run_blocked<256, 2, 16, 64>(s, L, status, bad_base);
 }
 
 hipError_t launch_block_apply(hipStream_t s, const vk_level& L, const double* x, double* y) {

@@ -357,6 +357,113 @@ inline unsigned capped_grid(int64_t work, int per_block, unsigned cap) {
   return (unsigned)g;
 }
 
+// ---------------------------------------------------------------------------
+// Patches too wide for LDS and for the register-resident kernels go through the
+// blocked Gauss-Jordan kernels of the directly solved blocks (coarse.hip), a
+// chunk of cells at a time: each cell's patch matrix is one block.
+// ---------------------------------------------------------------------------
+
+// Column-major dense patch matrices of cells [cell0, cell0 + gridDim.x) (zeroed beforehand):
+// W_b[c n + i] = J[dof_i][dof_c].  One workgroup per cell, a wavefront per row.
+__global__ __launch_bounds__(256) void patch_dense_cm_kernel(int32_t n, int32_t cell0,
+                                                             const int32_t* __restrict__ cell_dofs,
+                                                             const int64_t* __restrict__ row_ptr,
+                                                             const int32_t* __restrict__ col,
+                                                             const double* __restrict__ val, double* W_all) {
+  extern __shared__ int dsm[];
+  int* sdof = dsm;
+  int* skey = dsm + n;
+  int* sloc = dsm + 2 * n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int32_t* dofs = cell_dofs + (int64_t)(cell0 + (int64_t)blockIdx.x) * n;
+  for (int i = tid; i < n; i += 256) sdof[i] = dofs[i];
+  __syncthreads();
+  for (int i = tid; i < n; i += 256) {
+    const int v = sdof[i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) rank += (sdof[j] < v) ? 1 : 0;
+    skey[rank] = v;
+    sloc[rank] = i;
+  }
+  __syncthreads();
+  double* W = W_all + (int64_t)blockIdx.x * n * n;
+  for (int i = wave; i < n; i += 4) {
+    const int64_t row = sdof[i];
+    const int64_t e1 = row_ptr[row + 1];
+    for (int64_t e = row_ptr[row] + lane; e < e1; e += 64) {
+      const int c = col[e];
+      int lo = 0, hi = n;  // first key >= c
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (skey[mid] < c) lo = mid + 1; else hi = mid;
+      }
+      if (lo < n && skey[lo] == c) W[(int64_t)sloc[lo] * n + i] = val[e];
+    }
+  }
+}
+
+// rows[b] = b n, woff[b] = b n^2 (b < nb; rows also at nb)
+__global__ void block_offsets_kernel(int32_t nb, int64_t n, int64_t* rows, int64_t* woff) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b <= nb) rows[b] = b * n;
+  if (b < nb) woff[b] = b * n * n;
+}
+
+// The inverses of the eliminated blocks (row-major W_b, pivot rows q_b) into the patch store:
+// J_K^{-1}[k][q_j] = W_b[q_k][j], column-major with leading dimension ld, rows n..ld-1 zero.
+template <int P>
+__global__ void patch_export_blocked_kernel(int32_t n, int32_t cell0, int32_t nc, const double* __restrict__ W_all,
+                                            const int32_t* __restrict__ q_all, void* inv_out, int32_t ld,
+                                            int64_t cell_stride) {
+  using S = typename PT<P>::S;
+  const int64_t per = (int64_t)n * ld, total = (int64_t)nc * per;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e / per, rem = e - b * per;
+    const int j = (int)(rem / ld), k = (int)(rem - (int64_t)j * ld);
+    const int32_t* q = q_all + b * n;
+    S* out = reinterpret_cast<S*>(inv_out) + (cell0 + b) * cell_stride;
+    out[(int64_t)q[j] * ld + k] = store_cvt<P>(k < n ? W_all[b * n * n + (int64_t)q[k] * n + j] : 0.0);
+  }
+}
+
+template <int P>
+hipError_t setup_blocked(hipStream_t s, const vk_csr& J, const vk_group& G, const vk_blocked_ws& ws,
+                         int32_t* status) {
+  const int64_t n = G.n_K;
+  int64_t chunk = ws.cap / (n * n);
+  if (ws.rows_cap / n < chunk) chunk = ws.rows_cap / n;
+  if (ws.blocks_cap < chunk) chunk = ws.blocks_cap;
+  if (chunk < 1 || n > 512) return hipErrorInvalidValue;
+  vk_level B;  // the chunk's cells as the blocks of a level
+  B.cb_max = n;
+  B.cb_a = ws.a;
+  B.cb_q = ws.q;
+  B.cb_used = ws.used;
+  B.cb_gi = ws.gi;
+  B.cb_go = ws.go;
+  B.d_cb_rows = ws.rows;
+  B.d_cb_woff = ws.woff;
+  const int32_t nb_max = (int32_t)(G.n_cells < chunk ? G.n_cells : chunk);
+  block_offsets_kernel<<<(unsigned)((nb_max + 256) / 256), 256, 0, s>>>(nb_max, n, ws.rows, ws.woff);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  for (int32_t c0 = 0; c0 < G.n_cells; c0 += (int32_t)chunk) {
+    const int32_t nc = (int32_t)((G.n_cells - c0) < chunk ? (G.n_cells - c0) : chunk);
+    B.cb_rows.assign((size_t)nc + 1, 0);
+    for (int32_t b = 0; b <= nc; ++b) B.cb_rows[b] = (int64_t)b * n;
+    if ((e = launch_fill(s, (int64_t)nc * n * n, 0.0, ws.a)) != hipSuccess) return e;
+    patch_dense_cm_kernel<<<(unsigned)nc, 256, (size_t)3 * n * sizeof(int), s>>>((int32_t)n, c0, G.cell_dofs,
+                                                                                 J.row_ptr, J.col, J.val, ws.a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_blocks_invert_dense(s, B, status, c0)) != hipSuccess) return e;
+    const int64_t total = (int64_t)nc * n * G.ld;
+    patch_export_blocked_kernel<P><<<capped_grid(total, 256, 16384), 256, 0, s>>>(
+        (int32_t)n, c0, nc, ws.a, ws.q, G.inv, G.ld, G.cell_stride);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 template <int P>
 hipError_t setup_prec(hipStream_t s, const vk_csr& J, const vk_group& L, double* big, int32_t chunk, int32_t* status) {
   const int n = L.n_K;
@@ -1074,6 +1181,16 @@ hipError_t launch_patch_setup_fast(hipStream_t s, const vk_csr& J, const vk_grou
     case VK_F64: return setup_rows<VK_F64>(s, J, G, status, handled);
     case VK_F32: return setup_rows<VK_F32>(s, J, G, status, handled);
     default: return setup_rows<VK_BF16>(s, J, G, status, handled);
+  }
+}
+
+hipError_t launch_patch_setup_blocked(hipStream_t s, const vk_csr& J, const vk_group& G, vk_prec prec,
+                                      const vk_blocked_ws& ws, int32_t* status) {
+  if (G.n_cells == 0) return hipSuccess;
+  switch (prec) {
+    case VK_F64: return setup_blocked<VK_F64>(s, J, G, ws, status);
+    case VK_F32: return setup_blocked<VK_F32>(s, J, G, ws, status);
+    default: return setup_blocked<VK_BF16>(s, J, G, ws, status);
   }
 }
 

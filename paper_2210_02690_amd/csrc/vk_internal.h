@@ -88,6 +88,20 @@ struct vk_group {
   int64_t y_off = 0;          // first flat (cell, local) index of the group on its level
 };
 
+// Buffers of the blocked patch inversion: up to `cap` doubles of dense blocks (the setup scratch),
+// and per-row / per-block arrays for up to `rows_cap` rows and `blocks_cap` blocks.
+struct vk_blocked_ws {
+  double* a = nullptr;        // dense blocks (aliases the setup scratch)
+  int64_t cap = 0;            // doubles
+  int64_t rows_cap = 0, blocks_cap = 0;
+  int32_t* q = nullptr;       // pivot rows, per row
+  int32_t* used = nullptr;    // pivot records, per row
+  double* gi = nullptr;       // blocks_cap x VK_GJ_NBI_MAX x 64 (64-column outer blocks)
+  double* go = nullptr;       // 64 x rows_cap
+  int64_t* rows = nullptr;    // blocks_cap + 1 block offsets
+  int64_t* woff = nullptr;    // blocks_cap dense-matrix offsets
+};
+
 struct vk_level {
   bool set = false;
   vk_csr J{}, P{}, R{};
@@ -178,6 +192,7 @@ struct vk_ctx {
   // setup scratch for patches too wide for LDS
   double* big_scratch = nullptr;
   int32_t big_chunk = 0;
+  vk_blocked_ws blocked;  // patches wider than LDS through the blocked kernels (big_scratch holds the blocks)
   // multiplicative sweep: per-cell local defects of one colour
   double* rK = nullptr;
   // Krylov
@@ -230,6 +245,10 @@ hipError_t launch_patch_setup(hipStream_t s, const vk_csr& J, const vk_group& G,
                               int32_t big_chunk, int32_t* status);
 hipError_t launch_patch_setup_fast(hipStream_t s, const vk_csr& J, const vk_group& G, vk_prec prec, int32_t* status,
                                    bool* handled);
+// Patches of more than VK_LDS_SETUP_MAX_NK (at most 512) rows through the blocked Gauss-Jordan
+// kernels of the directly solved blocks, in chunks of the workspace's blocked-setup buffers.
+hipError_t launch_patch_setup_blocked(hipStream_t s, const vk_csr& J, const vk_group& G, vk_prec prec,
+                                      const vk_blocked_ws& ws, int32_t* status);
 hipError_t launch_patch_apply(hipStream_t s, const vk_group& G, vk_prec prec, int32_t colour, const double* r,
                               const double* rK, double* d, const double* inv_p, double omega);
 hipError_t launch_patch_residual(hipStream_t s, const vk_csr& J, int lpr, const vk_group& G, int32_t colour,
@@ -247,6 +266,9 @@ int vk_prec_bytes(vk_prec prec);
 // directly solved blocks (the coarsest level, and in batches every system's coarsest level)
 int64_t vk_coarse_max_n();
 hipError_t launch_block_invert(hipStream_t s, const vk_level& L, int32_t* status, double** result);
+// Blocked Gauss-Jordan inversion of L's blocks (cb_rows, cb_max <= 512), whose dense column-major
+// matrices are already in L.cb_a; a failing pivot sets status[0] to min(bad_base + block).
+hipError_t launch_blocks_invert_dense(hipStream_t s, const vk_level& L, int32_t* status, int32_t bad_base);
 hipError_t launch_block_apply(hipStream_t s, const vk_level& L, const double* x, double* y);
 hipError_t launch_block_export(hipStream_t s, const vk_level& L, int32_t block, double* out);
 // Krylov

@@ -51,6 +51,8 @@ CASES = {
     "r4_k0": ("channel2d_44x8_k1", dict(shape=(8, 4), levels=2, k=0, r=4)),
     "r4_k1": ("channel2d_44x8_k1", dict(shape=(8, 4), levels=2, k=1, r=4)),
     "r4_k2": ("channel2d_44x8_k1", dict(shape=(8, 4), levels=2, k=2, r=4)),
+    # wider than any register-resident kernel: the blocked Gauss-Jordan path
+    "r4_k3": ("channel2d_44x8_k1", dict(shape=(8, 4), levels=2, k=3, r=4)),
 }
 
 _cache = {}
@@ -288,6 +290,28 @@ def test_singular_patch_reported(vk):
     assert e.value.bad_level == 1 and e.value.bad_cell == cell
 
 
+def test_singular_wide_patch_reported(vk):
+    """A singular 255-wide patch (3D dG(2)), inverted by the blocked kernels, names its cell."""
+    P = build_problem("box3d_100x16x16_k1", shape=(4, 2, 2), levels=2, k=2)
+    L = P.finest
+    assert L.mesh.n_K == 255
+    J = L.J.tolil()
+    cell = 5
+    pdof = int(L.cell_dofs[cell][81])   # the first pressure DoF of time node 0: this cell's only
+    J[pdof, :] = 0.0
+    J = J.tocsr()
+    J.eliminate_zeros()
+    J.sort_indices()
+    L.J = J
+    S = vk.Solver([vk.upload_level(Lv, DEV) for Lv in P.levels])
+    S.vk_set_workspace("f32", 30, device=DEV)
+    with pytest.raises(vk.VkError) as e:
+        S.vanka_setup(0.7)
+    assert e.value.status == vk.VK_ERR_SINGULAR
+    assert e.value.bad_level == 1 and e.value.bad_cell == cell
+    S.close()
+
+
 def test_malformed_csr_rejected(vk):
     P = build_problem("channel2d_44x8_k1", shape=(8, 4), levels=2)
     lv = [vk.upload_level(L, DEV) for L in P.levels]
@@ -410,9 +434,11 @@ def test_dof_gather_widths_agree(vk, case):
     np.testing.assert_array_equal(outs[0], outs[1])
 
 
-@pytest.mark.parametrize("case", ["cfg0", "ragged_k2", "k3", "box3d", "k4", "box3d_k0", "r4_k1", "r4_k2"])
+@pytest.mark.parametrize("case", ["cfg0", "ragged_k2", "k3", "box3d", "k4", "box3d_k0", "r4_k1", "r4_k2",
+                                  "box3d_k2", "r4_k3"])
 def test_setup_variants_agree(vk, case):
-    """The register-resident and the LDS Gauss-Jordan kernels give the same inverses."""
+    """The register-resident (or, for the widest patches, the blocked) and the LDS / global-memory
+    Gauss-Jordan kernels give the same inverses."""
     P, H = problem(case)
     outs = []
     for variant in (0, 1):
