@@ -83,6 +83,32 @@ def phase_times(torch, S, b, x, nu, restart, max_iter, reps=3):
     return float(np.median(ts)), float(np.median(tg)), its, rel
 
 
+def stream_rates_gbs(torch, dev, mib=1024, reps=5):
+    """Rates (GB/s) of two plain torch kernels over a 1 GiB FP64 buffer on this GPU, beside the
+    published peak: a device copy (read + written bytes) and a sum (read bytes; the patch GEMV
+    reads 98 % of its bytes)."""
+    n = (mib << 20) // 8
+    src = torch.empty(n, dtype=torch.float64, device=dev).uniform_()
+    dst = torch.empty_like(src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+
+    def rate(fn, nbytes):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return reps * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+    copy = rate(lambda: dst.copy_(src), 2 * n * 8)
+    read = rate(lambda: src.sum(), n * 8)
+    del src, dst
+    return copy, read
+
+
 def sweep_rate(torch, S, P, b_np, sweeps=40):
     """Finest-level additive sweeps in isolation: cells*sweeps/s."""
     l = len(P.levels) - 1
@@ -564,6 +590,11 @@ def main():
         out["finest_sweep_rate"] = {args.prec: sweep_rate(torch, S, P, P.b)}
     except Exception as e:  # pragma: no cover
         log(f"[bench] sweep rate failed: {e}")
+    # context for the roofline: plain streaming kernels on the same GPU
+    cg, rg = stream_rates_gbs(torch, dev)
+    out["roofline"]["copy_GBps"] = cg
+    out["roofline"]["read_GBps"] = rg
+    out["roofline"]["frac_of_read"] = achieved / rg
 
     # the same steps with every Arnoldi step replayed from a recorded hipGraph
     S.vk_set_graphs(True)
