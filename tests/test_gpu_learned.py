@@ -220,7 +220,7 @@ def test_learned_guess_beats_extrapolation(vk):
          f"{[s['newton'] for s in st_f]} vs {[s['newton'] for s in st_l]}; gmres "
          f"{[s['gmres'] for s in st_f]} vs {[s['gmres'] for s in st_l]}")
     assert all(s["converged"] for s in st_f + st_l)
-    # the guess quality, judged by the slab residual: the learned start is closer to the solution
+    # the guess quality, measured by the slab residual: the learned start is closer to the solution
     assert f0_l < 0.5 * f0_f
     # both marches reach the same slab solutions
     nm.close()
