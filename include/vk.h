@@ -242,8 +242,8 @@ vk_status vk_set_sweep_variant(vk_ctx* ctx, int32_t variant);
 
 /* Patch inversion kernel used by vanka_setup: 0 (default) keeps the patch
  * matrix in registers where a kernel for the patch width is compiled (one row
- * per lane for n_K = 42, 63, 84; spread over a 512-thread workgroup for
- * n_K = 85, 105, 120, 170, 180), inverts other patches wider than 88 (up to
+ * per lane for n_K = 42, 63; spread over a 512-thread workgroup for
+ * n_K = 84, 85, 105, 120, 170, 180), inverts other patches wider than 88 (up to
  * 512) with the blocked kernels of the directly solved blocks, one block per
  * cell, and the rest in LDS; 1 always uses the LDS / global-memory kernel.
  * All compute the Gauss-Jordan inverse with partial pivoting; setup must run
