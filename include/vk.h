@@ -253,8 +253,11 @@ vk_status vk_set_setup_variant(vk_ctx* ctx, int32_t variant);
 /* Autotuner: after vanka_setup, times each level's SpMV kernels (J, P, R)
  * with 4, 8, 16, 32 and 64 lanes per row and the patch GEMV with 1, 2, 4 and
  * 8 cells per workgroup (`reps` launches each, HIP events) and keeps the
- * fastest for the context.  Results change only in floating-point summation
- * order.  Overwrites the level scratch vectors; synchronises the stream.
+ * fastest for the context; on levels with one cell group the GEMV tiles are
+ * then timed again inside V-cycles from the finest level (three rounds of
+ * `reps` V-cycles per tile, every launch timed), which decides.  Results change only in floating-point summation
+ * order.  Overwrites the level scratch vectors and clears the timing
+ * records; waits for the block inversion; synchronises the stream.
  * A later vk_set_workspace resets the choices (vk_set_patch_tile overrides). */
 vk_status vk_autotune(vk_ctx* ctx, int32_t reps);
 

@@ -1147,6 +1147,65 @@ vk_status vk_autotune(vk_ctx* ctx, int32_t reps) {
   }
   VK_TRY(hipEventDestroy(e0));
   VK_TRY(hipEventDestroy(e1));
+  // The GEMV tiles once more, inside V-cycles from the finest level, which move every level's
+  // data through the caches as the solve does: back-to-back launches of one tile reread inverses
+  // the last-level cache still holds (176x32 dG(2): 4 and 8 cells per workgroup time alike back
+  // to back, 16.8 and 18.5 us inside the solve).  Levels with one cell group; the candidates
+  // alternate over three rounds of `reps` V-cycles, every GEMV launch timed by its own events.
+  const int Lf = ctx->n_levels - 1;
+  bool single = false;
+  for (int l = 1; l <= Lf; ++l) single = single || ctx->lv[l].groups.size() == 1;
+  if (single && ctx->n_levels <= 32 && ctx->sweep_variant != VK_SWEEP_COLOURED_SCATTER) {
+    const bool t_on = ctx->timing;
+    const int32_t t_level = ctx->timing_level, t_every = ctx->timing_every;
+    const uint32_t t_kinds = ctx->timing_kinds;
+    const int cands[4] = {1, 2, 4, 8};
+    int32_t first[32] = {0};
+    bool valid[32][4] = {};
+    double tot[32][4] = {};
+    int64_t cnt[32][4] = {};
+    for (int l = 1; l <= Lf; ++l)
+      if (ctx->lv[l].groups.size() == 1) {
+        const vk_group& G = ctx->lv[l].groups[0];
+        first[l] = G.cpb_tuned;
+        for (int c = 0; c < 4; ++c) valid[l][c] = VK_NT / cands[c] >= G.ld / vk_prec_vw(ctx->prec);
+      }
+    vk_level& F = ctx->lv[Lf];
+    VK_TRY(launch_fill(s, F.J.n_rows, 1.0, F.b));
+    vk_status st = ctx->coarse_pending ? coarse_wait(ctx, true) : VK_OK;
+    for (int round = 0; round < 3 && st == VK_OK; ++round)
+      for (int c = 0; c < 4 && st == VK_OK; ++c) {
+        for (int l = 1; l <= Lf; ++l)
+          if (ctx->lv[l].groups.size() == 1)
+            ctx->lv[l].groups[0].cpb_tuned = valid[l][c] ? cands[c] : first[l];
+        if ((st = vk_timing_kinds(ctx, 1u << VK_KERNEL_PATCH_GEMV, 1)) != VK_OK) break;
+        if ((st = vk_timing_enable(ctx, 1, -1)) != VK_OK) break;
+        for (int r = 0; r < reps && st == VK_OK; ++r) st = vcycle_level(ctx, Lf, F.b, F.d, 2, 2);
+        for (int l = 1; l <= Lf && st == VK_OK; ++l) {
+          if (ctx->lv[l].groups.size() != 1 || !valid[l][c]) continue;
+          int64_t n = 0;
+          double ms = 0.0;
+          st = vk_timing_read(ctx, VK_KERNEL_PATCH_GEMV, l, &n, &ms);
+          tot[l][c] += ms;
+          cnt[l][c] += n;
+        }
+      }
+    for (int l = 1; l <= Lf; ++l) {
+      if (ctx->lv[l].groups.size() != 1) continue;
+      int best = -1;
+      for (int c = 0; c < 4; ++c)
+        if (valid[l][c] && cnt[l][c] > 0 && (best < 0 || tot[l][c] / cnt[l][c] < tot[l][best] / cnt[l][best]))
+          best = c;
+      ctx->lv[l].groups[0].cpb_tuned = (st == VK_OK && best >= 0) ? cands[best] : first[l];
+    }
+    ctx->timing = t_on;
+    ctx->timing_level = t_level;
+    ctx->timing_kinds = t_kinds;
+    ctx->timing_every = t_every;
+    ctx->recs.clear();
+    ctx->timing_seen = 0;
+    if (st != VK_OK) return st;
+  }
   return VK_OK;
 }
 
