@@ -4,13 +4,16 @@ One step = the whole hot path on one Newton system: vanka_setup (patch gather,
 FP64 patch inverses stored in the chosen precision, coarse inverse) followed by
 gmres_solve from x = 0 to a relative residual of 1e-8 (GMRES(30), one V-cycle
 with 2 pre- and 2 post-smoothing additive coloured Vanka sweeps, omega = 0.7).
+Default workload: the 100 x 16 x 16 hexahedral box, dG(1), Q2/P1disc (n_K = 170,
+1 518 134 unknowns, 4 levels).
 
 value = Vanka cell-sweeps performed per second over the timed steps: every
 V-cycle applies nu_pre + nu_post sweeps on each level l >= 1, each sweep visits
 every cell of the level once.  The headline runs with FP32 patch inverses; the
-same line carries the FP64 run, the GMRES time to 1e-8 of both, the roofline of
-the dominant kernel (the patch apply) and the FP64 CPU oracle timed on a bounded
-sample of the same workload.
+same line carries the FP64 leg, the GMRES time to 1e-8 of both, the roofline of
+the whole finest-level sweep (with each of its kernels, the patch inversion and
+the coarse block inversion beside it), the 176 x 32 dG(2) channel's figures and
+the FP64 CPU oracle timed phase by phase on a bounded sample.
 
 python bench.py [--steps K] [--warmup W] [--config NAME] [--prec f32|f64|bf16]
 """
@@ -130,25 +133,6 @@ def timed_steps(torch, step, reps):
     res = [step() for _ in range(reps)]
     torch.cuda.synchronize()
     return time.perf_counter() - t0, res
-
-
-def cpu_baseline(P, nu, restart, n_steps_total_cells):
-    """The FP64 oracle on the host: one full step (setup + GMRES to 1e-8)."""
-    import oracle
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        threads = 1
-    t0 = time.perf_counter()
-    H = oracle.OracleHierarchy(P.levels)
-    x, its, hist, conv, rel = oracle.gmres(P.finest.J, P.b, lambda v: oracle.vcycle(H, v, *nu),
-                                           restart=restart, max_iter=300, rtol=1e-8)
-    dt = time.perf_counter() - t0
-    cs = its * n_steps_total_cells
-    return {"value": cs / dt, "unit": "cell-sweeps/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"one full step (setup + GMRES to 1e-8, {its} iterations) of the same workload, "
-                      f"{dt:.1f} s"}, x, its
 
 
 def run_batch(args, torch, vk, dev):
@@ -476,16 +460,232 @@ def run_newton_march(args, torch, vk, dev):
     print(json.dumps(out), flush=True)
 
 
+def sweep_bytes(L, prec):
+    """Algorithmic bytes of one additive sweep of level L that forms its defect (Eq. 3.5 with
+    r = b - J d): N_c n_K^2 s_inv (the stored inverses) + nnz (8 + 4) (the CSR values and columns of
+    J) + 4 (n + 1) (row pointers) + 3 * 8 n (b and d read, d written) + 4 N_c n_K (the cell -> DoF
+    map).  The gathered defect entries and the per-DoF sums are taken as cache-resident."""
+    nK, Nc, n = L.mesh.n_K, L.mesh.n_cells, L.n
+    return Nc * nK * nK * PREC_BYTES[prec] + L.J.nnz * 12 + 4 * (n + 1) + 24 * n + 4 * Nc * nK
+
+
+def spmv_bytes(L):
+    """Algorithmic bytes of one defect r = b - J d on level L: values and columns, the int64 row
+    pointers, d and b read once, r written."""
+    return L.J.nnz * 12 + 8 * (L.n + 1) + 24 * L.n
+
+
+def gather_bytes(L, prec):
+    """Algorithmic bytes of one DoF gather d += omega z / p on level L: each cell product y_K entry
+    read once (FP64 or FP32), the fixed-width cell lists (8 int32 per DoF in 3D, 4 in 2D), 1/p read,
+    d read and written."""
+    w = 8 if L.mesh.d == 3 else 4
+    sy = 8 if prec == "f64" else 4
+    return L.mesh.n_cells * L.mesh.n_K * sy + L.n * (4 * w + 24)
+
+
+def roofline_entry(bound, achieved, peak, unit, **extra):
+    out = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak}
+    out.update(extra)
+    return out
+
+
+FP64_PEAK_TFS = 78.6   # MI355X FP64 (vector and matrix), TFLOP/s
+
+
+def measure(torch, vk, S, P, b, x, nu, restart, max_iter, steps, warmup, prec, label):
+    """Warm-up, then `steps` timed steps (setup + GMRES to 1e-8) with the finest level's sweeps,
+    SpMV, patch GEMV, DoF gather and patch inversion timed by HIP events inside the timed region;
+    then the block inversion of the coarsest level from two more steps.  Returns the record."""
+    L = len(P.levels) - 1
+    fine = P.finest
+    cs_per_vc = cells_sweeps_per_vcycle(P, *nu)
+    for w in range(warmup):
+        its, rel = run_step(S, b, x, nu, restart, max_iter)
+        log(f"[bench] {label} warmup {w}: {its} its, rel {rel:.2e}")
+    kinds = ["sweep", "spmv", "patch_gemv", "dof_gather", "patch_setup"]
+    S.vk_timing_kinds(kinds)
+    S.vk_timing_enable(True, L)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    total_its = 0
+    for _ in range(steps):
+        its, rel = run_step(S, b, x, nu, restart, max_iter)
+        total_its += its
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    live = {k: S.vk_timing_read(k, L) for k in kinds}
+    S.vk_timing_kinds(["block_invert"])
+    S.vk_timing_enable(True, 0)
+    for _ in range(2):
+        run_step(S, b, x, nu, restart, max_iter)
+    live["block_invert"] = S.vk_timing_read("block_invert", 0)
+    S.vk_timing_enable(False)
+    S.vk_timing_kinds(None)
+    avg = {k: (ms / n if n else None) for k, (n, ms) in live.items()}
+    log(f"[bench] {label}: timed {steps} steps in {dt:.3f} s, {total_its} GMRES its; finest sweep "
+        f"{avg['sweep']} ms, spmv {avg['spmv']} ms, gemv {avg['patch_gemv']} ms, setup {avg['patch_setup']} ms")
+    bs = sweep_bytes(fine, prec)
+    sweep_gbs = bs / (avg["sweep"] * 1e-3) / 1e9
+    kern = {
+        "spmv": roofline_entry("hbm", spmv_bytes(fine) / (avg["spmv"] * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s",
+                               bytes_per_launch=spmv_bytes(fine), avg_launch_ms=avg["spmv"],
+                               launches=live["spmv"][0]),
+        "patch_gemv": roofline_entry("hbm", patch_gemv_bytes(fine, prec) / (avg["patch_gemv"] * 1e-3) / 1e9,
+                                     HBM_PEAK_GBS, "GB/s", bytes_per_launch=patch_gemv_bytes(fine, prec),
+                                     avg_launch_ms=avg["patch_gemv"], launches=live["patch_gemv"][0]),
+        "dof_gather": roofline_entry("hbm", gather_bytes(fine, prec) / (avg["dof_gather"] * 1e-3) / 1e9,
+                                     HBM_PEAK_GBS, "GB/s", bytes_per_launch=gather_bytes(fine, prec),
+                                     avg_launch_ms=avg["dof_gather"], launches=live["dof_gather"][0]),
+    }
+    flops_setup = 2.0 * fine.mesh.n_K ** 3 * fine.mesh.n_cells
+    if avg["patch_setup"]:
+        kern["patch_setup"] = roofline_entry("alu", flops_setup / (avg["patch_setup"] * 1e-3) / 1e12, FP64_PEAK_TFS,
+                                             "TFLOP/s", flops_per_launch=flops_setup,
+                                             avg_launch_ms=avg["patch_setup"], launches=live["patch_setup"][0],
+                                             note="finest-level patch gather + FP64 Gauss-Jordan inversions, "
+                                                  "2 n_K^3 flop per cell")
+    n0 = P.levels[0].n
+    if avg["block_invert"]:
+        fl = 2.0 * n0 ** 3
+        kern["block_invert"] = roofline_entry("mfma", fl / (avg["block_invert"] * 1e-3) / 1e12, FP64_PEAK_TFS,
+                                              "TFLOP/s", flops_per_launch=fl, avg_ms=avg["block_invert"],
+                                              note=f"coarsest-level {n0}-unknown FP64 Gauss-Jordan inverse (a "
+                                                   f"chain of panel and update launches, bracketed as one)")
+    setup_ms, gmres_ms, its_h, rel_h = phase_times(torch, S, b, x, nu, restart, max_iter)
+    return {
+        "value": total_its * cs_per_vc / dt, "ms_per_step": dt / steps * 1e3, "steps": steps,
+        "gmres_iterations": its_h, "gmres_true_rel_residual": rel_h, "gmres_ms_to_1e-8": gmres_ms,
+        "setup_ms": setup_ms,
+        "roofline": roofline_entry("hbm", sweep_gbs, HBM_PEAK_GBS, "GB/s", traffic=None,
+                                   kernel="whole finest-level additive sweep with its defect (SpMV + patch GEMV "
+                                          "+ DoF gather), bracketed by events as one unit",
+                                   bytes_per_sweep=bs, avg_sweep_ms=avg["sweep"], sweeps=live["sweep"][0],
+                                   kernels=kern),
+        "finest_cell_sweeps_per_s": fine.mesh.n_cells / (avg["sweep"] * 1e-3),
+    }
+
+
+def cpu_baseline_protocol(P, nu, restart, cs_per_vc, its_gpu):
+    """The FP64 oracle timed phase by phase on a bounded sample of the same workload, median of 5
+    after one warm-up, on one core and on all cores:
+      setup_per_cell: patch gather + LAPACK inverse of 16 finest cells, per cell;
+      spmv: r = b - J d with the whole finest J (the defect of one sweep);
+      patch_apply_per_cell: the einsum of A_K r_K and its scatter for 1 024 cells (the 16 sampled
+        inverses repeated: the cost depends on the shapes only), per cell;
+      coarse_lu: LU factorisation of the dense coarsest matrix (all cores only).
+    value = finest-level cell-sweeps/s of the oracle's additive sweep, spmv + N_c * patch_apply
+    (all cores); step_estimate_s = setup (every level's cells + coarse LU) + GMRES iterations x
+    V-cycle sweeps (the sweeps dominate the oracle's V-cycle), with the GPU's iteration count."""
+    import platform
+    import oracle
+    from threadpoolctl import threadpool_limits
+    fine = P.finest
+    J = fine.J
+    cd = fine.cell_dofs
+    rng = np.random.default_rng(3)
+    cells = np.sort(rng.choice(fine.mesh.n_cells, 16, replace=False))
+    rep = np.resize(cells, 1024)
+    d = rng.standard_normal(fine.n)
+    r = P.b - J @ d
+    A16 = None
+
+    def med(fn, reps=5):
+        fn()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    def setup16():
+        nonlocal A16
+        A16 = oracle.invert_patches(oracle.patch_matrices(J, cd[cells]))
+
+    def apply1024():
+        A = A16[np.arange(1024) % 16]
+        y = np.einsum("kij,kj->ki", A, r[cd[rep]])
+        z = np.zeros(fine.n)
+        np.add.at(z, cd[rep].ravel(), y.ravel())
+
+    J0 = P.levels[0].J.toarray()
+    out = {}
+    for cores in ("1", "all"):
+        lim = 1 if cores == "1" else None
+        with threadpool_limits(limits=lim):
+            ph = {"setup_per_cell_ms": med(setup16) / 16 * 1e3,
+                  "spmv_ms": med(lambda: P.b - J @ d) * 1e3,
+                  "patch_apply_per_cell_ms": med(apply1024) / 1024 * 1e3}
+            if cores == "all":
+                import scipy.linalg as sla
+                ph["coarse_lu_ms"] = med(lambda: sla.lu_factor(J0), reps=3) * 1e3
+        out[cores] = ph
+    a = out["all"]
+    sweep_s = (a["spmv_ms"] + a["patch_apply_per_cell_ms"] * fine.mesh.n_cells) * 1e-3
+    cells_all = sum(L.mesh.n_cells for L in P.levels[1:])
+    setup_s = a["setup_per_cell_ms"] * cells_all * 1e-3 + a["coarse_lu_ms"] * 1e-3
+    vcycle_s = sum((sum(nu)) * (a["spmv_ms"] * L.J.nnz / J.nnz + a["patch_apply_per_cell_ms"] * L.mesh.n_cells)
+                   * 1e-3 for L in P.levels[1:])
+    step_s = setup_s + its_gpu * vcycle_s
+    try:
+        model = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")][0]
+    except Exception:
+        model = platform.processor()
+    try:
+        from threadpoolctl import threadpool_info
+        threads = int(max([i.get("num_threads", 1) for i in threadpool_info()] + [1]))
+    except Exception:
+        threads = 1
+    return {"value": fine.mesh.n_cells / sweep_s, "unit": "cell-sweeps/s", "cores": threads, "kind": "oracle",
+            "sample": "finest-level additive sweep of the same workload from timed parts: the SpMV with the "
+                      "whole J, and the patch apply of 1 024 cells scaled to all cells (median of 5 after a "
+                      "warm-up, all cores)",
+            "phases_1_core": out["1"], "phases_all_cores": out["all"], "cpu_model": model,
+            "nproc": os.cpu_count(), "step_estimate_s": step_s,
+            "step_estimate_cell_sweeps_per_s": its_gpu * cs_per_vc / step_s,
+            "step_estimate": "setup of every level's patches + coarse LU + GMRES iterations (the GPU's count) "
+                             "x V-cycle sweeps, from the phase timings"}
+
+
+def run_extra_channel(torch, vk, dev, nu, restart, max_iter, steps):
+    """The 176 x 32 dG(2) channel (5 levels, n_K = 63): FP32, FP64 and BF16 inverses."""
+    from synth import build_problem
+    P = build_problem("channel2d_176x32_k2")
+    levels = [vk.upload_level(L, dev) for L in P.levels]
+    b = torch.from_numpy(P.b).to(dev)
+    x = torch.zeros_like(b)
+    cs_per_vc = cells_sweeps_per_vcycle(P, *nu)
+    out = {"workload": "channel2d_176x32_k2", "unknowns": int(P.finest.n), "finest_cells": int(P.finest.mesh.n_cells),
+           "patch_size": int(P.finest.mesh.n_K)}
+    for prec in ("f32", "f64", "bf16"):
+        S = vk.Solver(levels)
+        S.vk_set_workspace(prec, restart, device=dev)
+        S.vanka_setup(0.7, "additive")
+        S.vk_autotune(10)
+        for _ in range(3):
+            run_step(S, b, x, nu, restart, max_iter)
+        dt, res = timed_steps(torch, lambda: run_step(S, b, x, nu, restart, max_iter), steps)
+        s_ms, g_ms, its, rel = phase_times(torch, S, b, x, nu, restart, max_iter)
+        out[prec] = {"value": sum(r[0] for r in res) * cs_per_vc / dt, "ms_per_step": dt / steps * 1e3,
+                     "setup_ms": s_ms, "gmres_ms_to_1e-8": g_ms, "gmres_iterations": its,
+                     "gmres_true_rel_residual": rel,
+                     "finest_cell_sweeps_per_s": sweep_rate(torch, S, P, P.b)}
+        S.close()
+        log(f"[bench] channel 176x32 {prec}: {out[prec]['ms_per_step']:.2f} ms/step, {its} its")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="channel2d_176x32_k2")
+    ap.add_argument("--config", default="box3d_100x16x16_k1")
     ap.add_argument("--prec", default="f32", choices=["f64", "f32", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-compare", action="store_true", help="skip the FP64/BF16 comparison runs")
-    ap.add_argument("--compare-precs", default="f64,bf16", help="precisions of the comparison runs")
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP64 leg and the 2D channel figures")
+    ap.add_argument("--compare-precs", default="f64", help="precisions of the comparison legs")
     ap.add_argument("--no-graphs", action="store_true", help="batch: launch Arnoldi steps eagerly")
     ap.add_argument("--epochs", type=int, default=40, help="learned guess: training epochs")
     ap.add_argument("--pmc-probe", action="store_true", help="short fixed workload for hardware-counter runs")
@@ -497,7 +697,7 @@ def main():
 
     import torch
     import paper_2210_02690_amd as vk
-    from synth import build_problem, CONFIGS
+    from synth import build_problem
 
     dev = torch.device("cuda:0")
     if args.config == "batch64_seed0":
@@ -518,133 +718,74 @@ def main():
     levels = [vk.upload_level(L, dev) for L in P.levels]
     b = torch.from_numpy(P.b).to(dev)
     x = torch.zeros_like(b)
-    cs_per_vc = cells_sweeps_per_vcycle(P, *nu)
     fine = P.finest
-    l_fine = len(P.levels) - 1
 
     def make(prec):
         S = vk.Solver(levels)
         S.vk_set_workspace(prec, restart, device=dev)
+        S.vanka_setup(0.7, "additive")
+        S.vk_autotune(10)
         return S
 
     S = make(args.prec)
-    S.vanka_setup(0.7, "additive")
-    S.vk_autotune(10)
-    for w in range(args.warmup):
-        its, rel = run_step(S, b, x, nu, restart, max_iter)
-        log(f"[bench] warmup {w}: {its} its, rel {rel:.2e}")
-    # timed region: events time one in TIMING_EVERY launches of the dominant kernel (the
-    # roofline's input), taken by the launch itself
-    S.vk_timing_kinds(["patch_gemv"], TIMING_EVERY)
-    S.vk_timing_enable(True, l_fine)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    total_its = 0
-    for _ in range(args.steps):
-        its, rel = run_step(S, b, x, nu, restart, max_iter)
-        total_its += its
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    n_apply, ms_apply = S.vk_timing_read("patch_gemv", l_fine)
-    # the other finest-level kernels, for the record, from three more (untimed) steps
-    S.vk_timing_kinds(["dof_gather", "spmv"])
-    S.vk_timing_enable(True, l_fine)
-    for _ in range(3):
-        run_step(S, b, x, nu, restart, max_iter)
-    n_gather, ms_gather = S.vk_timing_read("dof_gather", l_fine)
-    n_spmv, ms_spmv = S.vk_timing_read("spmv", l_fine)
-    S.vk_timing_enable(False)
-    S.vk_timing_kinds(None)
-    log(f"[bench] timed {args.steps} steps in {dt:.3f} s, {total_its} GMRES its")
-    value = total_its * cs_per_vc / dt
-    ms_per_step = dt / args.steps * 1e3
-
-    # roofline of the dominant kernel: the finest-level patch GEMV (all cells)
-    bytes_launch = patch_gemv_bytes(fine, args.prec)
-    avg_ms = ms_apply / max(n_apply, 1)
-    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-
-    setup_ms, gmres_ms, its_h, rel_h = phase_times(torch, S, b, x, nu, restart, max_iter)
+    head = measure(torch, vk, S, P, b, x, nu, restart, max_iter, args.steps, args.warmup, args.prec, args.prec)
     x_head = x.cpu().numpy()
-    out = {
-        "metric": "Vanka cells·sweeps/s + GMRES time to 1e-8 rel. residual, FP32-patch vs FP64",
-        "value": value, "unit": "cell-sweeps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"f32": "f32+f64", "bf16": "bf16+f32+f64", "f64": "f64"}[args.prec],
-        "data": "synthetic (seeded Newton linearisation of a channel flow; no dataset)",
-        "config": {"workload": args.config, "unknowns": int(fine.n), "levels": len(P.levels),
-                   "finest_cells": int(fine.mesh.n_cells), "patch_size": int(fine.mesh.n_K),
-                   "nnz_finest": int(fine.J.nnz), "patch_precision": args.prec, "gmres_restart": restart,
-                   "nu_pre": nu[0], "nu_post": nu[1], "omega": 0.7, "parallelism": "single GPU"},
-        "gmres_iterations": its_h, "gmres_true_rel_residual": rel_h,
-        "gmres_ms_to_1e-8": gmres_ms, "setup_ms": setup_ms,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": pmc_traffic(args.prec, args.config),
-                     "kernel": "patch_gemv (finest level, all cells per launch)",
-                     "bytes_per_launch": bytes_launch, "avg_launch_ms": avg_ms, "launches": n_apply,
-                     "timed_one_in": TIMING_EVERY},
-        "finest_level_kernels_avg_ms": {"patch_gemv": avg_ms, "dof_gather": ms_gather / max(n_gather, 1),
-                                        "spmv": ms_spmv / max(n_spmv, 1)},
-    }
-    try:
-        out["finest_sweep_rate"] = {args.prec: sweep_rate(torch, S, P, P.b)}
-    except Exception as e:  # pragma: no cover
-        log(f"[bench] sweep rate failed: {e}")
-    # context for the roofline: plain streaming kernels on the same GPU
-    cg, rg = stream_rates_gbs(torch, dev)
-    out["roofline"]["copy_GBps"] = cg
-    out["roofline"]["read_GBps"] = rg
-    out["roofline"]["frac_of_read"] = achieved / rg
-
+    gmres_x_true = float(np.linalg.norm(P.b - fine.J @ x_head) / np.linalg.norm(P.b))
     # the same steps with every Arnoldi step replayed from a recorded hipGraph
     S.vk_set_graphs(True)
     run_step(S, b, x, nu, restart, max_iter)  # records the step graphs
     reps = max(5, args.steps // 2)
     dt_g, res = timed_steps(torch, lambda: run_step(S, b, x, nu, restart, max_iter), reps)
     s_ms, g_ms, its_g, rel_g = phase_times(torch, S, b, x, nu, restart, max_iter)
-    out["graphs"] = {"value": sum(r[0] for r in res) * cs_per_vc / dt_g, "ms_per_step": dt_g / reps * 1e3,
-                     "gmres_ms_to_1e-8": g_ms, "setup_ms": s_ms, "gmres_iterations": its_g,
-                     "rel_diff_solution_vs_headline": float(np.linalg.norm(x.cpu().numpy() - x_head)
-                                                             / np.linalg.norm(x_head)),
-                     "graph_recordings": S.vk_graph_stats()[0]}
+    graphs = {"value": sum(r[0] for r in res) * cells_sweeps_per_vcycle(P, *nu) / dt_g,
+              "ms_per_step": dt_g / reps * 1e3, "gmres_ms_to_1e-8": g_ms, "setup_ms": s_ms,
+              "gmres_iterations": its_g,
+              "rel_diff_solution_vs_eager": float(np.linalg.norm(x.cpu().numpy() - x_head) / np.linalg.norm(x_head)),
+              "graph_recordings": S.vk_graph_stats()[0]}
     log(f"[bench] graphs: {dt_g / reps * 1e3:.2f} ms/step, gmres {g_ms:.2f} ms")
     S.vk_set_graphs(False)
     S.close()
-
+    cg, rg = stream_rates_gbs(torch, dev)
+    rf = head.pop("roofline")
+    rf["copy_GBps"] = cg
+    rf["read_GBps"] = rg
+    rf["frac_of_read"] = rf["achieved"] / rg
+    out = {
+        "metric": "Vanka cells·sweeps/s + GMRES time to 1e-8 rel. residual, FP32-patch vs FP64",
+        "value": head["value"], "unit": "cell-sweeps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f32": "f32+f64", "bf16": "bf16+f32+f64", "f64": "f64"}[args.prec],
+        "data": "synthetic (seeded Newton linearisation of a channel/box flow; no dataset)",
+        "config": {"workload": args.config, "unknowns": int(fine.n), "levels": len(P.levels),
+                   "finest_cells": int(fine.mesh.n_cells), "patch_size": int(fine.mesh.n_K),
+                   "nnz_finest": int(fine.J.nnz), "patch_precision": args.prec, "gmres_restart": restart,
+                   "nu_pre": nu[0], "nu_post": nu[1], "omega": 0.7, "parallelism": "single GPU"},
+        "gmres_iterations": head["gmres_iterations"], "gmres_true_rel_residual": head["gmres_true_rel_residual"],
+        "gmres_true_rel_residual_host": gmres_x_true,
+        "gmres_ms_to_1e-8": head["gmres_ms_to_1e-8"], "setup_ms": head["setup_ms"],
+        "finest_cell_sweeps_per_s": head["finest_cell_sweeps_per_s"],
+        "roofline": rf, "graphs": graphs,
+    }
     if not args.no_compare:
-        for prec in [p for p in args.compare_precs.split(",") if p and p != args.prec]:
+        for prec in [q for q in args.compare_precs.split(",") if q and q != args.prec]:
             S2 = make(prec)
-            S2.vanka_setup(0.7, "additive")
-            S2.vk_autotune(10)
-            run_step(S2, b, x, nu, restart, max_iter)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            k_its = 0
-            reps = max(3, args.steps // 4)
-            for _ in range(reps):
-                its2, _ = run_step(S2, b, x, nu, restart, max_iter)
-                k_its += its2
-            torch.cuda.synchronize()
-            dt2 = time.perf_counter() - t0
-            s_ms, g_ms, its2, rel2 = phase_times(torch, S2, b, x, nu, restart, max_iter)
+            rec = measure(torch, vk, S2, P, b, x, nu, restart, max_iter, max(3, args.steps // 2), 1, prec, prec)
             xs = x.cpu().numpy()
-            out[prec] = {"value": k_its * cs_per_vc / dt2, "ms_per_step": dt2 / reps * 1e3,
-                         "gmres_ms_to_1e-8": g_ms, "setup_ms": s_ms, "gmres_iterations": its2,
-                         "gmres_true_rel_residual": rel2,
-                         "rel_diff_solution_vs_headline": float(np.linalg.norm(xs - x_head) / np.linalg.norm(xs))}
-            try:
-                out["finest_sweep_rate"][prec] = sweep_rate(torch, S2, P, P.b)
-            except Exception:
-                pass
+            rec["rel_diff_solution_vs_headline"] = float(np.linalg.norm(xs - x_head) / np.linalg.norm(xs))
+            rec["gmres_ms_ratio_vs_headline"] = rec["gmres_ms_to_1e-8"] / head["gmres_ms_to_1e-8"]
+            out[prec] = rec
             S2.close()
-            log(f"[bench] {prec}: {its2} its, gmres {g_ms:.2f} ms, setup {s_ms:.2f} ms")
-
+            log(f"[bench] {prec}: {rec['gmres_iterations']} its, gmres {rec['gmres_ms_to_1e-8']:.2f} ms, "
+                f"sweep frac {rec['roofline']['frac']:.3f}")
+        if args.config != "channel2d_176x32_k2":
+            del levels
+            torch.cuda.empty_cache()
+            out["channel2d_176x32_k2"] = run_extra_channel(torch, vk, dev, nu, restart, max_iter,
+                                                           max(5, args.steps // 2))
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle ...")
-        cb, x_or, its_or = cpu_baseline(P, nu, restart, cs_per_vc)
-        cb["oracle_gmres_iterations"] = its_or
-        cb["rel_diff_headline_solution_vs_oracle"] = float(np.linalg.norm(x_head - x_or) / np.linalg.norm(x_or))
-        out["cpu_baseline"] = cb
+        out["cpu_baseline"] = cpu_baseline_protocol(P, nu, restart, cells_sweeps_per_vcycle(P, *nu),
+                                                    head["gmres_iterations"])
     print(json.dumps(out), flush=True)
 
 

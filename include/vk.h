@@ -298,7 +298,11 @@ typedef enum {
   VK_KERNEL_PATCH_SETUP = 2,    /* patch gather + Gauss-Jordan inverse */
   VK_KERNEL_PATCH_RESIDUAL = 3, /* multiplicative mode local defects */
   VK_KERNEL_PATCH_GEMV = 4,     /* y_K = A_K r_K for all cells (additive, DoF gather) */
-  VK_KERNEL_DOF_GATHER = 5      /* d += omega z / p from the y_K (additive, DoF gather) */
+  VK_KERNEL_DOF_GATHER = 5,     /* d += omega z / p from the y_K (additive, DoF gather) */
+  VK_KERNEL_SWEEP = 6,          /* one whole additive sweep that starts with its defect b - J d
+                                   (SpMV, patch GEMVs, DoF gather; Eq. 3.5); the first sweep from
+                                   d = 0, which has no defect to form, is not recorded */
+  VK_KERNEL_BLOCK_INVERT = 7    /* the inversion of one level's directly solved blocks (setup) */
 } vk_kernel_kind;
 vk_status vk_timing_enable(vk_ctx* ctx, int32_t enable, int32_t level);
 vk_status vk_timing_kinds(vk_ctx* ctx, uint32_t mask, int32_t every);

@@ -97,7 +97,7 @@ _SIGS = {
     "vk_mlp_slab_extrapolate": (ctypes.c_int, [_P, _I64, _I32, _PD, _P, _P]),
 }
 KERNEL_KINDS = {"patch_apply": 0, "spmv": 1, "patch_setup": 2, "patch_residual": 3, "patch_gemv": 4,
-                "dof_gather": 5}
+                "dof_gather": 5, "sweep": 6, "block_invert": 7}
 SWEEP_VARIANTS = {"dof_gather": 0, "coloured_scatter": 1, "dof_gather_offsets": 2}
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)

@@ -169,6 +169,7 @@ size_t plan_workspace(vk_ctx* ctx, vk_prec prec, int32_t restart, char* base) {
   ctx->n_partial = (ns * 64 > 1024 ? ns * 64 : 1024) * (m + 1);
   ctx->partial = cv.take<double>(ctx->n_partial);
   ctx->scal = cv.take<double>(16);
+  ctx->ghist = cv.take<double>(2 * (int64_t)(m + 1));
   ctx->d_seg = cv.take<int64_t>(ns + 1);
   ctx->seg_scal = cv.take<double>(5 * (int64_t)ns);
   ctx->seg_flags = cv.take<int32_t>(3 * (int64_t)ns);
@@ -208,7 +209,7 @@ struct Timed {
   int32_t slot = -1;
   Timed(vk_ctx* c, int32_t kind, int32_t level, hipStream_t s = nullptr, bool launch_events = false)
       : ctx(c), stream(s ? s : c->stream), in_launch(launch_events) {
-    if (!ctx->timing || (int32_t)ctx->recs.size() >= kTimingPool) return;
+    if (!ctx->timing || (int32_t)ctx->recs.size() >= kTimingPool || level < -1) return;
     if (ctx->timing_level >= 0 && level != ctx->timing_level) return;
     if (!((ctx->timing_kinds >> kind) & 1u)) return;
     if (ctx->timing_seen++ % ctx->timing_every != 0) return;
@@ -223,7 +224,25 @@ struct Timed {
   }
 };
 
+// Scratch of one smoothing call: the defect r (n_l doubles), the per-cell products y_K (one entry
+// per (cell, local DoF) of the level, FP64 or FP32) and the multiplicative mode's local defects.
+struct sweep_bufs {
+  double* r;
+  void* Y;
+  double* rK;
+};
+
+vk_status smooth_with(vk_ctx* ctx, int l, const double* b, double* d, int32_t sweeps, bool zero,
+                      const sweep_bufs& buf);
+
+sweep_bufs workspace_bufs(vk_ctx* ctx, int l) { return {ctx->lv[l].r, ctx->Y, ctx->rK}; }
+
 vk_status smooth(vk_ctx* ctx, int l, const double* b, double* d, int32_t sweeps, bool zero) {
+  return smooth_with(ctx, l, b, d, sweeps, zero, workspace_bufs(ctx, l));
+}
+
+vk_status smooth_with(vk_ctx* ctx, int l, const double* b, double* d, int32_t sweeps, bool zero,
+                      const sweep_bufs& buf) {
   vk_level& L = ctx->lv[l];
   hipStream_t s = ctx->stream;
   // from d = 0 the first additive DoF-gather sweep writes d instead of adding to a zeroed d
@@ -233,18 +252,20 @@ vk_status smooth(vk_ctx* ctx, int l, const double* b, double* d, int32_t sweeps,
   for (int it = 0; it < sweeps; ++it) {
     if (ctx->mode == VK_ADDITIVE) {
       const double* r = b;
+      // a whole sweep that forms its defect, bracketed as one unit (every kernel of Eq. 3.5)
+      Timed tsw(ctx, VK_KERNEL_SWEEP, (it == 0 && zero) ? -2 : l);
       if (!(it == 0 && zero)) {
         Timed t(ctx, VK_KERNEL_SPMV, l);
-        VK_TRY(launch_spmv(s, L.J, L.lpr_J, -1.0, d, 1.0, b, L.r));
-        r = L.r;
+        VK_TRY(launch_spmv(s, L.J, L.lpr_J, -1.0, d, 1.0, b, buf.r));
+        r = buf.r;
       }
       if (gather) {
         for (const vk_group& G : L.groups) {
           Timed t(ctx, VK_KERNEL_PATCH_GEMV, l, s, true);
-          VK_TRY(launch_patch_gemv(s, G, ctx->prec, r, ctx->Y, 0, t.start(), t.stop()));
+          VK_TRY(launch_patch_gemv(s, G, ctx->prec, r, buf.Y, 0, t.start(), t.stop()));
         }
         Timed t(ctx, VK_KERNEL_DOF_GATHER, l);
-        VK_TRY(launch_dof_gather(s, L, ctx->prec, ctx->Y, ctx->omega, d, write_first && it == 0,
+        VK_TRY(launch_dof_gather(s, L, ctx->prec, buf.Y, ctx->omega, d, write_first && it == 0,
                                  ctx->sweep_variant == VK_SWEEP_DOF_GATHER));
       } else {
         for (const vk_group& G : L.groups)
@@ -262,10 +283,10 @@ vk_status smooth(vk_ctx* ctx, int l, const double* b, double* d, int32_t sweeps,
           if (c >= G.n_colours) continue;
           {
             Timed t(ctx, VK_KERNEL_PATCH_RESIDUAL, l);
-            VK_TRY(launch_patch_residual(s, L.J, L.lpr_J, G, c, b, d, ctx->rK));
+            VK_TRY(launch_patch_residual(s, L.J, L.lpr_J, G, c, b, d, buf.rK));
           }
           Timed t(ctx, VK_KERNEL_PATCH_APPLY, l);
-          VK_TRY(launch_patch_apply(s, G, ctx->prec, c, nullptr, ctx->rK, d, nullptr, ctx->omega));
+          VK_TRY(launch_patch_apply(s, G, ctx->prec, c, nullptr, buf.rK, d, nullptr, ctx->omega));
         }
       }
     }
@@ -325,6 +346,36 @@ vk_status to_dev(vk_ctx* ctx, void* dst, const void* src, size_t bytes) {
 
 vk_status read_scalars(vk_ctx* ctx, const double* dev, int count, double* out) {
   return to_host(ctx, out, dev, sizeof(double) * count);
+}
+
+// Two device-to-host copies behind one synchronisation (both fit the pinned staging buffer).
+vk_status to_host2(vk_ctx* ctx, void* dst0, const void* src0, size_t b0, void* dst1, const void* src1, size_t b1) {
+  if (b0 + b1 > ctx->pinned_bytes) {
+    VK_CHECK(to_host(ctx, dst0, src0, b0));
+    return to_host(ctx, dst1, src1, b1);
+  }
+  VK_TRY(hipMemcpyAsync(ctx->pinned, src0, b0, hipMemcpyDeviceToHost, ctx->stream));
+  VK_TRY(hipMemcpyAsync(ctx->pinned + b0, src1, b1, hipMemcpyDeviceToHost, ctx->stream));
+  VK_TRY(hipStreamSynchronize(ctx->stream));
+  std::memcpy(dst0, ctx->pinned, b0);
+  std::memcpy(dst1, ctx->pinned + b0, b1);
+  return VK_OK;
+}
+
+// How many Arnoldi steps to enqueue before the host next looks at the residual estimates.  The
+// convergence test runs on the host from values the device wrote, so every look is one round trip
+// in which the GPU idles; steps enqueued past convergence are discarded, each a V-cycle of wasted
+// work.  From the mean reduction factor per step so far, rho = (r_now / r_start)^(1/steps), the
+// steps still needed are log(tol / r_now) / log(rho); one fewer than that is enqueued (at most 8),
+// so a steady rate costs two looks and no wasted step.  Without a rate yet: one step.
+int32_t steps_ahead(double r_start, double r_now, int32_t steps, double tol) {
+  if (steps < 1 || !(r_now > tol) || !(r_start > 0.0) || !(r_now > 0.0)) return 1;
+  const double rho = std::pow(r_now / r_start, 1.0 / steps);
+  if (!(rho < 0.999)) return 1;
+  const double need = std::log(tol / r_now) / std::log(rho);
+  if (!(need > 2.0)) return 1;
+  const double c = std::floor(need) - 1.0;
+  return c >= 8.0 ? 8 : (int32_t)c;
 }
 
 // Runs enqueue() on ctx->stream, or, with graphs on, replays the graph held in `slot` when it was
@@ -739,14 +790,30 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
       VK_TRY(launch_inv_count(ps, L.J.n_rows, count, L.inv_p));
       VK_TRY(launch_dof_map(ps, L, count));
     }
+    // the colouring: cells of one colour must share no DoF (status words [700 + l]), checked
+    // once per mesh with one 64-bit colour mask per DoF in the level's iterate vector
+    VK_TRY(launch_fill_i32(ps, 64, 0, ctx->status + 700));
+    for (int l = 1; l < ctx->n_levels; ++l) {
+      vk_level& L = ctx->lv[l];
+      unsigned long long* mask = reinterpret_cast<unsigned long long*>(L.d);
+      VK_TRY(launch_fill(ps, L.J.n_rows, 0.0, L.d));
+      for (const vk_group& G : L.groups)
+        VK_TRY(launch_colour_check(ps, G.n_K, G.cell_dofs, G.colour_cells, G.colour_ptr.data(), G.n_colours, mask,
+                                   ctx->status + 700 + l));
+    }
     // fixed-width lists when every DoF lies in at most 8 cells (status words [600 + l]: the
     // largest multiplicity of level l); read once per mesh
     VK_TRY(launch_fill_i32(ps, 64, 0, ctx->status + 600));
     for (int l = 1; l < ctx->n_levels; ++l)
       if (!ctx->lv[l].groups.empty()) VK_TRY(launch_dof_max_count(ps, ctx->lv[l], ctx->status + 600 + l));
     VK_TRY(hipStreamSynchronize(ps));
-    int32_t mc[64];
+    int32_t mc[64], cc[64];
     VK_CHECK(to_host(ctx, mc, ctx->status + 600, sizeof(mc)));
+    VK_CHECK(to_host(ctx, cc, ctx->status + 700, sizeof(cc)));
+    for (int l = 1; l < ctx->n_levels; ++l)
+      if (cc[l] != 0)
+        return fail(ctx, VK_ERR_ARG, "level " + std::to_string(l) +
+                                         ": two cells of one colour share a DoF (the colouring must be DoF-disjoint)");
     for (int l = 1; l < ctx->n_levels; ++l) {
       vk_level& L = ctx->lv[l];
       L.ell_w = L.groups.empty() ? 0 : (mc[l] <= 4 ? 4 : (mc[l] <= 8 ? 8 : 0));
@@ -802,7 +869,10 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
       VK_TRY(hipStreamWaitEvent(st, ctx->fork_ev, 0));
     }
     vk_level& L = ctx->lv[blevels[k]];
-    VK_TRY(launch_block_invert(st, L, ctx->status, &L.cb_W));
+    {
+      Timed t(ctx, VK_KERNEL_BLOCK_INVERT, blevels[k], st);
+      VK_TRY(launch_block_invert(st, L, ctx->status, &L.cb_W));
+    }
     if (k > 0) {
       VK_TRY(hipEventRecord(ctx->xjoin[k - 1], st));
       ctx->n_xside = (int)k;
@@ -885,6 +955,7 @@ vk_status gmres_solve(vk_ctx* ctx, const double* b, double* x, int32_t restart, 
   bool first = true;
   bool converged = false;
   double beta = 0.0;
+  double r_start = 0.0, r_last = 0.0;  // residual estimates: at the first restart's start, latest
   for (;;) {
     double* V0 = ctx->V;
     VK_TRY(launch_spmv(s, F.J, F.lpr_J, -1.0, x, 1.0, b, V0));
@@ -895,7 +966,9 @@ vk_status gmres_solve(vk_ctx* ctx, const double* b, double* x, int32_t restart, 
     if (first) {
       if (history) history[0] = beta;
       first = false;
+      r_start = beta;
     }
+    r_last = beta;
     if (beta <= tol) {
       converged = true;
       break;
@@ -903,36 +976,56 @@ vk_status gmres_solve(vk_ctx* ctx, const double* b, double* x, int32_t restart, 
     if (its >= max_iter) break;
     VK_TRY(launch_scale_by_inv(s, n, V0, sc + 1, V0));
     VK_TRY(launch_gmres_init(s, restart, ctx->H, ctx->g, sc + 1));
-    int32_t jn = 0;
-    for (int32_t j = 0; j < restart; ++j) {
-      double* Vj = ctx->V + (int64_t)j * ldv;
-      double* Vn = ctx->V + (int64_t)(j + 1) * ldv;
-      double* Zj = ctx->Z + (int64_t)j * ldv;
-      double* Hc = ctx->H + (int64_t)j * ldh;
-      auto step = [&]() -> vk_status {
-        hipStream_t q = ctx->stream;
-        VK_CHECK(vcycle_level(ctx, L, Vj, Zj, nu_pre, nu_post));
-        VK_TRY(launch_spmv(q, F.J, F.lpr_J, 1.0, Zj, 0.0, nullptr, Vn));
-        // classical Gram-Schmidt, applied twice
-        VK_TRY(launch_mdot(q, n, ctx->V, ldv, j + 1, Vn, ctx->partial, ctx->n_partial, Hc));
-        VK_TRY(launch_maxpy(q, n, ctx->V, ldv, j + 1, Hc, -1.0, Vn));
-        VK_TRY(launch_mdot(q, n, ctx->V, ldv, j + 1, Vn, ctx->partial, ctx->n_partial, ctx->h2));
-        VK_TRY(launch_maxpy(q, n, ctx->V, ldv, j + 1, ctx->h2, -1.0, Vn));
-        VK_TRY(launch_dot(q, n, Vn, Vn, ctx->partial, ctx->n_partial, Hc + j + 1, true));
-        VK_TRY(launch_givens(q, j, ldh, ctx->H, ctx->h2, ctx->cs, ctx->sn, ctx->g, sc + 2));
-        VK_TRY(launch_scale_by_inv(q, n, Vn, sc + 3, Vn));
-        return VK_OK;
-      };
-      const int64_t key[6] = {j, ldh, nu_pre, nu_post, 0, 0};
-      VK_CHECK(replay(ctx, 1 + (size_t)j, key, step));
-      VK_CHECK(read_scalars(ctx, sc + 2, 2, hb));
+    // Step j writes |g_{j+1}| and ||w|| to ghist[2j], ghist[2j + 1] and nothing the earlier steps'
+    // results depend on (column j of H, rotation j, g[j], g[j + 1], v_{j+1}, z_j), so steps enqueued
+    // past the stopping step leave the iterate unchanged: the host enqueues several steps, reads
+    // their estimates in one round trip and takes the first that stops.
+    int32_t jn = 0, j = 0;
+    bool stop = false;
+    while (!stop && j < restart && its < max_iter) {
+      int32_t ahead = steps_ahead(r_start, r_last, its, tol);
+      ahead = std::min(ahead, std::min(restart - j, max_iter - its));
+      const int32_t j0 = j;
+      for (int32_t q = 0; q < ahead; ++q, ++j) {
+        double* Vj = ctx->V + (int64_t)j * ldv;
+        double* Vn = ctx->V + (int64_t)(j + 1) * ldv;
+        double* Zj = ctx->Z + (int64_t)j * ldv;
+        double* Hc = ctx->H + (int64_t)j * ldh;
+        double* out = ctx->ghist + 2 * (int64_t)j;
+        const int32_t jj = j;
+        auto step = [&]() -> vk_status {
+          hipStream_t qs = ctx->stream;
+          VK_CHECK(vcycle_level(ctx, L, Vj, Zj, nu_pre, nu_post));
+          VK_TRY(launch_spmv(qs, F.J, F.lpr_J, 1.0, Zj, 0.0, nullptr, Vn));
+          // classical Gram-Schmidt, applied twice
+          VK_TRY(launch_mdot(qs, n, ctx->V, ldv, jj + 1, Vn, ctx->partial, ctx->n_partial, Hc));
+          VK_TRY(launch_maxpy(qs, n, ctx->V, ldv, jj + 1, Hc, -1.0, Vn));
+          VK_TRY(launch_mdot(qs, n, ctx->V, ldv, jj + 1, Vn, ctx->partial, ctx->n_partial, ctx->h2));
+          VK_TRY(launch_maxpy(qs, n, ctx->V, ldv, jj + 1, ctx->h2, -1.0, Vn));
+          VK_TRY(launch_dot(qs, n, Vn, Vn, ctx->partial, ctx->n_partial, Hc + jj + 1, true));
+          VK_TRY(launch_givens(qs, jj, ldh, ctx->H, ctx->h2, ctx->cs, ctx->sn, ctx->g, out));
+          VK_TRY(launch_scale_by_inv(qs, n, Vn, out + 1, Vn));
+          return VK_OK;
+        };
+        const int64_t key[6] = {jj, ldh, nu_pre, nu_post, 0, 0};
+        VK_CHECK(replay(ctx, 1 + (size_t)jj, key, step));
+      }
+      double gh[2 * VK_MAX_RESTART];
+      VK_CHECK(read_scalars(ctx, ctx->ghist + 2 * (int64_t)j0, 2 * (j - j0), gh));
       VK_CHECK(coarse_check(ctx));
-      ++its;
-      jn = j + 1;
-      if (history) history[its] = hb[0];
-      if (!std::isfinite(hb[0]) || !std::isfinite(hb[1]))
-        return fail(ctx, VK_ERR_BREAKDOWN, "non-finite value in the Arnoldi process");
-      if (hb[0] <= tol || hb[1] == 0.0 || its >= max_iter) break;
+      for (int32_t t = 0; t < j - j0; ++t) {
+        const double est = gh[2 * t], hn = gh[2 * t + 1];
+        ++its;
+        jn = j0 + t + 1;
+        if (history) history[its] = est;
+        if (!std::isfinite(est) || !std::isfinite(hn))
+          return fail(ctx, VK_ERR_BREAKDOWN, "non-finite value in the Arnoldi process");
+        r_last = est;
+        if (est <= tol || hn == 0.0 || its >= max_iter) {
+          stop = true;
+          break;
+        }
+      }
     }
     VK_TRY(launch_trisolve(s, jn, ldh, ctx->H, ctx->g, ctx->y));
     VK_TRY(launch_maxpy(s, n, ctx->Z, ldv, jn, ctx->y, 1.0, x));
@@ -985,6 +1078,7 @@ vk_status gmres_solve_batched(vk_ctx* ctx, const double* b, double* x, int32_t r
   }
   VK_CHECK(to_dev(ctx, tol, tl.data(), sizeof(double) * ns));
   VK_TRY(launch_fill_i32(s, ns, 0, its));
+  int32_t done_steps = 0;  // Arnoldi steps over all cycles (every system starts at step 0)
   for (;;) {
     double* V0 = ctx->V;
     VK_TRY(launch_spmv(s, F.J, F.lpr_J, -1.0, x, 1.0, b, V0));
@@ -995,36 +1089,60 @@ vk_status gmres_solve_batched(vk_ctx* ctx, const double* b, double* x, int32_t r
     for (int i = 0; i < ns; ++i) n_active += hi[i];
     if (n_active == 0) break;
     VK_TRY(launch_seg_scale(s, ns, seg, max_len, V0, beta, active, V0));
-    int32_t j_end = 0;
-    for (int32_t j = 0; j < m; ++j) {
-      double* Vj = ctx->V + (int64_t)j * ldv;
-      double* Vn = ctx->V + (int64_t)(j + 1) * ldv;
-      double* Zj = ctx->Z + (int64_t)j * ldv;
-      // classical Gram-Schmidt twice, per segment; the first pass goes into column j of H
-      double* Hc = ctx->H + (int64_t)j * (m + 1);
-      auto step = [&]() -> vk_status {
-        hipStream_t q = ctx->stream;
-        VK_CHECK(vcycle_level(ctx, L, Vj, Zj, nu_pre, nu_post));
-        VK_TRY(launch_spmv(q, F.J, F.lpr_J, 1.0, Zj, 0.0, nullptr, Vn));
-        VK_TRY(launch_seg_mdot(q, ns, seg, max_len, ctx->V, ldv, j + 1, Vn, ctx->partial, ctx->n_partial, Hc,
-                               (int32_t)hs));
-        VK_TRY(launch_seg_maxpy(q, ns, seg, max_len, ctx->V, ldv, j + 1, Hc, (int32_t)hs, nullptr, -1.0, Vn));
-        VK_TRY(launch_seg_mdot(q, ns, seg, max_len, ctx->V, ldv, j + 1, Vn, ctx->partial, ctx->n_partial, ctx->h2,
-                               m + 1));
-        VK_TRY(launch_seg_maxpy(q, ns, seg, max_len, ctx->V, ldv, j + 1, ctx->h2, m + 1, nullptr, -1.0, Vn));
-        VK_TRY(launch_seg_dot(q, ns, seg, max_len, Vn, Vn, ctx->partial, ctx->n_partial, resid + ns, true));
-        VK_TRY(launch_seg_givens(q, ns, j, m, ctx->H, ctx->h2, ctx->cs, ctx->sn, ctx->g, tol, its, max_iter,
-                                 active, jn, resid));
-        VK_TRY(launch_seg_scale(q, ns, seg, max_len, Vn, resid + ns, active, Vn));
-        return VK_OK;
-      };
-      const int64_t key[6] = {j, m, nu_pre, nu_post, max_iter, 0};
-      VK_CHECK(replay(ctx, 1 + (size_t)ctx->restart + (size_t)j, key, step));
-      j_end = j + 1;
-      VK_CHECK(to_host(ctx, hi.data(), active, sizeof(int32_t) * ns));
+    // The stopping test runs on the device (seg_givens clears a system's active flag); the host
+    // enqueues several steps between looks at the flags.  Steps past the point where every system
+    // stopped change nothing (each kernel skips inactive systems, and their jn is frozen), so
+    // speculative steps only cost their V-cycle.  The look-ahead uses the slowest active system's
+    // mean reduction per step.
+    int32_t j_end = 0, j = 0;
+    std::vector<double> res_now(ns);
+    double worst_start = 0.0, worst_now = 0.0, worst_tol = 0.0;
+    while (j < m) {
+      const int32_t ahead = std::min(steps_ahead(worst_start, worst_now, done_steps, worst_tol), m - j);
+      for (int32_t q0 = 0; q0 < ahead; ++q0, ++j) {
+        double* Vj = ctx->V + (int64_t)j * ldv;
+        double* Vn = ctx->V + (int64_t)(j + 1) * ldv;
+        double* Zj = ctx->Z + (int64_t)j * ldv;
+        // classical Gram-Schmidt twice, per segment; the first pass goes into column j of H
+        double* Hc = ctx->H + (int64_t)j * (m + 1);
+        const int32_t jj = j;
+        auto step = [&]() -> vk_status {
+          hipStream_t q = ctx->stream;
+          VK_CHECK(vcycle_level(ctx, L, Vj, Zj, nu_pre, nu_post));
+          VK_TRY(launch_spmv(q, F.J, F.lpr_J, 1.0, Zj, 0.0, nullptr, Vn));
+          VK_TRY(launch_seg_mdot(q, ns, seg, max_len, ctx->V, ldv, jj + 1, Vn, ctx->partial, ctx->n_partial, Hc,
+                                 (int32_t)hs));
+          VK_TRY(launch_seg_maxpy(q, ns, seg, max_len, ctx->V, ldv, jj + 1, Hc, (int32_t)hs, nullptr, -1.0, Vn));
+          VK_TRY(launch_seg_mdot(q, ns, seg, max_len, ctx->V, ldv, jj + 1, Vn, ctx->partial, ctx->n_partial,
+                                 ctx->h2, m + 1));
+          VK_TRY(launch_seg_maxpy(q, ns, seg, max_len, ctx->V, ldv, jj + 1, ctx->h2, m + 1, nullptr, -1.0, Vn));
+          VK_TRY(launch_seg_dot(q, ns, seg, max_len, Vn, Vn, ctx->partial, ctx->n_partial, resid + ns, true));
+          VK_TRY(launch_seg_givens(q, ns, jj, m, ctx->H, ctx->h2, ctx->cs, ctx->sn, ctx->g, tol, its, max_iter,
+                                   active, jn, resid));
+          VK_TRY(launch_seg_scale(q, ns, seg, max_len, Vn, resid + ns, active, Vn));
+          return VK_OK;
+        };
+        const int64_t key[6] = {jj, m, nu_pre, nu_post, max_iter, 0};
+        VK_CHECK(replay(ctx, 1 + (size_t)ctx->restart + (size_t)jj, key, step));
+      }
+      j_end = j;
+      done_steps += ahead;
+      VK_CHECK(to_host2(ctx, hi.data(), active, sizeof(int32_t) * ns, res_now.data(), resid, sizeof(double) * ns));
       VK_CHECK(coarse_check(ctx));
       n_active = 0;
-      for (int i = 0; i < ns; ++i) n_active += hi[i];
+      // the active system furthest from its tolerance (in reduction factors) sets the look-ahead
+      double worst = -1.0;
+      for (int i = 0; i < ns; ++i) {
+        n_active += hi[i];
+        if (!hi[i]) continue;
+        const double need = std::log(res_now[i] / tl[i]);
+        if (need > worst) {
+          worst = need;
+          worst_start = bn[i];
+          worst_now = res_now[i];
+          worst_tol = tl[i];
+        }
+      }
       if (n_active == 0) break;
     }
     VK_TRY(launch_seg_trisolve(s, ns, m, ctx->H, ctx->g, jn, ctx->y));

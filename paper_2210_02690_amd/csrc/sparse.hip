@@ -78,6 +78,20 @@ __global__ void validate_cells_kernel(int32_t n_cells, int32_t n_K, const int32_
   }
 }
 
+// Colour c of a cell group: every cell of the colour sets bit c of its DoFs' masks; a bit that was
+// already set means two cells of the colour share that DoF.
+__global__ void colour_conflict_kernel(int32_t c, int32_t n0, int32_t cnt, int32_t n_K,
+                                       const int32_t* __restrict__ cell_dofs,
+                                       const int32_t* __restrict__ colour_cells, unsigned long long* mask,
+                                       int32_t* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)cnt * n_K) return;
+  const int32_t K = colour_cells[n0 + i / n_K];
+  const int32_t mu = cell_dofs[(int64_t)K * n_K + i % n_K];
+  const unsigned long long bit = 1ull << c;
+  if (atomicOr(mask + mu, bit) & bit) atomicOr(flag, 1);
+}
+
 __global__ void fill_kernel(int64_t n, double v, double* x) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     x[i] = v;
@@ -128,6 +142,18 @@ hipError_t launch_validate_cells(hipStream_t s, int32_t n_cells, int32_t n_K, co
                                  const int32_t* colour_cells, int32_t* flag) {
   validate_cells_kernel<<<grid_for((int64_t)n_cells * n_K, 256), 256, 0, s>>>(n_cells, n_K, cell_dofs, n,
                                                                               colour_cells, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_colour_check(hipStream_t s, int32_t n_K, const int32_t* cell_dofs, const int32_t* colour_cells,
+                               const int32_t* colour_ptr, int32_t n_colours, unsigned long long* mask,
+                               int32_t* flag) {
+  for (int32_t c = 0; c < n_colours && c < 64; ++c) {
+    const int32_t n0 = colour_ptr[c], cnt = colour_ptr[c + 1] - colour_ptr[c];
+    if (cnt <= 0) continue;
+    colour_conflict_kernel<<<grid_for((int64_t)cnt * n_K, 256), 256, 0, s>>>(c, n0, cnt, n_K, cell_dofs,
+                                                                             colour_cells, mask, flag);
+  }
   return hipGetLastError();
 }
 

@@ -207,6 +207,7 @@ struct vk_ctx {
   double* y = nullptr;
   double* partial = nullptr;  // block partial sums
   double* scal = nullptr;     // device scalars
+  double* ghist = nullptr;    // per Arnoldi step of a cycle: |g_{j+1}|, ||w|| (2 (restart + 1))
   int32_t n_partial = 0;
   // hipGraph replay: one graph per Arnoldi step index (single and batched GMRES) and one
   // for the stand-alone V-cycle, captured on first use and replayed while nothing baked
@@ -232,6 +233,10 @@ hipError_t launch_validate_csr(hipStream_t s, const vk_csr& A, int32_t* flag);
 hipError_t launch_validate_cells(hipStream_t s, int32_t n_cells, int32_t n_K, const int32_t* cell_dofs,
                                  int64_t n, const int32_t* colour_cells, int32_t* flag);
 hipError_t launch_fill(hipStream_t s, int64_t n, double v, double* x);
+// sets *flag if two cells of one colour share a DoF (mask: one zeroed 64-bit word per DoF)
+hipError_t launch_colour_check(hipStream_t s, int32_t n_K, const int32_t* cell_dofs, const int32_t* colour_cells,
+                               const int32_t* colour_ptr, int32_t n_colours, unsigned long long* mask,
+                               int32_t* flag);
 hipError_t launch_fill_i32(hipStream_t s, int64_t n, int32_t v, int32_t* x);
 // patches
 hipError_t launch_count_add(hipStream_t s, int32_t n_cells, int32_t n_K, const int32_t* cell_dofs, int32_t* count);

@@ -1,13 +1,20 @@
 """Parity at the workloads' full sizes, in the configuration bench.py times.
 
 * 176 x 32 dG(2) channel (188 358 unknowns, 5 levels): the whole oracle still runs in seconds, so the
-  V-cycle is compared element by element (1e-10) and GMRES counts within +-1.
+  V-cycle is compared element by element (1e-10); GMRES counts within +-1 of the oracle for FP64, FP32
+  and BF16 patch inverses and for the paper's four-plus-four smoothing iterations.
 * 100 x 16 x 16 dG(1) box (1 518 134 unknowns, n_K = 170): sampled outputs the oracle computes one by
   one (patch inverses of sampled cells; the sweep update of sampled DoFs from Eq. 3.5 with the inverses
-  of the cells that contain them), and GMRES's true residual (a property at any size).
-* The 64-system batch: every system's true residual, and the iteration counts of the two smallest
-  systems against their own oracle solves.
+  of the cells that contain them); the 4-level V-cycle at 2 000 sampled entries and its 2-norm; GMRES
+  counts within +-1 for FP64 and FP32 inverses with true residuals <= 1e-8.
+* The 64-system batch: every system's true residual and iteration count (+-1).
+
+The oracle's counts, V-cycle sample and norms at these sizes take minutes to hours on the host, so they
+come from tests/golden/oracle_counts.json, written by tests/golden/make_oracle_counts.py, which calls only
+the oracle and the seeded input generators.
 """
+import json
+import os
 import sys
 
 import numpy as np
@@ -21,6 +28,15 @@ import oracle  # noqa: E402
 from synth import build_problem  # noqa: E402
 
 DEV = "cuda:0"
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_counts.json")
+
+
+def golden(key):
+    with open(GOLDEN) as f:
+        ent = json.load(f)["entries"]
+    if key not in ent:
+        pytest.fail(f"{key} missing from {GOLDEN}: run tests/golden/make_oracle_counts.py")
+    return ent[key]
 
 
 def _say(msg):
@@ -55,13 +71,21 @@ def test_channel_176x32_k2_full(vk):
     ref = oracle.vcycle(H, P.b, 2, 2)
     assert np.abs(x.cpu().numpy() - ref).max() <= 1e-10 * np.abs(ref).max()
     _, its_o, *_ = oracle.gmres(P.finest.J, P.b, lambda v: oracle.vcycle(H, v, 2, 2))
-    for prec in ("f64", "f32"):
+    assert its_o == golden("channel2d_176x32_k2/f64/nu22")["iters"]
+    for prec in ("f64", "f32", "bf16"):
         S2 = S if prec == "f64" else solver(vk, P.levels, prec)
-        x = torch.zeros_like(b)
-        its, rel, _, ok = S2.gmres_solve(b, x, rtol=1e-8)
-        true_rel = np.linalg.norm(P.b - P.finest.J @ x.cpu().numpy()) / np.linalg.norm(P.b)
-        assert ok and true_rel <= 1e-8 and abs(its - its_o) <= 1, (prec, its, its_o, true_rel)
-        S2.close()
+        for nu in ((2, 2), (4, 4)):
+            key = f"channel2d_176x32_k2/{prec}/nu{nu[0]}{nu[1]}"
+            if nu == (4, 4) and prec == "bf16":
+                continue
+            its_g = golden(key)["iters"]
+            x = torch.zeros_like(b)
+            its, rel, _, ok = S2.gmres_solve(b, x, rtol=1e-8, nu_pre=nu[0], nu_post=nu[1])
+            true_rel = np.linalg.norm(P.b - P.finest.J @ x.cpu().numpy()) / np.linalg.norm(P.b)
+            _say(f"{key}: {its} its (oracle {its_g}), true rel {true_rel:.2e}")
+            assert ok and true_rel <= 1e-8 and abs(its - its_g) <= 1, (key, its, its_g, true_rel)
+        if S2 is not S:
+            S2.close()
 
 
 def test_box3d_full_sampled(vk):
@@ -100,13 +124,28 @@ def test_box3d_full_sampled(vk):
             z += (A @ r[cd[K]])[loc]
         ref = d0[mu] + 0.7 * z / p[mu]
         assert abs(got[mu] - ref) <= 1e-10 * max(1.0, abs(ref)), (mu, got[mu], ref)
-    # GMRES to 1e-8: the true residual on the host
-    x = torch.zeros_like(b)
-    its, rel, _, ok = S.gmres_solve(b, x, rtol=1e-8)
-    true_rel = np.linalg.norm(P.b - F.J @ x.cpu().numpy()) / np.linalg.norm(P.b)
-    _say(f"box3d gmres {its} its, true rel {true_rel:.2e}")
-    assert ok and true_rel <= 1e-8 and abs(true_rel - rel) <= 1e-12
-    S.close()
+    # the 4-level V-cycle from b at the oracle's sampled entries (relative to the oracle's max |V(b)|)
+    ref = golden("box3d_100x16x16_k1/f64/vcycle22_sample")
+    v = torch.empty_like(b)
+    S.vcycle(b, v, 2, 2)
+    vg = v.cpu().numpy()
+    idx = np.asarray(ref["indices"])
+    err = np.abs(vg[idx] - np.asarray(ref["values"])).max() / ref["max_abs"]
+    _say(f"box3d V-cycle sample: max rel err {err:.2e}")
+    assert err <= 1e-10
+    assert abs(np.linalg.norm(vg) - ref["norm2"]) <= 1e-10 * ref["norm2"]
+    assert abs(np.abs(vg).max() - ref["max_abs"]) <= 1e-10 * ref["max_abs"]
+    # GMRES to 1e-8 with FP64 and FP32 inverses: counts against the oracle's, true residual on the host
+    for prec in ("f64", "f32"):
+        S2 = S if prec == "f64" else solver(vk, P.levels, prec)
+        its_g = golden(f"box3d_100x16x16_k1/{prec}/nu22")["iters"]
+        x = torch.zeros_like(b)
+        its, rel, _, ok = S2.gmres_solve(b, x, rtol=1e-8)
+        true_rel = np.linalg.norm(P.b - F.J @ x.cpu().numpy()) / np.linalg.norm(P.b)
+        _say(f"box3d gmres {prec}: {its} its (oracle {its_g}), true rel {true_rel:.2e}")
+        assert ok and true_rel <= 1e-8 and abs(true_rel - rel) <= 1e-12
+        assert abs(its - its_g) <= 1, (prec, its, its_g)
+        S2.close()
 
 
 def test_batch64_full(vk):
@@ -128,10 +167,17 @@ def test_batch64_full(vk):
         J = B.hierarchies[si][-1].J
         true_rel = np.linalg.norm(B.rhs[si] - J @ xg[off:off + n]) / np.linalg.norm(B.rhs[si])
         assert true_rel <= 1e-8 and abs(true_rel - rel[seg]) <= 1e-12, (si, true_rel, rel[seg])
+    # every system's count against the oracle's solve of that system alone (FP32-rounded inverses)
+    ref = golden("batch64_seed0/f32/nu22")
+    bad = [(si, int(its[seg]), ref[str(si)]["iters"]) for seg, (si, _) in enumerate(order)
+           if abs(int(its[seg]) - ref[str(si)]["iters"]) > 1]
+    _say(f"batch64 counts {int(its.min())}..{int(its.max())}; outside +-1 of the oracle: {bad}")
+    assert not bad
+    # the smallest system once more against a fresh oracle solve (pins the golden file itself)
     sizes = [B.hierarchies[si][-1].n for si, _ in order]
-    for seg in np.argsort(sizes)[:2]:
-        si = order[seg][0]
-        Hs = oracle.OracleHierarchy(B.hierarchies[si])
-        _, its_o, *_ = oracle.gmres(B.hierarchies[si][-1].J, B.rhs[si], lambda v: oracle.vcycle(Hs, v, 2, 2))
-        assert abs(int(its[seg]) - its_o) <= 1, (si, its[seg], its_o)
+    seg = int(np.argmin(sizes))
+    si = order[seg][0]
+    Hs = oracle.OracleHierarchy(B.hierarchies[si], patch_store=oracle.round_f32)
+    _, its_o, *_ = oracle.gmres(B.hierarchies[si][-1].J, B.rhs[si], lambda v: oracle.vcycle(Hs, v, 2, 2))
+    assert its_o == ref[str(si)]["iters"]
     S.close()

@@ -53,6 +53,8 @@ CASES = {
     "r4_k2": ("channel2d_44x8_k1", dict(shape=(8, 4), levels=2, k=2, r=4)),
     # wider than any register-resident kernel: the blocked Gauss-Jordan path
     "r4_k3": ("channel2d_44x8_k1", dict(shape=(8, 4), levels=2, k=3, r=4)),
+    # the widest patch of the study: (Q4)^2 x P3disc dG(4), n_K = 300
+    "r4_k4": ("channel2d_44x8_k1", dict(shape=(8, 4), levels=2, k=4, r=4)),
 }
 
 _cache = {}
@@ -557,3 +559,47 @@ def test_singular_coarse_block_reported_by_the_solve(vk):
         with pytest.raises(vk.VkError, match="vanka_setup"):
             S.gmres_solve(b, x)
         S.close()
+
+
+def test_colouring_conflict_rejected(vk):
+    """Cells of one colour must share no DoF (the coloured scatter and the multiplicative sweep
+    update concurrently within a colour): a colouring that puts neighbours together is refused."""
+    P, _ = problem("cfg0")
+    ups = [vk.upload_level(L, DEV) for L in P.levels]
+    lv = ups[-1]
+    n = int(lv["n_cells"])
+    lv["colour_cells"] = torch.arange(n, dtype=torch.int32, device=DEV)
+    lv["colour_ptr"] = np.array([0, n], dtype=np.int32)
+    lv["n_colours"] = 1
+    S = vk.Solver(ups)
+    S.vk_set_workspace("f64", 30, device=DEV)
+    with pytest.raises(vk.VkError) as e:
+        S.vanka_setup(0.7, "additive")
+    assert e.value.status == vk.VK_ERR_ARG and "colour" in str(e.value)
+    S.close()
+
+
+@pytest.mark.parametrize("restart,max_iter", [(3, 200), (30, 5), (4, 6)])
+def test_gmres_lookahead_restarts_and_limits(vk, restart, max_iter):
+    """Several Arnoldi steps are enqueued between looks at the residual estimates; steps past the
+    stopping step must not change the iterate, across restarts and at the iteration limit."""
+    P, H = problem("cfg0")
+    S = make_solver(vk, P)
+    b = P.b
+    x = torch.zeros(P.finest.n, dtype=torch.float64, device=DEV)
+    its, relres, hist, ok = S.gmres_solve(t(b), x, restart=restart, max_iter=max_iter, rtol=1e-8,
+                                          raise_on_noconv=False)
+    xo, its_o, hist_o, ok_o, rel_o = oracle.gmres(P.finest.J, b, lambda v: oracle.vcycle(H, v, 2, 2),
+                                                  restart=restart, max_iter=max_iter)
+    xg = x.cpu().numpy()
+    true_rel = np.linalg.norm(b - P.finest.J @ xg) / np.linalg.norm(b)
+    _say(f"restart {restart} max_iter {max_iter}: {its} its (oracle {its_o}), ok {ok}")
+    assert ok == ok_o
+    assert abs(true_rel - relres) <= 1e-12
+    if ok:
+        assert abs(its - its_o) <= 1 and true_rel <= 1e-8
+    else:
+        assert its == max_iter == its_o
+        assert rel(xg, xo) <= 1e-6
+    k = min(len(hist), len(hist_o))
+    np.testing.assert_allclose(hist[:k], hist_o[:k], rtol=1e-6)
