@@ -179,6 +179,20 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
 vk_status vanka_smooth(vk_ctx* ctx, int32_t l, const double* b, double* d, int32_t sweeps,
                        int32_t d_is_zero);
 
+/* vanka_smooth for callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid allocation): the same sweeps with the same kernels and
+ * results, but the per-call scratch (the defect b - J d, the per-cell products y_K and, in the
+ * multiplicative mode, the per-cell local defects of one colour) lives in a fixed device array of
+ * the library (64 MiB, one per GPU, held until the process ends) instead of the context's
+ * workspace.  The call allocates nothing and makes no allocating library call.  Levels whose
+ * scratch exceeds 64 MiB (8 n_l + n_cells n_K (8 for FP64 inverses, else 4) + 8 n_K x the largest
+ * colour's cell count, each part rounded up to 256 bytes) are rejected with VK_ERR_ARG.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time on one GPU (from
+ * different contexts, streams or threads) race and must be serialised by the caller.  Nothing is
+ * assumed about the array's contents at entry.  Arguments, errors and stream as vanka_smooth. */
+vk_status vanka_smooth_noalloc(vk_ctx* ctx, int32_t l, const double* b, double* d, int32_t sweeps,
+                               int32_t d_is_zero);
+
 /* One V-cycle x = V(b) on the finest level from the zero initial guess
  * (Sec. 3): nu_pre sweeps from d = 0, defect restriction, recursion, direct
  * solve on T_0, prolongation of the correction, nu_post sweeps.  b, x: n_L FP64;

@@ -59,6 +59,7 @@ _SIGS = {
     "vk_set_workspace": (ctypes.c_int, [_P, _P, _SZ, ctypes.c_int, _I32]),
     "vanka_setup": (ctypes.c_int, [_P, _D, ctypes.c_int, _PI32, _PI32]),
     "vanka_smooth": (ctypes.c_int, [_P, _I32, _P, _P, _I32, _I32]),
+    "vanka_smooth_noalloc": (ctypes.c_int, [_P, _I32, _P, _P, _I32, _I32]),
     "vcycle": (ctypes.c_int, [_P, _P, _P, _I32, _I32]),
     "gmres_solve": (ctypes.c_int, [_P, _P, _P, _I32, _I32, _D, _D, _I32, _I32, _PI32, _PD, _PD]),
     "vk_spmv": (ctypes.c_int, [_P, _I32, _D, _P, _D, _P, _P]),
@@ -281,6 +282,9 @@ class Solver:
 
     def vanka_smooth(self, l, b, d, sweeps, d_is_zero=False):
         self._check(_lib.vanka_smooth(self.ctx, l, _ptr(b), _ptr(d), sweeps, 1 if d_is_zero else 0))
+
+    def vanka_smooth_noalloc(self, l, b, d, sweeps, d_is_zero=False):
+        self._check(_lib.vanka_smooth_noalloc(self.ctx, l, _ptr(b), _ptr(d), sweeps, 1 if d_is_zero else 0))
 
     def vcycle(self, b, x, nu_pre=2, nu_post=2):
         self._check(_lib.vcycle(self.ctx, _ptr(b), _ptr(x), nu_pre, nu_post))

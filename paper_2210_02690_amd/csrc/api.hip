@@ -11,7 +11,36 @@
 
 #include "vk_internal.h"
 
+#include <mutex>
+
+// Fixed device scratch of vanka_smooth_noalloc: one copy per GPU, held until the process ends.  Host
+// code never passes `scratch` itself to a kernel (on the host it names a stand-in, not device
+// memory): vk_create looks up each device's address once with hipGetSymbolAddress.
+#define VK_NOALLOC_SCRATCH_BYTES (64ull << 20)
+static __device__ __align__(256) char scratch[VK_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first call per device).
+hipError_t noalloc_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 vk_status fail(vk_ctx* ctx, vk_status st, const std::string& msg) {
   if (ctx) ctx->err = msg;
@@ -511,6 +540,7 @@ vk_status vk_create(vk_ctx** out, int32_t n_levels, void* hip_stream) {
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->setup_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = noalloc_scratch(&ctx->noalloc);
   if (e == hipSuccess) create_setup_stream(ctx);
   if (e != hipSuccess) {
     (void)hipGetLastError();  // do not leave the error for the caller's next check
@@ -912,6 +942,35 @@ vk_status vanka_smooth(vk_ctx* ctx, int32_t l, const double* b, double* d, int32
     return smooth(ctx, l, b, d, sweeps, true);
   }
   return smooth(ctx, l, b, d, sweeps, false);
+}
+
+vk_status vanka_smooth_noalloc(vk_ctx* ctx, int32_t l, const double* b, double* d, int32_t sweeps,
+                               int32_t d_is_zero) {
+  VK_CHECK(ready(ctx));
+  if (l < 1 || l >= ctx->n_levels) return fail(ctx, VK_ERR_ARG, "smoothing needs a level >= 1");
+  if (!b || !d || sweeps < 0) return fail(ctx, VK_ERR_ARG, "null vector or negative sweep count");
+  if (!ctx->noalloc) return fail(ctx, VK_ERR_STATE, "no fixed scratch on this device");
+  const vk_level& L = ctx->lv[l];
+  // the scratch: r, then y_K, then the multiplicative mode's local defects (256-byte aligned parts)
+  const int64_t sy = ctx->prec == VK_F64 ? 8 : 4;
+  int64_t rk = 0;
+  for (const vk_group& G : L.groups) rk = std::max(rk, (int64_t)G.max_colour_cells * G.n_K);
+  const int64_t off_y = round_up(8 * L.J.n_rows, 256);
+  const int64_t off_rk = off_y + round_up(sy * L.n_items, 256);
+  const int64_t need = off_rk + 8 * rk;
+  if (need > (int64_t)VK_NOALLOC_SCRATCH_BYTES) {
+    char buf[200];
+    snprintf(buf, sizeof(buf), "level %d needs %lld bytes of scratch; the fixed scratch holds %llu", l,
+             (long long)need, (unsigned long long)VK_NOALLOC_SCRATCH_BYTES);
+    return fail(ctx, VK_ERR_ARG, buf);
+  }
+  char* base = reinterpret_cast<char*>(ctx->noalloc);
+  const sweep_bufs bufs{reinterpret_cast<double*>(base), base + off_y, reinterpret_cast<double*>(base + off_rk)};
+  if (d_is_zero && sweeps == 0) {
+    VK_TRY(launch_fill(ctx->stream, L.J.n_rows, 0.0, d));
+    return VK_OK;
+  }
+  return smooth_with(ctx, l, b, d, sweeps, d_is_zero != 0, bufs);
 }
 
 vk_status vcycle(vk_ctx* ctx, const double* b, double* x, int32_t nu_pre, int32_t nu_post) {

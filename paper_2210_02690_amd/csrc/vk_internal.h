@@ -208,6 +208,7 @@ struct vk_ctx {
   double* partial = nullptr;  // block partial sums
   double* scal = nullptr;     // device scalars
   double* ghist = nullptr;    // per Arnoldi step of a cycle: |g_{j+1}|, ||w|| (2 (restart + 1))
+  void* noalloc = nullptr;    // device address of the fixed scratch on the context's device
   int32_t n_partial = 0;
   // hipGraph replay: one graph per Arnoldi step index (single and batched GMRES) and one
   // for the stand-alone V-cycle, captured on first use and replayed while nothing baked
