@@ -255,13 +255,16 @@ typedef enum {
 vk_status vk_set_sweep_variant(vk_ctx* ctx, int32_t variant);
 
 /* Patch inversion kernel used by vanka_setup: 0 (default) keeps the patch
- * matrix in registers where a kernel for the patch width is compiled (one row
- * per lane for n_K = 42, 63; spread over a 512-thread workgroup for
- * n_K = 84, 85, 105, 120, 170, 180), inverts other patches wider than 88 (up to
- * 512) with the blocked kernels of the directly solved blocks, one block per
- * cell, and the rest in LDS; 1 always uses the LDS / global-memory kernel.
- * All compute the Gauss-Jordan inverse with partial pivoting; setup must run
- * again after a change. */
+ * matrix in registers where a kernel for the patch width is compiled: blocked
+ * Gauss-Jordan on the FP64 matrix cores for n_K = 170 (16 x 16 tiles over a
+ * 512-thread workgroup, rank-8 panel updates), one row per lane for n_K = 42,
+ * 63, spread over a 512-thread workgroup with vector FP64 for n_K = 84, 85,
+ * 105, 120, 180; inverts other patches wider than 88 (up to 512) with the
+ * blocked kernels of the directly solved blocks, one block per cell, and the
+ * rest in LDS; 1 always uses the LDS / global-memory kernel; 2 is 0 without
+ * the matrix-core kernel (n_K = 170 on the vector unit).  All compute the
+ * Gauss-Jordan inverse with the same partial pivoting; setup must run again
+ * after a change. */
 vk_status vk_set_setup_variant(vk_ctx* ctx, int32_t variant);
 
 /* Autotuner: after vanka_setup, times each level's SpMV kernels (J, P, R)

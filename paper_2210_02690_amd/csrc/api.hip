@@ -540,11 +540,17 @@ vk_status vk_create(vk_ctx** out, int32_t n_levels, void* hip_stream) {
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->setup_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->la.aux, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->la.gathered, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->la.bulk_done, hipEventDisableTiming);
   if (e == hipSuccess) e = noalloc_scratch(&ctx->noalloc);
   if (e == hipSuccess) create_setup_stream(ctx);
   if (e != hipSuccess) {
     (void)hipGetLastError();  // do not leave the error for the caller's next check
     if (ctx->setup) (void)hipStreamDestroy(ctx->setup);
+    if (ctx->la.bulk_done) (void)hipEventDestroy(ctx->la.bulk_done);
+    if (ctx->la.gathered) (void)hipEventDestroy(ctx->la.gathered);
+    if (ctx->la.aux) (void)hipStreamDestroy(ctx->la.aux);
     if (ctx->setup_ev) (void)hipEventDestroy(ctx->setup_ev);
     if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
     if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
@@ -575,6 +581,12 @@ void vk_destroy(vk_ctx* ctx) {
   }
   if (ctx->setup_ev) (void)hipEventDestroy(ctx->setup_ev);
   if (ctx->side) (void)hipStreamSynchronize(ctx->side);
+  if (ctx->la.aux) {
+    (void)hipStreamSynchronize(ctx->la.aux);
+    (void)hipStreamDestroy(ctx->la.aux);
+  }
+  if (ctx->la.gathered) (void)hipEventDestroy(ctx->la.gathered);
+  if (ctx->la.bulk_done) (void)hipEventDestroy(ctx->la.bulk_done);
   for (size_t i = 0; i < ctx->xside.size(); ++i) {
     (void)hipStreamSynchronize(ctx->xside[i]);
     (void)hipStreamDestroy(ctx->xside[i]);
@@ -855,7 +867,8 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
     Timed t(ctx, VK_KERNEL_PATCH_SETUP, l, ps);
     for (const vk_group& G : L.groups) {
       bool handled = false;
-      if (ctx->fast_setup) VK_TRY(launch_patch_setup_fast(ps, L.J, G, ctx->prec, ctx->status + 64 + l, &handled));
+      if (ctx->fast_setup)
+        VK_TRY(launch_patch_setup_fast(ps, L.J, G, ctx->prec, ctx->status + 64 + l, &handled, ctx->mfma_setup));
       // wider than LDS and no register-resident kernel: the blocked kernels of the directly
       // solved blocks, one block per cell
       if (!handled && ctx->fast_setup && G.n_K > VK_LDS_SETUP_MAX_NK && G.n_K <= 512 && ctx->blocked.cap > 0) {
@@ -901,7 +914,8 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
     vk_level& L = ctx->lv[blevels[k]];
     {
       Timed t(ctx, VK_KERNEL_BLOCK_INVERT, blevels[k], st);
-      VK_TRY(launch_block_invert(st, L, ctx->status, &L.cb_W));
+      // the level with the largest blocks (the longest chain) gets the look-ahead stream
+      VK_TRY(launch_block_invert(st, L, ctx->status, &L.cb_W, k == 0 ? &ctx->la : nullptr));
     }
     if (k > 0) {
       VK_TRY(hipEventRecord(ctx->xjoin[k - 1], st));
@@ -1397,8 +1411,9 @@ vk_status vk_set_sweep_variant(vk_ctx* ctx, int32_t variant) {
 
 vk_status vk_set_setup_variant(vk_ctx* ctx, int32_t variant) {
   if (!ctx) return VK_ERR_ARG;
-  if (variant != 0 && variant != 1) return fail(ctx, VK_ERR_ARG, "unknown setup variant");
-  ctx->fast_setup = variant == 0;
+  if (variant < 0 || variant > 2) return fail(ctx, VK_ERR_ARG, "unknown setup variant");
+  ctx->fast_setup = variant != 1;
+  ctx->mfma_setup = variant == 0;
   ctx->setup_done = false;
   return VK_OK;
 }

@@ -441,12 +441,15 @@ __global__ void block_export_kernel(int64_t n, const double* __restrict__ W, con
 }
 
 template <int CTT, int R, int NB, int NBO>
-hipError_t run_blocked(hipStream_t s, const vk_level& L, int32_t* status, int32_t bad_base = -1) {
+hipError_t run_blocked(hipStream_t s, const vk_level& L, int32_t* status, int32_t bad_base = -1,
+                       const vk_lookahead* la = nullptr) {
   static_assert(NBO % NB == 0 && NB <= VK_GJ_NBI_MAX && NBO % 64 == 0 && NBO <= VK_GJ_NBO,
                 "inner panels must tile the outer block, whose columns come in whole 64-column tiles");
   const int nbk = (int)L.cb_rows.size() - 1;
   const int64_t n = L.cb_max;
   const unsigned row_tiles = (unsigned)((n + 63) / 64);
+  hipError_t e = hipSuccess;
+  bool bulk_pending = false;  // a rank-NBO update of the other columns is running on la->aux
   for (int64_t c0o = 0; c0o < n; c0o += NBO) {
     for (int64_t k0 = c0o; k0 < c0o + NBO && k0 < n; k0 += NB) {
       block_panel_kernel<CTT, R, NB><<<nbk, CTT, 0, s>>>(L.d_cb_rows, L.d_cb_woff, k0, c0o, L.cb_a, L.cb_q,
@@ -457,14 +460,35 @@ hipError_t run_blocked(hipStream_t s, const vk_level& L, int32_t* status, int32_
             L.d_cb_rows, L.d_cb_woff, L.cb_a, L.cb_used, k0, NB, L.cb_gi, (int64_t)NB * NBO, NBO, c0o, c0o,
             c0o + NBO, k0, k0 + NB, k0, k0 + NB, c0o);
     }
+    // the previous outer block's update of the other columns must be complete before its pivot
+    // rows' values are gathered here (and before the gather buffer is overwritten)
+    if (bulk_pending && (e = hipStreamWaitEvent(s, la->bulk_done, 0)) != hipSuccess) return e;
+    bulk_pending = false;
     gather_pivot_rows_kernel<<<dim3((unsigned)((n + 255) / 256 < 64 ? (n + 255) / 256 : 64), NBO, nbk), 256, 0, s>>>(
         L.d_cb_rows, L.d_cb_woff, c0o, NBO, L.cb_a, L.cb_q, L.cb_go);
-    gj_update_kernel<NBO><<<dim3(row_tiles, row_tiles, nbk), 256, 0, s>>>(L.d_cb_rows, L.d_cb_woff, L.cb_a, L.cb_used,
-                                                                     c0o, NBO, L.cb_go, 0, 0, 0, 0, n, c0o,
-                                                                     c0o + NBO, c0o, c0o + NBO, 0);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    const int64_t c1 = c0o + NBO, c2 = c1 + NBO < n ? c1 + NBO : n;
+    if (la && c1 < n) {
+      // Look-ahead: the next outer block's columns first, on the chain's stream (its panels need
+      // only them); the rest on the second stream, overlapping those panels.  The two column sets
+      // are disjoint from each other and from the next panels' columns.
+      gj_update_kernel<NBO><<<dim3(row_tiles, (unsigned)((c2 - c1 + 63) / 64), nbk), 256, 0, s>>>(
+          L.d_cb_rows, L.d_cb_woff, L.cb_a, L.cb_used, c0o, NBO, L.cb_go, 0, 0, 0, c1, c2, c0o, c0o + NBO, c0o,
+          c0o + NBO, c1);
+      if ((e = hipEventRecord(la->gathered, s)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(la->aux, la->gathered, 0)) != hipSuccess) return e;
+      gj_update_kernel<NBO><<<dim3(row_tiles, row_tiles, nbk), 256, 0, la->aux>>>(
+          L.d_cb_rows, L.d_cb_woff, L.cb_a, L.cb_used, c0o, NBO, L.cb_go, 0, 0, 0, 0, n, c0o, c2, c0o, c0o + NBO,
+          0);
+      if ((e = hipEventRecord(la->bulk_done, la->aux)) != hipSuccess) return e;
+      bulk_pending = true;
+    } else {
+      gj_update_kernel<NBO><<<dim3(row_tiles, row_tiles, nbk), 256, 0, s>>>(L.d_cb_rows, L.d_cb_woff, L.cb_a,
+                                                                       L.cb_used, c0o, NBO, L.cb_go, 0, 0, 0, 0, n,
+                                                                       c0o, c0o + NBO, c0o, c0o + NBO, 0);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
+  if (bulk_pending && (e = hipStreamWaitEvent(s, la->bulk_done, 0)) != hipSuccess) return e;
   const unsigned tiles = (unsigned)((n + 31) / 32);
   block_transpose_kernel<<<dim3(tiles, tiles, nbk), 256, 0, s>>>(L.d_cb_rows, L.d_cb_woff, L.cb_a);
   return hipGetLastError();
@@ -474,7 +498,8 @@ hipError_t run_blocked(hipStream_t s, const vk_level& L, int32_t* status, int32_
 
 int64_t vk_coarse_max_n() { return 9216; }
 
-hipError_t launch_block_invert(hipStream_t s, const vk_level& L, int32_t* status, double** result) {
+hipError_t launch_block_invert(hipStream_t s, const vk_level& L, int32_t* status, double** result,
+                               const vk_lookahead* la) {
   const int nbk = (int)L.cb_rows.size() - 1;
   *result = L.cb_a;
   if (nbk <= 0) return hipSuccess;
@@ -492,11 +517,16 @@ hipError_t launch_block_invert(hipStream_t s, const vk_level& L, int32_t* status
   // are few workgroups wide; many blocks per level keep 64
   const int64_t m = L.cb_max;
   const bool wide = nbk <= 8;
-  if (m <= 1024) e = wide ? run_blocked<512, 2, 16, 128>(s, L, status) : run_blocked<512, 2, 16, 64>(s, L, status);
-  else if (m <= 2048) e = wide ? run_blocked<256, 8, 8, 128>(s, L, status) : run_blocked<256, 8, 8, 64>(s, L, status);
-  else if (m <= 4096) e = wide ? run_blocked<512, 8, 8, 128>(s, L, status) : run_blocked<512, 8, 8, 64>(s, L, status);
-  else if (m <= 8192) e = wide ? run_blocked<1024, 8, 4, 128>(s, L, status) : run_blocked<1024, 8, 4, 64>(s, L, status);
-  else e = wide ? run_blocked<1024, 9, 4, 128>(s, L, status) : run_blocked<1024, 9, 4, 64>(s, L, status);
+  if (m <= 1024)
+    e = wide ? run_blocked<512, 2, 16, 128>(s, L, status, -1, la) : run_blocked<512, 2, 16, 64>(s, L, status, -1, la);
+  else if (m <= 2048)
+    e = wide ? run_blocked<256, 8, 8, 128>(s, L, status, -1, la) : run_blocked<256, 8, 8, 64>(s, L, status, -1, la);
+  else if (m <= 4096)
+    e = wide ? run_blocked<512, 8, 8, 128>(s, L, status, -1, la) : run_blocked<512, 8, 8, 64>(s, L, status, -1, la);
+  else if (m <= 8192)
+    e = wide ? run_blocked<1024, 8, 4, 128>(s, L, status, -1, la) : run_blocked<1024, 8, 4, 64>(s, L, status, -1, la);
+  else
+    e = wide ? run_blocked<1024, 9, 4, 128>(s, L, status, -1, la) : run_blocked<1024, 9, 4, 64>(s, L, status, -1, la);
   return e;
 }
 

@@ -923,8 +923,395 @@ __global__ __launch_bounds__(64 * WideCfg<N>::NW) void patch_setup_wide_kernel(
   }
 }
 
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
+// The cell's DoFs -> their local indices, an open-addressing hash table in LDS (linear probing,
+// slots hold (DoF, local index), DoF -1 = empty).  1024 slots for at most 256 DoFs.
+struct PatchHash {
+  static constexpr int SLOTS = 1024;
+  __device__ static int slot(int dof) { return (int)(((uint32_t)dof * 2654435761u) >> 22); }
+  __device__ __attribute__((always_inline)) static void insert(int2* tab, int dof, int loc) {
+    int h = slot(dof);
+    for (;;) {  // the DoFs of a cell are distinct and fewer than the slots: ends
+      if (atomicCAS(&tab[h].x, -1, dof) == -1) {
+        tab[h].y = loc;
+        return;
+      }
+      h = (h + 1) & (SLOTS - 1);
+    }
+  }
+};
+
+// Rows [row0, row0 + 16) of the patch into stage (row r - row0, local column).  pre[r] is the
+// offset of row row0 + r among the 16 rows' CSR entries (pre[16] their number) and rbeg[i] row i's
+// first CSR entry.  Each thread takes one contiguous range of the entries, issues every load of up
+// to Q entries before using any, and looks the columns up in the hash table with two rounds of
+// batched probes (a third, rare, probe sequence finishes the remaining lookups).
+template <int NT>
+__device__ __attribute__((always_inline)) inline void gather_rows(const int32_t* __restrict__ col, const double* __restrict__ val,
+                                   const int64_t* rbeg, const int* pre, int row0, const int2* htab,
+                                   double* stage, int ldst) {
+  constexpr int Q = 6;
+  int pr[17];
+#pragma unroll
+  for (int k = 0; k < 17; ++k) pr[k] = __builtin_amdgcn_readfirstlane(pre[k]);  // uniform: scalar registers
+  const int total = pr[16];
+  const int per = (total + NT - 1) / NT;
+  const int e0 = threadIdx.x * per;
+  const int e1 = min(e0 + per, total);
+  for (int eb = e0; eb < e1; eb += Q) {
+    int cq[Q], rq[Q], hq[Q], lq[Q];
+    double vq[Q];
+    int64_t gq[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = eb + q;
+      int r = 0;
+#pragma unroll
+      for (int k = 1; k < 16; ++k) r += (e >= pr[k]) ? 1 : 0;
+      rq[q] = r;
+      gq[q] = rbeg[row0 + (e < e1 ? r : 0)] + (e - pr[r]);
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const bool ok = eb + q < e1;
+      const int64_t g = ok ? gq[q] : 0;
+      cq[q] = col[g];
+      vq[q] = val[g];
+      if (!ok) cq[q] = -1;
+    }
+    // probe rounds: lq = local index (>= 0), -1 not in the patch, -2 unresolved
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      hq[q] = PatchHash::slot(cq[q]);
+      lq[q] = cq[q] < 0 ? -1 : -2;
+    }
+#pragma unroll
+    for (int round = 0; round < 2; ++round) {
+      int2 eq[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) eq[q] = htab[hq[q]];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        if (lq[q] == -2) {
+          if (eq[q].x == cq[q]) lq[q] = eq[q].y;
+          else if (eq[q].x == -1) lq[q] = -1;
+        }
+        hq[q] = (hq[q] + 1) & (PatchHash::SLOTS - 1);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      int h = hq[q];
+      for (int probe = 0; lq[q] == -2 && probe < PatchHash::SLOTS; ++probe) {
+        const int2 e = htab[h];
+        if (e.x == cq[q]) lq[q] = e.y;
+        else if (e.x == -1) lq[q] = -1;
+        h = (h + 1) & (PatchHash::SLOTS - 1);
+      }
+      if (lq[q] >= 0) stage[rq[q] * ldst + lq[q]] = vq[q];
+    }
+  }
+}
+
+// 1 / a for the Gauss-Jordan pivots: the hardware reciprocal refined by two Newton steps
+// (each doubles the correct bits), in place of the IEEE division sequence.
+__device__ inline double recip_f64(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+  r = fma(r, fma(-a, r, 1.0), r);
+  r = fma(r, fma(-a, r, 1.0), r);
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Wide patches on the FP64 matrix cores (compiled for n_K = 170, the 3D Q2/P1disc dG(1) patch):
+// blocked Gauss-Jordan with implicit partial pivoting.  The patch, padded to NP = 16 T, lives in
+// registers as T x T tiles of 16 x 16: wavefront w holds tile row w (T wavefronts).  Columns are
+// eliminated in panels of NB = 4:
+//   1. the tiles of the panel's column block copy the panel's columns to LDS;
+//   2. one wavefront runs the panel's NB elimination steps on it (rows in registers) and writes the
+//      eliminated panel M back, with the pivot rows q_t;
+//   3. the owners of the pivot rows copy their old values, B[t][c] = W[q_t][c], to LDS and clear
+//      those rows;
+//   4. every tile applies the panel as one rank-NB update on the matrix cores,
+//        W'[i][c] = (i pivotal in this panel ? 0 : W[i][c]) + sum_t M[i][t] B[t][c],
+//      and the panel's own columns become M.
+// This composes the NB single-column Gauss-Jordan steps exactly (for one step it reads
+// W'[i][c] = W[i][c] - W[i][k] W[p][c] / W[p][k], W'[p][c] = W[p][c] / W[p][k]).  After all steps
+// J_K^{-1}[k][q_j] = W[q_k][j], written out through LDS one 16-column block at a time so the
+// stores of a column are contiguous.
+// Pivot choice: the largest |a| among the rows not yet pivotal, compared on its bit pattern with
+// the lowest 8 mantissa bits replaced by 255 - row, so one wavefront maximum gives the row as
+// well: candidates within 2^-44 of each other count as ties and the lowest row wins (the first
+// maximal row of the LU pivot sequence whenever the maximum is unique to that precision).
+// The FP64 MFMA (16 x 16 x 4) computes D(m, n) = sum_k A(m, k) B(k, n) + C: lane l supplies
+// A(l % 16, l / 16) and B(l / 16, l % 16), and accumulator element v holds D(4 v + l / 16, l % 16),
+// so a tile's lane l owns rows 4 v + l / 16 of column l % 16.  Tile indices are compile-time
+// (the register arrays are never indexed at run time) and the branches depend on wave-uniform
+// values only.
+// ---------------------------------------------------------------------------
+template <int N> struct MfCfg {
+  static constexpr int NP = (N + 15) / 16 * 16;  // padded width
+  static constexpr int T = NP / 16;              // tiles per dimension = wavefronts
+  static constexpr int NT = 64 * T;
+  static constexpr int NB = 4;                   // panel width (one MFMA depth)
+  static constexpr int R = (NP + 63) / 64;       // panel rows per lane
+  static constexpr int PW = T - 1;               // the wavefront that eliminates the panels
+  static constexpr int PLD = NB + 1;             // LDS row length of a panel (doubles)
+};
+
+template <int P, int N>
+__global__ __launch_bounds__(MfCfg<N>::NT) void patch_setup_mfma_kernel(
+    const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const double* __restrict__ val,
+    const int32_t* __restrict__ cell_dofs, void* inv_out, int32_t ld, int64_t cell_stride, int32_t* status) {
+  using C = MfCfg<N>;
+  constexpr int NP = C::NP, T = C::T, NT = C::NT, NB = C::NB, R = C::R, PW = C::PW, PLD = C::PLD;
+  static_assert(R <= 4 && NP <= 256, "patch width");
+  __shared__ int qs[NP], kinv[NP];
+  __shared__ int pq[2][NB];               // the panel's pivot rows (-1: none), double-buffered
+  __shared__ double stage[16 * NP];       // gather rows / output columns
+  __shared__ double pan[2][NP * PLD];     // panel columns (double-buffered)
+  __shared__ double bs[2][NB * NP];       // old pivot rows (double-buffered)
+  __shared__ int2 htab[PatchHash::SLOTS]; // DoF -> local index
+  __shared__ int64_t rbeg[N];             // first CSR entry of each patch row
+  __shared__ int rlen[NP];                // CSR entries per patch row (0 beyond N)
+  __shared__ int pre[17];
+  __shared__ int bad_s;
+  const int K = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // this wavefront's tile row
+  const int l16 = lane & 15, l4 = lane >> 4;
+  for (int h = tid; h < PatchHash::SLOTS; h += NT) htab[h] = make_int2(-1, 0);
+  for (int i = tid; i < NP; i += NT) {
+    qs[i] = i < N ? i : 0;  // overwritten by every pivot; keeps the output in range otherwise
+    kinv[i] = -1;
+    rlen[i] = 0;
+  }
+  for (int e = tid; e < 2 * NB * NP; e += NT) (&bs[0][0])[e] = 0.0;
+  if (tid == 0) bad_s = 0;
+  __syncthreads();
+  if (tid < N) {
+    const int dof = cell_dofs[(int64_t)K * N + tid];
+    const int64_t b0 = row_ptr[dof];
+    rbeg[tid] = b0;
+    rlen[tid] = (int)(row_ptr[dof + 1] - b0);
+    PatchHash::insert(htab, dof, tid);
+  }
+  // ---- gather: 16 patch rows at a time through LDS, then into the tiles of that row block ----
+  f64x4_t acc[T];
+#pragma unroll
+  for (int J = 0; J < T; ++J) acc[J] = (f64x4_t){0.0, 0.0, 0.0, 0.0};
+  for (int I = 0; I < T; ++I) {
+    __syncthreads();
+    for (int e = tid; e < 16 * NP; e += NT) stage[e] = 0.0;
+    if (tid < 64) {  // prefix offsets of the block's rows: one wavefront scan
+      int v = lane < 16 ? rlen[16 * I + lane] : 0;
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        const int u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+      }
+      if (lane < 16) pre[lane + 1] = v;
+      if (lane == 0) pre[0] = 0;
+    }
+    __syncthreads();
+    gather_rows<NT>(col, val, rbeg, pre, 16 * I, htab, stage, NP);
+    __syncthreads();
+    if (w == I) {
+#pragma unroll
+      for (int J = 0; J < T; ++J)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[J][v] = stage[(4 * v + l4) * NP + 16 * J + l16];
+    }
+  }
+  // ---- elimination, panel by panel ----
+  uint32_t used = 0;  // the panel wavefront's record of pivotal rows (bit r: row r * 64 + lane)
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (r * 64 + lane >= N) used |= 1u << r;
+  bool singular = false;
+  constexpr int NPAN = (N + NB - 1) / NB;
+  for (int j = 0; j < NPAN; ++j) {
+    const int k0 = NB * j, Jp = k0 / 16, h0 = k0 % 16;  // panel columns [k0, k0 + NB) in tile column Jp
+    double* pn = pan[j & 1];
+    double* bb = bs[j & 1];
+    int* pqj = pq[j & 1];
+    const bool in_pan = l16 >= h0 && l16 < h0 + NB;
+    // 1. the panel's columns to LDS
+#pragma unroll
+    for (int J = 0; J < T; ++J)
+      if (J == Jp && in_pan) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pn[(16 * w + 4 * v + l4) * PLD + (l16 - h0)] = acc[J][v];
+      }
+    __syncthreads();
+    // 2. the panel's elimination steps on one wavefront
+    if (w == PW) {
+      double pr[R][NB];
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) pr[r][c] = (r * 64 + lane < NP) ? pn[(r * 64 + lane) * PLD + c] : 0.0;
+#pragma unroll
+      for (int t = 0; t < NB; ++t) {
+        const int k = k0 + t;
+        if (k >= N) {  // uniform: a padding column of the last panel
+          if (lane == 0) pqj[t] = -1;
+          continue;
+        }
+        double key = -1.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          int2 kb = __builtin_bit_cast(int2, fabs(pr[r][t]));
+          kb.x = (kb.x & ~0xFF) | (255 - 64 * r - lane);  // the low mantissa byte: 255 - row
+          if (!((used >> r) & 1u)) key = fmax(key, __builtin_bit_cast(double, kb));
+        }
+        const double m = wave_max(key);
+        const uint64_t mb = __builtin_bit_cast(uint64_t, m);
+        const int p = 255 - (int)(mb & 0xFFull);
+        if (!(m > 0.0) || (mb >> 8) == 0 || p >= N) {  // uniform: no nonzero finite candidate
+          singular = true;
+          if (lane == 0) pqj[t] = -1;
+          continue;
+        }
+        const int pl = p & 63, ps = p >> 6;
+        double prow[NB];
+        if (ps == 0) {
+#pragma unroll
+          for (int c = 0; c < NB; ++c) prow[c] = readlane_f64(pr[0][c], pl);
+        } else if (ps == 1 || R < 3) {
+#pragma unroll
+          for (int c = 0; c < NB; ++c) prow[c] = readlane_f64(pr[R > 1 ? 1 : 0][c], pl);
+        } else {
+#pragma unroll
+          for (int c = 0; c < NB; ++c) prow[c] = readlane_f64(pr[R > 2 ? 2 : 0][c], pl);
+        }
+        const double inv = recip_f64(prow[t]);
+#pragma unroll
+        for (int c = 0; c < NB; ++c) prow[c] = (c == t) ? inv : prow[c] * inv;
+        // the next panel column first: the next step's pivot search needs only it
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) {
+          const int c = (t + 1 + cc) % NB;
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            pr[r][c] = (c == t) ? -pr[r][t] * inv : fma(-pr[r][t], prow[c], pr[r][c]);
+        }
+        if (lane == pl) {  // the pivot row becomes the scaled pivot row
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            if (r == ps) {
+#pragma unroll
+              for (int c = 0; c < NB; ++c) pr[r][c] = prow[c];
+            }
+          used |= 1u << ps;
+        }
+        if (lane == 0) {
+          qs[k] = p;
+          kinv[p] = k;
+          pqj[t] = p;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+          if (r * 64 + lane < NP) pn[(r * 64 + lane) * PLD + c] = pr[r][c];
+    }
+    __syncthreads();
+    // 3. the owners of the panel's pivot rows copy their old values to LDS and clear the rows (rows
+    //    of steps without a pivot stay zero in B); the pivot rows are wave-uniform
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+      const int q = __builtin_amdgcn_readfirstlane(pqj[t]);
+      if (q >= 0 && (q >> 4) == w) {
+        const int m = q & 15;
+        if (l4 == (m & 3)) {
+          double* dst = &bb[t * NP + l16];
+          switch (m >> 2) {
+#define VK_B_ROW(V)                                  \
+  case V:                                            \
+    _Pragma("unroll") for (int J = 0; J < T; ++J) {  \
+      dst[16 * J] = acc[J][V];                       \
+      acc[J][V] = 0.0;                               \
+    }                                                \
+    break;
+            VK_B_ROW(0)
+            VK_B_ROW(1)
+            VK_B_ROW(2)
+            VK_B_ROW(3)
+#undef VK_B_ROW
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // 4. rank-NB update of every tile; the panel's own columns become M
+    double* bo = bs[(j + 1) & 1];  // the next panel's buffer: cleared while nobody reads it
+    for (int e = tid; e < NB * NP; e += NT) bo[e] = 0.0;
+    const double a = pn[(16 * w + l16) * PLD + l4];
+    double bv[T];
+#pragma unroll
+    for (int J = 0; J < T; ++J) bv[J] = bb[l4 * NP + 16 * J + l16];
+#pragma unroll
+    for (int J = 0; J < T; ++J) acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[J], acc[J], 0, 0, 0);
+    if (in_pan) {
+      double mv[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) mv[v] = pn[(16 * w + 4 * v + l4) * PLD + (l16 - h0)];
+#pragma unroll
+      for (int J = 0; J < T; ++J)
+        if (J == Jp) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[J][v] = mv[v];
+        }
+    }
+  }
+  if (singular && lane == 0) bad_s = 1;
+  __syncthreads();
+  if (tid == 0 && bad_s) atomicMin(status, K);
+  // ---- output: J_K^{-1}[kinv[i]][q_j] = W[i][j], one 16-column block at a time through LDS ----
+  using S = typename PT<P>::S;
+  S* out = reinterpret_cast<S*>(inv_out) + (int64_t)K * cell_stride;
+  // each of this lane's rows goes to stage row kinv[i] (i itself only after a failed pivot)
+  int dr[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = 16 * w + 4 * v + l4;
+    const int ki = kinv[i];
+    dr[v] = i < N ? (ki >= 0 ? ki : i) : -1;
+  }
+  constexpr int OW = (16 * NP + NT - 1) / NT;  // output elements per thread and block
+#pragma unroll
+  for (int J = 0; J < T; ++J) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (dr[v] >= 0) stage[l16 * NP + dr[v]] = acc[J][v];
+    __syncthreads();
+    int cq[OW];
+    double xv[OW];
+#pragma unroll
+    for (int o = 0; o < OW; ++o) {
+      const int e = tid + NT * o;
+      const int jj = e / ld, r = e - jj * ld;
+      const int c = 16 * J + jj;
+      const bool ok = e < 16 * ld && c < N;
+      cq[o] = ok ? qs[c] : -1;
+      xv[o] = (ok && r < N) ? stage[jj * NP + r] : 0.0;
+    }
+#pragma unroll
+    for (int o = 0; o < OW; ++o) {
+      const int e = tid + NT * o;
+      const int jj = e / ld, r = e - jj * ld;
+      if (cq[o] >= 0) out[(int64_t)cq[o] * ld + r] = store_cvt<P>(xv[o]);
+    }
+    __syncthreads();
+  }
+}
+
 template <int P>
-hipError_t setup_rows(hipStream_t s, const vk_csr& J, const vk_group& L, int32_t* status, bool* handled) {
+hipError_t setup_rows(hipStream_t s, const vk_csr& J, const vk_group& L, int32_t* status, bool* handled,
+                      bool mfma) {
   *handled = true;
   switch (L.n_K) {
 #define VK_ROWS_CASE(NN)                                                                                \
@@ -944,9 +1331,17 @@ hipError_t setup_rows(hipStream_t s, const vk_csr& J, const vk_group& L, int32_t
     VK_WIDE_CASE(85)
     VK_WIDE_CASE(105)
     VK_WIDE_CASE(120)
-    VK_WIDE_CASE(170)
     VK_WIDE_CASE(180)
 #undef VK_WIDE_CASE
+    case 170:
+      if (mfma) {
+        patch_setup_mfma_kernel<P, 170><<<L.n_cells, MfCfg<170>::NT, 0, s>>>(
+            J.row_ptr, J.col, J.val, L.cell_dofs, L.inv, L.ld, L.cell_stride, status);
+      } else {
+        patch_setup_wide_kernel<P, 170><<<L.n_cells, 64 * WideCfg<170>::NW, 0, s>>>(
+            J.row_ptr, J.col, J.val, L.cell_dofs, L.inv, L.ld, L.cell_stride, status);
+      }
+      return hipGetLastError();
     default:
       *handled = false;
       return hipSuccess;
@@ -1173,15 +1568,15 @@ hipError_t gemv_prec(hipStream_t s, const vk_group& L, int cpb, const double* r,
 }  // namespace
 
 hipError_t launch_patch_setup_fast(hipStream_t s, const vk_csr& J, const vk_group& G, vk_prec prec, int32_t* status,
-                                   bool* handled) {
+                                   bool* handled, bool mfma) {
   if (G.n_cells == 0) {
     *handled = true;
     return hipSuccess;
   }
   switch (prec) {
-    case VK_F64: return setup_rows<VK_F64>(s, J, G, status, handled);
-    case VK_F32: return setup_rows<VK_F32>(s, J, G, status, handled);
-    default: return setup_rows<VK_BF16>(s, J, G, status, handled);
+    case VK_F64: return setup_rows<VK_F64>(s, J, G, status, handled, mfma);
+    case VK_F32: return setup_rows<VK_F32>(s, J, G, status, handled, mfma);
+    default: return setup_rows<VK_BF16>(s, J, G, status, handled, mfma);
   }
 }
 

@@ -147,6 +147,7 @@ struct vk_ctx {
   int32_t n_levels = 0;
   hipStream_t stream = nullptr;
   hipStream_t side = nullptr;       // internal stream: coarse inversion during patch setup
+  vk_lookahead la{};                // second stream and events of the first block level's inversion
   // internal stream for the patch inversions, masked to 3/4 of the CUs (when the runtime allows
   // it), so they do not hold back the side stream's short block-inversion launches
   hipStream_t setup = nullptr;
@@ -175,6 +176,7 @@ struct vk_ctx {
   vk_mode mode = VK_ADDITIVE;
   int32_t sweep_variant = 0;  // additive sweep: 0 DoF gather, 1 coloured scatter
   bool fast_setup = true;     // register-resident patch inversion where compiled
+  bool mfma_setup = true;     // the matrix-core kernel where one is compiled for the patch width
   bool maps_ready = false;    // multiplicities and DoF lists (depend on the mesh only)
   // the block inversions of the last setup run on `side`; the first call that applies a
   // block makes `stream` wait for them, and the first synchronisation after that checks
@@ -249,8 +251,9 @@ hipError_t launch_dof_max_count(hipStream_t s, const vk_level& L, int32_t* max_c
 hipError_t launch_dof_ell(hipStream_t s, const vk_level& L);
 hipError_t launch_patch_setup(hipStream_t s, const vk_csr& J, const vk_group& G, vk_prec prec, double* big_scratch,
                               int32_t big_chunk, int32_t* status);
+// mfma: the matrix-core kernel where one is compiled for the patch width (else the VALU kernel)
 hipError_t launch_patch_setup_fast(hipStream_t s, const vk_csr& J, const vk_group& G, vk_prec prec, int32_t* status,
-                                   bool* handled);
+                                   bool* handled, bool mfma = true);
 // Patches of more than VK_LDS_SETUP_MAX_NK (at most 512) rows through the blocked Gauss-Jordan
 // kernels of the directly solved blocks, in chunks of the workspace's blocked-setup buffers.
 hipError_t launch_patch_setup_blocked(hipStream_t s, const vk_csr& J, const vk_group& G, vk_prec prec,
@@ -271,7 +274,16 @@ int vk_prec_vw(vk_prec prec);
 int vk_prec_bytes(vk_prec prec);
 // directly solved blocks (the coarsest level, and in batches every system's coarsest level)
 int64_t vk_coarse_max_n();
-hipError_t launch_block_invert(hipStream_t s, const vk_level& L, int32_t* status, double** result);
+// A second stream for the look-ahead of the blocked inversion: after each outer block of columns
+// the next block's columns are updated on the inversion's stream and all other columns on `aux`,
+// overlapping the next block's panels (events: `gathered` orders aux after the pivot rows'
+// gather, `bulk_done` the next gather after aux).
+struct vk_lookahead {
+  hipStream_t aux;
+  hipEvent_t gathered, bulk_done;
+};
+hipError_t launch_block_invert(hipStream_t s, const vk_level& L, int32_t* status, double** result,
+                               const vk_lookahead* la = nullptr);
 // Blocked Gauss-Jordan inversion of L's blocks (cb_rows, cb_max <= 512), whose dense column-major
 // matrices are already in L.cb_a; a failing pivot sets status[0] to min(bad_base + block).
 hipError_t launch_blocks_invert_dense(hipStream_t s, const vk_level& L, int32_t* status, int32_t bad_base);

@@ -37,8 +37,11 @@ class MarchLevelData:
 class ChannelMarch:
     """Meshes, slab operators and transfers of the marching channel."""
 
-    def __init__(self, shape=(88, 16), levels=4, k=1, nu=1e-3, tau=0.01, lengths=(2.2, H_CHANNEL)):
+    def __init__(self, shape=(88, 16), levels=4, k=1, nu=1e-3, tau=0.01, lengths=(2.2, H_CHANNEL),
+                 inflow=(0.3, 0.5, 0.5)):
+        """inflow = (U0, rel, period): peak U(t) = U0 (1 + rel sin(2 pi t / period))."""
         self.k, self.nu, self.tau = k, nu, tau
+        self.inflow = tuple(inflow)
         shapes = hierarchy_shapes(shape, levels)
         meshes = [StructuredMesh(s, lengths, k) for s in shapes]
         self.levels = []
@@ -67,7 +70,11 @@ class ChannelMarch:
 
     def initial_slab(self):
         """Slab vector of the initial state on every time node (Poiseuille flow of U(0))."""
-        return poiseuille_slab(self.fine.mesh, inflow_amplitude(0.0), self.nu)
+        return poiseuille_slab(self.fine.mesh, self.amplitude(0.0), self.nu)
+
+    def amplitude(self, t):
+        U0, rel, period = self.inflow
+        return inflow_amplitude(t, U0, rel, period)
 
     def end_velocity(self, X):
         """Velocity at the slab's end point (its last Radau node, s = 1)."""
@@ -81,7 +88,7 @@ class ChannelMarch:
 
     def residual(self, X, X_prev, n):
         """F(X) of slab n given the previous slab's solution."""
-        return self.fine.op.residual(X, self.end_velocity(X_prev), self.slab_start(n))
+        return self.fine.op.residual(X, self.end_velocity(X_prev), self.slab_start(n), amplitude=self.amplitude)
 
     def hierarchy(self, X):
         """Newton Jacobians of the state X on every level, as `problems.Level` objects."""

@@ -314,6 +314,31 @@ def test_singular_wide_patch_reported(vk):
     S.close()
 
 
+@pytest.mark.parametrize("variant", [0, 2])
+def test_singular_170_patch_reported(vk, variant):
+    """A singular 170-wide patch (3D dG(1)) names its cell, on the matrix cores (variant 0) and on
+    the vector unit (variant 2)."""
+    P = build_problem("box3d_100x16x16_k1", shape=(4, 2, 2), levels=2, k=1)
+    L = P.finest
+    assert L.mesh.n_K == 170
+    J = L.J.tolil()
+    cell = 5
+    pdof = int(L.cell_dofs[cell][81])   # the first pressure DoF of time node 0: this cell's only
+    J[pdof, :] = 0.0
+    J = J.tocsr()
+    J.eliminate_zeros()
+    J.sort_indices()
+    L.J = J
+    S = vk.Solver([vk.upload_level(Lv, DEV) for Lv in P.levels])
+    S.vk_set_workspace("f64", 30, device=DEV)
+    S.vk_set_setup_variant(variant)
+    with pytest.raises(vk.VkError) as e:
+        S.vanka_setup(0.7)
+    assert e.value.status == vk.VK_ERR_SINGULAR
+    assert e.value.bad_level == 1 and e.value.bad_cell == cell
+    S.close()
+
+
 def test_malformed_csr_rejected(vk):
     P = build_problem("channel2d_44x8_k1", shape=(8, 4), levels=2)
     lv = [vk.upload_level(L, DEV) for L in P.levels]
@@ -443,7 +468,7 @@ def test_setup_variants_agree(vk, case):
     Gauss-Jordan kernels give the same inverses."""
     P, H = problem(case)
     outs = []
-    for variant in (0, 1):
+    for variant in (0, 1, 2):
         S = vk.Solver([vk.upload_level(L, DEV) for L in P.levels])
         S.vk_set_workspace("f64", 30, device=DEV)
         S.vk_set_setup_variant(variant)
