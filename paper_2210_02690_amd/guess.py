@@ -15,7 +15,11 @@ Guesses for slab n from the two previous solutions:
     Radau nodes (HIP kernel);
   * LearnedGuess: that extrapolation plus the averaged patch corrections of the
     BF16 network (feature gather, forward pass and DoF averaging are HIP
-    kernels; training runs the library's gradient and Adam kernels).
+    kernels; training runs the library's gradient and Adam kernels);
+  * JudgedGuess: the learned guess with the extrapolation as fallback, judged by
+    the slab residual: both candidates are evaluated with F of Eq. 2.2 (the same
+    residual Newton stops on) and Newton starts from the one with the smaller
+    ||F||, whose residual it reuses.
 
 The problem object provides initial_slab(), hierarchy(X) (levels with J, P, R,
 cell_dofs, colours), residual(X, X_prev, n), E (the extrapolation matrix) and
@@ -52,12 +56,13 @@ class NewtonMarch:
         for lv, L in zip(self.levels, self.pr.hierarchy(X)):
             lv["J"]["val"].copy_(torch.from_numpy(L.J.data))
 
-    def solve_slab(self, X0, X_prev, n):
-        """Newton iteration of slab n from X0; returns (X, stats)."""
+    def solve_slab(self, X0, X_prev, n, F0=None):
+        """Newton iteration of slab n from X0 (F0: its residual, if already evaluated); returns
+        (X, stats)."""
         t_asm = t_gpu = t_res = 0.0
         X = np.array(X0, dtype=np.float64, copy=True)
         t0 = time.perf_counter()
-        F = self.pr.residual(X, X_prev, n)
+        F = self.pr.residual(X, X_prev, n) if F0 is None else F0
         t_res += time.perf_counter() - t0
         nrm = float(np.linalg.norm(F))
         st = {"F0": nrm, "newton": 0, "gmres": 0, "hist": [nrm]}
@@ -205,6 +210,32 @@ class LearnedGuess:
         return self.out.cpu().numpy()
 
 
+class JudgedGuess:
+    """The learned guess with the plain extrapolation as fallback, the slab residual as judge: both
+    candidates are evaluated with the problem's F (Eq. 2.2, the residual Newton iterates on; it is
+    assembled by the caller's problem object on the host, as in every Newton step), and the one with
+    the smaller ||F|| is returned.  `last_F` keeps its residual for the first Newton step and
+    `choices` counts the picks."""
+
+    def __init__(self, learned, fallback, problem):
+        self.learned, self.fallback, self.pr = learned, fallback, problem
+        self.last_F = None
+        self.choices = {"learned": 0, "extrapolation": 0}
+
+    def __call__(self, n, X_prev2, X_prev):
+        Xl = self.learned(n, X_prev2, X_prev)
+        Xe = self.fallback(n, X_prev2, X_prev)
+        Fl = self.pr.residual(Xl, X_prev, n)
+        Fe = self.pr.residual(Xe, X_prev, n)
+        if np.linalg.norm(Fl) <= np.linalg.norm(Fe):
+            self.choices["learned"] += 1
+            self.last_F = Fl
+            return Xl
+        self.choices["extrapolation"] += 1
+        self.last_F = Fe
+        return Xe
+
+
 def march(nm, first, last, slabs, guess):
     """Slabs first..last with NewtonMarch nm; slabs holds X_0..X_{first-1} and is extended.
     Returns the per-slab statistics."""
@@ -214,8 +245,9 @@ def march(nm, first, last, slabs, guess):
         prev2 = slabs[n - 2] if n >= 2 else slabs[n - 1]
         t0 = time.perf_counter()
         X0 = guess(n, prev2, prev)
+        F0 = getattr(guess, "last_F", None)
         t1 = time.perf_counter()
-        X, st = nm.solve_slab(X0, prev, n)
+        X, st = nm.solve_slab(X0, prev, n, F0=F0)
         st["t_guess"] = t1 - t0
         st["t_total"] = time.perf_counter() - t0
         slabs.append(X)
