@@ -334,8 +334,8 @@ def run_learned(args, torch, vk, dev):
 def run_pmc_probe(args, torch, vk, dev):
     """Short fixed workload for hardware-counter runs (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE):
     three copies of a 512 MiB FP64 buffer (the calibration kernel: 512 MiB read and written per
-    launch), then 20 finest-level additive sweeps of the default workload with the same setup as
-    the timed benchmark (the dominant kernel: patch_gemv over all finest cells)."""
+    launch), then 20 finest-level additive sweeps of the workload with the same setup as the timed
+    benchmark (each: SpMV, patch GEMV, DoF gather over the finest level)."""
     from synth import build_problem
     P = build_problem(args.config)
     S = vk.Solver([vk.upload_level(L, dev) for L in P.levels])
@@ -354,27 +354,33 @@ def run_pmc_probe(args, torch, vk, dev):
     S.vanka_smooth(l, b, d, 20, d_is_zero=False)
     torch.cuda.synchronize()
     print(json.dumps({"probe": args.config, "copy_bytes_per_launch": 2 * n * 8, "copy_launches": 3,
-                      "patch_gemv_launches": 20, "patch_gemv_bytes_per_launch": patch_gemv_bytes(P.finest, args.prec),
+                      "sweeps": 20, "patch_gemv_bytes_per_launch": patch_gemv_bytes(P.finest, args.prec),
+                      "spmv_bytes_per_launch": spmv_bytes(P.finest),
+                      "dof_gather_bytes_per_launch": gather_bytes(P.finest, args.prec),
+                      "sweep_bytes": sweep_bytes(P.finest, args.prec),
                       "finest_cells": P.finest.mesh.n_cells}), flush=True)
     S.close()
 
 
 def pmc_traffic(prec, config):
-    """HBM bytes per finest patch_gemv launch from the committed counter summary, scaled by the
-    copy-kernel calibration; None if the summary is missing or the kernel source changed since."""
+    """Measured HBM bytes of one finest-level sweep and of each of its kernels, from the committed
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel calibration); None if the
+    summary is missing, is for another workload, or the kernels' sources changed since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"pmc_patch_gemv_{config}_{prec}.json")
-    src = os.path.join(ROOT, "paper_2210_02690_amd", "csrc", "patch.hip")
+    path = os.path.join(ROOT, "profiles", f"pmc_sweep_{config}.json")
+    csrc = os.path.join(ROOT, "paper_2210_02690_amd", "csrc")
     try:
         with open(path) as f:
             rec = json.load(f)
-        with open(src, "rb") as f:
-            digest = hashlib.sha256(f.read()).hexdigest()
+        digest = {}
+        for name in ("sparse", "patch"):
+            with open(os.path.join(csrc, f"{name}.hip"), "rb") as f:
+                digest[name] = hashlib.sha256(f.read()).hexdigest()
     except OSError:
         return None
-    if rec.get("patch_hip_sha256") != digest:
+    if rec.get("sparse_hip_sha256") != digest["sparse"] or rec.get("patch_hip_sha256") != digest["patch"]:
         return None
-    return rec.get("traffic_bytes_per_launch")
+    return rec.get(prec)
 
 
 def _threads():
@@ -563,15 +569,23 @@ def measure(torch, vk, S, P, b, x, nu, restart, max_iter, steps, warmup, prec, l
                                               note=f"coarsest-level {n0}-unknown FP64 Gauss-Jordan inverse (a "
                                                    f"chain of panel and update launches, bracketed as one)")
     setup_ms, gmres_ms, its_h, rel_h = phase_times(torch, S, b, x, nu, restart, max_iter)
+    # HBM bytes per launch from the committed counter summary (None when it does not apply)
+    tr = pmc_traffic(prec, P.name)
+    traffic = tr["sweep_traffic_bytes"] if tr else None
+    if tr:
+        for k, rec in tr["kernels"].items():
+            for name in kern:
+                if k.startswith(name):
+                    kern[name]["traffic"] = rec["traffic_bytes"]
     return {
         "value": total_its * cs_per_vc / dt, "ms_per_step": dt / steps * 1e3, "steps": steps,
         "gmres_iterations": its_h, "gmres_true_rel_residual": rel_h, "gmres_ms_to_1e-8": gmres_ms,
         "setup_ms": setup_ms,
-        "roofline": roofline_entry("hbm", sweep_gbs, HBM_PEAK_GBS, "GB/s", traffic=None,
+        "roofline": roofline_entry("hbm", sweep_gbs, HBM_PEAK_GBS, "GB/s",
                                    kernel="whole finest-level additive sweep with its defect (SpMV + patch GEMV "
                                           "+ DoF gather), bracketed by events as one unit",
-                                   bytes_per_sweep=bs, avg_sweep_ms=avg["sweep"], sweeps=live["sweep"][0],
-                                   kernels=kern),
+                                   traffic=traffic, bytes_per_sweep=bs, avg_sweep_ms=avg["sweep"],
+                                   sweeps=live["sweep"][0], kernels=kern),
         "finest_cell_sweeps_per_s": fine.mesh.n_cells / (avg["sweep"] * 1e-3),
     }
 
