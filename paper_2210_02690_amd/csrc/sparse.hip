@@ -4,7 +4,12 @@
 
 namespace {
 
-// LPR lanes cooperate on one row; LPR divides the 64-wide wavefront.
+// LPR lanes cooperate on one row; LPR divides the 64-wide wavefront.  A lane takes two
+// consecutive entries at a time (one 16-byte load of the values, one 8-byte load of the columns),
+// the row's lanes together 2 LPR consecutive entries, so a row's stream is read in whole 16-byte
+// pieces: an odd first entry (whose pair would straddle the 16-byte boundary) goes to the row's
+// last lane on its own, and an odd last entry is the lone half of the last pair.  Two pairs are in
+// flight per lane and iteration.  (The value array is 16-byte aligned, as device allocations are.)
 template <int LPR>
 __global__ __launch_bounds__(256) void spmv_kernel(int64_t n_rows, const int64_t* __restrict__ row_ptr,
                                                    const int32_t* __restrict__ col,
@@ -16,18 +21,30 @@ __global__ __launch_bounds__(256) void spmv_kernel(int64_t n_rows, const int64_t
   const int lane = threadIdx.x & (LPR - 1);
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   if (row < n_rows) {
+    int64_t e0 = row_ptr[row];
     const int64_t e1 = row_ptr[row + 1];
-    int64_t e = row_ptr[row] + lane;
-    // four independent loads in flight per lane
-    for (; e + 3 * LPR < e1; e += 4 * LPR) {
-      const int32_t c0 = col[e], c1 = col[e + LPR], c2 = col[e + 2 * LPR], c3 = col[e + 3 * LPR];
-      const double v0 = val[e], v1 = val[e + LPR], v2 = val[e + 2 * LPR], v3 = val[e + 3 * LPR];
-      s0 = fma(v0, x[c0], s0);
-      s1 = fma(v1, x[c1], s1);
-      s2 = fma(v2, x[c2], s2);
-      s3 = fma(v3, x[c3], s3);
+    if ((e0 & 1) && e0 < e1) {  // the odd head entry
+      if (lane == LPR - 1) s3 = val[e0] * x[col[e0]];
+      ++e0;
     }
-    for (; e < e1; e += LPR) s0 = fma(val[e], x[col[e]], s0);
+    int64_t e = e0 + 2 * lane;
+    for (; e + 2 * LPR + 1 < e1; e += 4 * LPR) {
+      const int2 c01 = *reinterpret_cast<const int2*>(col + e);
+      const int2 c23 = *reinterpret_cast<const int2*>(col + e + 2 * LPR);
+      const double2 v01 = *reinterpret_cast<const double2*>(val + e);
+      const double2 v23 = *reinterpret_cast<const double2*>(val + e + 2 * LPR);
+      s0 = fma(v01.x, x[c01.x], s0);
+      s1 = fma(v01.y, x[c01.y], s1);
+      s2 = fma(v23.x, x[c23.x], s2);
+      s3 = fma(v23.y, x[c23.y], s3);
+    }
+    for (; e + 1 < e1; e += 2 * LPR) {
+      const int2 c01 = *reinterpret_cast<const int2*>(col + e);
+      const double2 v01 = *reinterpret_cast<const double2*>(val + e);
+      s0 = fma(v01.x, x[c01.x], s0);
+      s1 = fma(v01.y, x[c01.y], s1);
+    }
+    if (e < e1) s2 = fma(val[e], x[col[e]], s2);  // the odd tail entry
   }
   double sum = (s0 + s1) + (s2 + s3);
 #pragma unroll

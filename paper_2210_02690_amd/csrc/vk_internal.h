@@ -131,6 +131,15 @@ struct vk_level {
   int32_t* cb_used = nullptr;   // per row: 0, or 1 + the column it is the pivot of
 };
 
+// A second stream for the look-ahead of the blocked inversion: after each outer block of columns
+// the next block's columns are updated on the inversion's stream and all other columns on `aux`,
+// overlapping the next block's panels (events: `gathered` orders aux after the pivot rows'
+// gather, `bulk_done` the next gather after aux).
+struct vk_lookahead {
+  hipStream_t aux;
+  hipEvent_t gathered, bulk_done;
+};
+
 struct vk_timing_rec {
   int32_t kind, level, slot;
 };
@@ -274,14 +283,6 @@ int vk_prec_vw(vk_prec prec);
 int vk_prec_bytes(vk_prec prec);
 // directly solved blocks (the coarsest level, and in batches every system's coarsest level)
 int64_t vk_coarse_max_n();
-// A second stream for the look-ahead of the blocked inversion: after each outer block of columns
-// the next block's columns are updated on the inversion's stream and all other columns on `aux`,
-// overlapping the next block's panels (events: `gathered` orders aux after the pivot rows'
-// gather, `bulk_done` the next gather after aux).
-struct vk_lookahead {
-  hipStream_t aux;
-  hipEvent_t gathered, bulk_done;
-};
 hipError_t launch_block_invert(hipStream_t s, const vk_level& L, int32_t* status, double** result,
                                const vk_lookahead* la = nullptr);
 // Blocked Gauss-Jordan inversion of L's blocks (cb_rows, cb_max <= 512), whose dense column-major
