@@ -70,6 +70,7 @@ _SIGS = {
     "vk_timing_enable": (ctypes.c_int, [_P, _I32, _I32]),
     "vk_set_sweep_variant": (ctypes.c_int, [_P, _I32]),
     "vk_set_setup_variant": (ctypes.c_int, [_P, _I32]),
+    "vk_set_coarse_pivoting": (ctypes.c_int, [_P, _I32]),
     "vk_autotune": (ctypes.c_int, [_P, _I32]),
     "vk_set_graphs": (ctypes.c_int, [_P, _I32]),
     "vk_graph_stats": (ctypes.c_int, [_P, _PI64, _PI64]),
@@ -335,6 +336,10 @@ class Solver:
 
     def vk_set_setup_variant(self, variant):
         self._check(_lib.vk_set_setup_variant(self.ctx, variant))
+
+    def vk_set_coarse_pivoting(self, mode):
+        """0: tournament pivoting for blocks wider than 2048 rows; 1: partial pivoting over all rows."""
+        self._check(_lib.vk_set_coarse_pivoting(self.ctx, mode))
 
     def vk_autotune(self, reps=10):
         self._check(_lib.vk_autotune(self.ctx, reps))

@@ -148,6 +148,10 @@ size_t plan_workspace(vk_ctx* ctx, vk_prec prec, int32_t restart, char* base) {
       L.d_cb_woff = cv.take<int64_t>(nbk);
       L.cb_q = cv.take<int32_t>(n);
       L.cb_used = cv.take<int32_t>(n);
+      L.cb_cand_stride = (L.cb_max + 511) / 512 * VK_GJ_NBI_MAX;
+      L.cb_cand = cv.take<int32_t>(nbk * L.cb_cand_stride);
+      L.cb_prs = cv.take<double>((int64_t)nbk * VK_GJ_NBI_MAX * VK_GJ_NBI_MAX);
+      L.cb_pq = cv.take<int32_t>((int64_t)nbk * VK_GJ_NBI_MAX);
     }
   }
   ctx->blocked = vk_blocked_ws();
@@ -506,21 +510,28 @@ vk_status ready(vk_ctx* ctx) {
 // leaves 1/4 of the CUs (64 of 256) out of its mask: measured on the workloads here, 1/8 and
 // 1/4 both shorten the setup (1/4 slightly more), 1/16 and 1/32 do not.  Without CU masking
 // the patch inversions stay on the caller's stream.
-void create_setup_stream(vk_ctx* ctx) {
+// A stream restricted to the first n_cu - n_cu / leave_out CUs; null if CU masking is unavailable.
+// (One such stream per context: with a second one, measured here, the side stream's launches waited
+// for the whole patch inversion.)
+hipStream_t create_masked_stream(int leave_out) {
   int dev = 0, n_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 32) {
     (void)hipGetLastError();
-    return;
+    return nullptr;
   }
-  const int keep = n_cu - n_cu / 4;
+  const int keep = n_cu - n_cu / leave_out;
   std::vector<uint32_t> mask((n_cu + 31) / 32, 0u);
   for (int c = 0; c < keep; ++c) mask[c / 32] |= 1u << (c % 32);
-  if (hipExtStreamCreateWithCUMask(&ctx->setup, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
+  hipStream_t st = nullptr;
+  if (hipExtStreamCreateWithCUMask(&st, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
     (void)hipGetLastError();
-    ctx->setup = nullptr;
+    return nullptr;
   }
+  return st;
 }
+
+void create_setup_stream(vk_ctx* ctx) { ctx->setup = create_masked_stream(4); }
 
 extern "C" {
 
@@ -915,7 +926,7 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
     {
       Timed t(ctx, VK_KERNEL_BLOCK_INVERT, blevels[k], st);
       // the level with the largest blocks (the longest chain) gets the look-ahead stream
-      VK_TRY(launch_block_invert(st, L, ctx->status, &L.cb_W, k == 0 ? &ctx->la : nullptr));
+      VK_TRY(launch_block_invert(st, L, ctx->status, &L.cb_W, k == 0 ? &ctx->la : nullptr, ctx->coarse_tourney));
     }
     if (k > 0) {
       VK_TRY(hipEventRecord(ctx->xjoin[k - 1], st));
@@ -1414,6 +1425,14 @@ vk_status vk_set_setup_variant(vk_ctx* ctx, int32_t variant) {
   if (variant < 0 || variant > 2) return fail(ctx, VK_ERR_ARG, "unknown setup variant");
   ctx->fast_setup = variant != 1;
   ctx->mfma_setup = variant == 0;
+  ctx->setup_done = false;
+  return VK_OK;
+}
+
+vk_status vk_set_coarse_pivoting(vk_ctx* ctx, int32_t mode) {
+  if (!ctx) return VK_ERR_ARG;
+  if (mode != 0 && mode != 1) return fail(ctx, VK_ERR_ARG, "unknown coarse pivoting mode");
+  ctx->coarse_tourney = mode == 0;
   ctx->setup_done = false;
   return VK_OK;
 }

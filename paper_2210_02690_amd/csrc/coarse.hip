@@ -241,6 +241,261 @@ __global__ __launch_bounds__(CTT) void block_panel_kernel(const int64_t* __restr
   }
 }
 
+// ---- Tournament pivoting for the panels of wide blocks ----
+// Partial pivoting over all n rows makes every column step a reduction over the whole block, one
+// workgroup wide, n steps in a row.  For wide blocks the pivots of a TP-column panel are chosen by
+// a tournament instead: every leaf (512 rows, one workgroup) runs the panel's TP elimination
+// steps on its own rows with partial pivoting and proposes the TP rows it chose; one workgroup
+// then plays off the proposals the same way and chooses the panel's TP pivots.  Each proposal
+// set spans its rows' panel (the rows a leaf leaves behind are reduced to zero in the panel's
+// columns), so the final round finds a nonzero pivot at every step exactly when partial
+// pivoting over all rows would.  The pivots differ from those of partial pivoting over all
+// rows, the inverse does not (up to rounding).  The final round also records the scaled pivot
+// row of every step; a separate launch then applies the TP steps to every row, with the same
+// arithmetic as the single-workgroup panel.  Per 16 columns this is four launches (leaves, final
+// round, apply, the rank-16 update of the outer block) instead of four single-workgroup panels
+// and four rank-4 updates.
+constexpr int TP = 16;          // panel width
+constexpr int TLW = 8;          // wavefronts per leaf: 512 rows
+constexpr int TL = TLW * 64;
+constexpr int TRW = 5;          // wavefronts of the final round: up to 320 proposals
+
+// The panel's TP elimination steps over one workgroup's rows (NW wavefronts, one row per thread:
+// panel values P, block-local id, -1 for none).  Step t takes the unused row of largest |value|
+// in the panel's column t (lowest id on ties; a zero value is taken like any other, then
+// eliminates nothing), scales it by its pivot and eliminates column t from every other row.
+// sel[t] receives the chosen id (-1: no row left).  The rounds before the final one only propose
+// rows: they update just the columns still to come, and a chosen row is not replaced by its
+// scaled copy (its values are not read again).  The final round (FINAL) carries the full steps
+// and writes prs[t][.], the scaled pivot row of step t (in the rotated order below), and bad[t],
+// whether step t failed (no row, or a zero or non-finite pivot).
+// The step loop is not unrolled beyond groups of TU steps (a workgroup runs it once; an unrolled
+// body would be fetched from memory instruction by instruction): the columns rotate by TU after
+// each group, so in group g (steps g .. g + TU - 1) P[c] holds the panel's column (g + c) mod TP
+// and step t's column sits at P[t - g].  One barrier per step; the LDS exchange is
+// double-buffered by step parity, as in the single-workgroup panel.
+constexpr int TU = 4;
+template <int NW, bool FINAL>
+__device__ __attribute__((always_inline)) inline void wg_panel_steps(double (&P)[TP], int id, int nb,
+                                                                   double (*xkey)[16], int (*xid)[16],
+                                                                   double (*xrow)[16][TP], int* sel, double* prs,
+                                                                   int* bad) {
+  static_assert(NW <= 16, "the cross-wave step reduces over one 16-lane row");
+  static_assert(TP % TU == 0, "the rotation groups tile the panel");
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0)
+    for (int t = nb; t < TP; ++t) sel[t] = -1;
+  bool used = id < 0;
+#pragma unroll 1
+  for (int g = 0; g < nb; g += TU) {
+#pragma unroll
+    for (int u = 0; u < TU; ++u) {
+      const int t = g + u;
+      if (t >= nb) break;  // uniform
+      const int buf = t & 1;
+      const double key = used ? -1.0 : pivot_key(P[u], id);
+      const double wk = wave_max(key);
+      if (wk >= 0.0 && key == wk) {  // one lane per wavefront (keys are distinct)
+        xkey[buf][wave] = wk;
+        xid[buf][wave] = id;
+#pragma unroll
+        for (int c = 0; c < TP; ++c) xrow[buf][wave][c] = P[c];
+      }
+      if (!(wk >= 0.0) && lane == 0) xkey[buf][wave] = -1.0;
+      __syncthreads();
+      const int wl = lane & 15;
+      const double kw = wl < NW ? xkey[buf][wl] : -1.0;
+      const double pk = row16_max(kw);
+      if (!(pk >= 0.0)) {  // uniform: no unused row left
+        if (tid == 0) {
+          sel[t] = -1;
+          if (FINAL) {
+            bad[t] = 1;
+            for (int c = 0; c < TP; ++c) prs[t * TP + c] = 0.0;
+          }
+        }
+        continue;
+      }
+      const uint64_t hit = __ballot(wl < NW && kw == pk) & 0xFFFFull;
+      const int ow = __ffsll((unsigned long long)hit) - 1;
+      double pr[TP];
+#pragma unroll
+      for (int c = 0; c < TP; ++c) pr[c] = xrow[buf][ow][c];
+      const int p = xid[buf][ow];
+      const double piv = pr[u];
+      const bool zero = !(piv != 0.0) || !isfinite(piv);
+      const double inv = zero ? 0.0 : 1.0 / piv;
+      if (FINAL) {
+#pragma unroll
+        for (int c = 0; c < TP; ++c) pr[c] = (c == u ? 1.0 : pr[c]) * inv;
+        const double f = P[u];
+#pragma unroll
+        for (int c = 0; c < TP; ++c) P[c] = (c == u) ? -f * pr[c] : fma(-f, pr[c], P[c]);
+      } else {
+        const double q = P[u] * inv;
+#pragma unroll
+        for (int c = u + 1; c < TP; ++c) P[c] = fma(-q, pr[c], P[c]);
+      }
+      if (id == p) used = true;
+      if (tid == 0) {
+        sel[t] = p;
+        if (FINAL) {
+          bad[t] = zero ? 1 : 0;
+#pragma unroll
+          for (int c = 0; c < TP; ++c) prs[t * TP + c] = pr[c];
+        }
+      }
+    }
+    // rotate by TU: the next group's columns to P[0 .. TU)
+    double keep[TU];
+#pragma unroll
+    for (int c = 0; c < TU; ++c) keep[c] = P[c];
+#pragma unroll
+    for (int c = 0; c + TU < TP; ++c) P[c] = P[c + TU];
+#pragma unroll
+    for (int c = 0; c < TU; ++c) P[TP - TU + c] = keep[c];
+  }
+  __syncthreads();
+}
+
+// Pivots of the panel [k0, k0 + nb) of every block (blockIdx.y) by tournament, first round; W is
+// only read.  Workgroup x of a block is the leaf of rows [TL x, TL x + TL); its TP winners go to
+// cand[TP x ..].
+__global__ __launch_bounds__(TL) void tourney_leaf_kernel(const int64_t* __restrict__ rows,
+                                                          const int64_t* __restrict__ woff, int64_t k0,
+                                                          const double* __restrict__ W_all,
+                                                          const int32_t* __restrict__ pcol_all,
+                                                          int32_t* __restrict__ cand_all, int32_t cand_stride) {
+  __shared__ double xkey[2][16];
+  __shared__ int xid[2][16];
+  __shared__ double xrow[2][16][TP];
+  __shared__ int s_win[TP];
+  const int bk = blockIdx.y;
+  const int64_t r0 = rows[bk], n = rows[bk + 1] - r0;
+  const int64_t left = n - k0;
+  const int nb = left <= 0 ? 0 : (left < TP ? (int)left : TP);
+  if (nb == 0 || (int64_t)blockIdx.x * TL >= n) return;  // uniform for the workgroup
+  const double* W = W_all + woff[bk];
+  const int64_t i = (int64_t)blockIdx.x * TL + threadIdx.x;
+  const int id = (i < n && pcol_all[r0 + (i < n ? i : 0)] == 0) ? (int)i : -1;
+  double P[TP];
+#pragma unroll
+  for (int c = 0; c < TP; ++c) P[c] = (i < n && c < nb) ? W[(k0 + c) * n + (i < n ? i : 0)] : 0.0;
+  wg_panel_steps<TLW, false>(P, id, nb, xkey, xid, xrow, s_win, nullptr, nullptr);
+  if (threadIdx.x < TP) cand_all[(int64_t)bk * cand_stride + blockIdx.x * TP + threadIdx.x] = s_win[threadIdx.x];
+}
+
+// Final round (one workgroup per block, blockIdx.x): the panel's TP pivots from the leaves'
+// proposals (at most 64 TRW).  It records q, pcol, the scaled pivot rows prs, the pivot rows pq
+// (-1 for a failed step) and gi (the new pivot rows' old values in the outer block's other
+// columns, laid out [t][c - c0o]).
+__global__ __launch_bounds__(64 * TRW) void tourney_root_kernel(
+    const int64_t* __restrict__ rows, const int64_t* __restrict__ woff, int64_t k0, int64_t c0o,
+    const double* __restrict__ W_all, int32_t* __restrict__ q_all, int32_t* __restrict__ pcol_all,
+    double* __restrict__ gi_all, int32_t nbo, const int32_t* __restrict__ cand_all, int32_t cand_stride,
+    double* __restrict__ prs_all, int32_t* __restrict__ pq_all, int32_t bad_base, int32_t* status) {
+  __shared__ double xkey[2][16];
+  __shared__ int xid[2][16];
+  __shared__ double xrow[2][16][TP];
+  __shared__ int s_fin[TP];
+  __shared__ int s_bad[TP];
+  __shared__ double s_prs[TP * TP];
+  const int bk = blockIdx.x;
+  const int64_t r0 = rows[bk], n = rows[bk + 1] - r0;
+  const int64_t left = n - k0;
+  const int nb = left <= 0 ? 0 : (left < TP ? (int)left : TP);
+  if (nb == 0) return;  // uniform
+  const double* W = W_all + woff[bk];
+  const int tid = threadIdx.x;
+  const int C = (int)((n + TL - 1) / TL) * TP;
+  const int id = tid < C ? cand_all[(int64_t)bk * cand_stride + tid] : -1;
+  double P[TP];
+#pragma unroll
+  for (int c = 0; c < TP; ++c) P[c] = (id >= 0 && c < nb) ? W[(k0 + c) * n + (id >= 0 ? id : 0)] : 0.0;
+  wg_panel_steps<TRW, true>(P, id, nb, xkey, xid, xrow, s_fin, s_prs, s_bad);
+  int32_t* q_g = q_all + r0;
+  int32_t* pcol_g = pcol_all + r0;
+  if (tid < nb) {
+    const bool bad = s_bad[tid] != 0 || s_fin[tid] < 0;
+    // failure path only: -1, or the first failing block's number from bad_base on
+    if (bad) atomicMin(&status[0], bad_base < 0 ? -1 : bad_base + bk);
+    const int p = bad ? 0 : s_fin[tid];
+    s_fin[tid] = p;
+    q_g[k0 + tid] = p;
+    pcol_g[p] = (int32_t)(k0 + tid + 1);
+    pq_all[bk * TP + tid] = bad ? -1 : p;
+  }
+  for (int e = tid; e < TP * TP; e += 64 * TRW) prs_all[(int64_t)bk * TP * TP + e] = s_prs[e];
+  __syncthreads();
+  const int64_t ge = (c0o + nbo < n ? c0o + nbo : n);
+  const int gw = (int)(ge - c0o);
+  double* gi = gi_all + (int64_t)bk * TP * nbo;
+  for (int e = tid; e < nb * gw; e += 64 * TRW) {
+    const int t = e / gw;
+    const int64_t c = c0o + (e - t * gw);
+    if (c < k0 || c >= k0 + nb) gi[t * nbo + (c - c0o)] = W[c * n + s_fin[t]];
+  }
+}
+
+// The panel's steps applied to every row of every block (blockIdx.y), one row per thread, with
+// the (rotated) scaled pivot rows of the tournament: the pivot row of step t becomes prs[t];
+// every other row loses f = its column-t value times prs[t] (and column t becomes -f times the
+// scaled pivot).  The same
+// operations in the same order as in the single-workgroup panel.
+__global__ __launch_bounds__(256) void panel_apply_kernel(const int64_t* __restrict__ rows,
+                                                          const int64_t* __restrict__ woff, int64_t k0,
+                                                          double* W_all, const double* __restrict__ prs_all,
+                                                          const int32_t* __restrict__ pq_all) {
+  __shared__ double s_pr[TP][TP];
+  __shared__ int s_pq[TP];
+  const int bk = blockIdx.y;
+  const int64_t r0 = rows[bk], n = rows[bk + 1] - r0;
+  const int64_t left = n - k0;
+  const int nb = left <= 0 ? 0 : (left < TP ? (int)left : TP);
+  if (nb == 0 || (int64_t)blockIdx.x * 256 >= n) return;  // uniform
+  const int tid = threadIdx.x;
+  s_pr[tid >> 4][tid & 15] = prs_all[(int64_t)bk * TP * TP + tid];
+  if (tid < TP) s_pq[tid] = pq_all[bk * TP + tid];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * 256 + tid;
+  if (i >= n) return;
+  double* W = W_all + woff[bk];
+  double P[TP];
+#pragma unroll
+  for (int c = 0; c < TP; ++c) P[c] = c < nb ? W[(k0 + c) * n + i] : 0.0;
+  // rolled over groups of TU steps, as in the tournament: in group g, P[c] holds the panel's
+  // column (g + c) mod TP, as do the scaled pivot rows
+#pragma unroll 1
+  for (int g = 0; g < nb; g += TU) {
+#pragma unroll
+    for (int u = 0; u < TU; ++u) {
+      const int t = g + u;
+      if (t >= nb) break;  // uniform
+      if (i == s_pq[t]) {
+#pragma unroll
+        for (int c = 0; c < TP; ++c) P[c] = s_pr[t][c];
+      } else {
+        const double f = P[u];
+#pragma unroll
+        for (int c = 0; c < TP; ++c) P[c] = (c == u) ? -f * s_pr[t][c] : fma(-f, s_pr[t][c], P[c]);
+      }
+    }
+    double keep[TU];
+#pragma unroll
+    for (int c = 0; c < TU; ++c) keep[c] = P[c];
+#pragma unroll
+    for (int c = 0; c + TU < TP; ++c) P[c] = P[c + TU];
+#pragma unroll
+    for (int c = 0; c < TU; ++c) P[TP - TU + c] = keep[c];
+  }
+  const int rot = (nb + TU - 1) / TU * TU;  // the rotation after the last group
+#pragma unroll
+  for (int c = 0; c < TP; ++c) {
+    const int a = (rot + c) & (TP - 1);  // the panel column at P[c]
+    if (a < nb) W[(k0 + a) * n + i] = P[c];
+  }
+}
+
 // old values of the outer block's pivot rows in every column: go[t][c] = W[q[c0o + t]][c]
 __global__ void gather_pivot_rows_kernel(const int64_t* __restrict__ rows, const int64_t* __restrict__ woff,
                                          int64_t c0o, int32_t nbo, const double* __restrict__ W_all,
@@ -285,6 +540,7 @@ __global__ __launch_bounds__(256, 3) void gj_update_kernel(const int64_t* __rest
   const int64_t rt = (int64_t)blockIdx.x * 64;
   const int64_t ct = tile_c0 + (int64_t)blockIdx.y * 64;
   if (kk <= 0 || ct >= ceb || rt >= n) return;  // uniform for the workgroup
+  if (ct >= sk0 && ct + 64 <= sk1) return;       // every column of the tile is skipped
   double* W = W_all + woff[bk];
   const int32_t* pcol = pcol_all + rb0;
   const double* G = g_stride > 0 ? G_all + (int64_t)bk * g_stride : G_all + (int64_t)K * (rb0 - rows[0]);
@@ -440,11 +696,13 @@ __global__ void block_export_kernel(int64_t n, const double* __restrict__ W, con
   }
 }
 
-template <int CTT, int R, int NB, int NBO>
+// TN: panels of TP columns with tournament pivoting (CTT and R unused)
+template <int CTT, int R, int NB, int NBO, bool TN = false>
 hipError_t run_blocked(hipStream_t s, const vk_level& L, int32_t* status, int32_t bad_base = -1,
                        const vk_lookahead* la = nullptr) {
   static_assert(NBO % NB == 0 && NB <= VK_GJ_NBI_MAX && NBO % 64 == 0 && NBO <= VK_GJ_NBO,
                 "inner panels must tile the outer block, whose columns come in whole 64-column tiles");
+  static_assert(!TN || NB == TP, "tournament panels are TP columns wide");
   const int nbk = (int)L.cb_rows.size() - 1;
   const int64_t n = L.cb_max;
   const unsigned row_tiles = (unsigned)((n + 63) / 64);
@@ -452,8 +710,18 @@ hipError_t run_blocked(hipStream_t s, const vk_level& L, int32_t* status, int32_
   bool bulk_pending = false;  // a rank-NBO update of the other columns is running on la->aux
   for (int64_t c0o = 0; c0o < n; c0o += NBO) {
     for (int64_t k0 = c0o; k0 < c0o + NBO && k0 < n; k0 += NB) {
-      block_panel_kernel<CTT, R, NB><<<nbk, CTT, 0, s>>>(L.d_cb_rows, L.d_cb_woff, k0, c0o, L.cb_a, L.cb_q,
-                                                         L.cb_used, L.cb_gi, NBO, bad_base, status);
+      if constexpr (TN) {
+        tourney_leaf_kernel<<<dim3((unsigned)((n + TL - 1) / TL), nbk), TL, 0, s>>>(
+            L.d_cb_rows, L.d_cb_woff, k0, L.cb_a, L.cb_used, L.cb_cand, (int32_t)L.cb_cand_stride);
+        tourney_root_kernel<<<nbk, 64 * TRW, 0, s>>>(L.d_cb_rows, L.d_cb_woff, k0, c0o, L.cb_a, L.cb_q, L.cb_used,
+                                               L.cb_gi, NBO, L.cb_cand, (int32_t)L.cb_cand_stride, L.cb_prs,
+                                               L.cb_pq, bad_base, status);
+        panel_apply_kernel<<<dim3((unsigned)((n + 255) / 256), nbk), 256, 0, s>>>(L.d_cb_rows, L.d_cb_woff, k0,
+                                                                                 L.cb_a, L.cb_prs, L.cb_pq);
+      } else {
+        block_panel_kernel<CTT, R, NB><<<nbk, CTT, 0, s>>>(L.d_cb_rows, L.d_cb_woff, k0, c0o, L.cb_a, L.cb_q,
+                                                           L.cb_used, L.cb_gi, NBO, bad_base, status);
+      }
       // the same steps on the outer block's other columns, before and after the panel
       if (n > NB)
         gj_update_kernel<NB><<<dim3(row_tiles, NBO / 64, nbk), 256, 0, s>>>(
@@ -499,7 +767,7 @@ hipError_t run_blocked(hipStream_t s, const vk_level& L, int32_t* status, int32_
 int64_t vk_coarse_max_n() { return 9216; }
 
 hipError_t launch_block_invert(hipStream_t s, const vk_level& L, int32_t* status, double** result,
-                               const vk_lookahead* la) {
+                               const vk_lookahead* la, bool tourney) {
   const int nbk = (int)L.cb_rows.size() - 1;
   *result = L.cb_a;
   if (nbk <= 0) return hipSuccess;
@@ -517,6 +785,12 @@ hipError_t launch_block_invert(hipStream_t s, const vk_level& L, int32_t* status
   // are few workgroups wide; many blocks per level keep 64
   const int64_t m = L.cb_max;
   const bool wide = nbk <= 8;
+  if (tourney && m > VK_TOURNEY_MIN_N) {
+    // proposals: TP per TL rows, at most one per thread of the final round
+    if ((m + TL - 1) / TL * TP > 64 * TRW || L.cb_cand_stride < (m + TL - 1) / TL * TP) return hipErrorInvalidValue;
+    return wide ? run_blocked<256, 1, TP, 128, true>(s, L, status, -1, la)
+                : run_blocked<256, 1, TP, 64, true>(s, L, status, -1, la);
+  }
   if (m <= 1024)
     e = wide ? run_blocked<512, 2, 16, 128>(s, L, status, -1, la) : run_blocked<512, 2, 16, 64>(s, L, status, -1, la);
   else if (m <= 2048)

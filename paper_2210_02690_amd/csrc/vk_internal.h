@@ -129,6 +129,13 @@ struct vk_level {
   int64_t* d_cb_woff = nullptr; // offset of each block's dense matrix
   int32_t* cb_q = nullptr;      // pivot rows (block-local), per block
   int32_t* cb_used = nullptr;   // per row: 0, or 1 + the column it is the pivot of
+  // tournament pivoting of wide blocks: leaves' proposals (cb_cand_stride per block), the
+  // panel's scaled pivot rows (per block VK_GJ_NBI_MAX^2) and pivot rows (per block
+  // VK_GJ_NBI_MAX, -1 for a failed step)
+  int32_t* cb_cand = nullptr;
+  int64_t cb_cand_stride = 0;
+  double* cb_prs = nullptr;
+  int32_t* cb_pq = nullptr;
 };
 
 // A second stream for the look-ahead of the blocked inversion: after each outer block of columns
@@ -186,6 +193,7 @@ struct vk_ctx {
   int32_t sweep_variant = 0;  // additive sweep: 0 DoF gather, 1 coloured scatter
   bool fast_setup = true;     // register-resident patch inversion where compiled
   bool mfma_setup = true;     // the matrix-core kernel where one is compiled for the patch width
+  bool coarse_tourney = true; // tournament pivoting for wide directly solved blocks
   bool maps_ready = false;    // multiplicities and DoF lists (depend on the mesh only)
   // the block inversions of the last setup run on `side`; the first call that applies a
   // block makes `stream` wait for them, and the first synchronisation after that checks
@@ -283,8 +291,10 @@ int vk_prec_vw(vk_prec prec);
 int vk_prec_bytes(vk_prec prec);
 // directly solved blocks (the coarsest level, and in batches every system's coarsest level)
 int64_t vk_coarse_max_n();
+// tourney: blocks wider than VK_TOURNEY_MIN_N rows choose their pivots by tournament
+#define VK_TOURNEY_MIN_N 2048
 hipError_t launch_block_invert(hipStream_t s, const vk_level& L, int32_t* status, double** result,
-                               const vk_lookahead* la = nullptr);
+                               const vk_lookahead* la = nullptr, bool tourney = true);
 // Blocked Gauss-Jordan inversion of L's blocks (cb_rows, cb_max <= 512), whose dense column-major
 // matrices are already in L.cb_a; a failing pivot sets status[0] to min(bad_base + block).
 hipError_t launch_blocks_invert_dense(hipStream_t s, const vk_level& L, int32_t* status, int32_t bad_base);

@@ -507,10 +507,12 @@ def test_autotuned_matches_oracle(vk):
     assert rel(x.cpu().numpy(), oracle.vcycle(H, b, 2, 2)) <= 1e-10
 
 
-def test_coarse_solve_3d_box_size(vk):
+@pytest.mark.parametrize("pivoting", [0, 1])
+def test_coarse_solve_3d_box_size(vk, pivoting):
     """The 3D box's coarsest level (25 x 2 x 2 hexahedra, dG(1), n = 8 450, the largest directly
     solved block) on its own: the one-level V-cycle is the direct solve; it agrees with a sparse
-    LU solve and leaves a residual at rounding level."""
+    LU solve and leaves a residual at rounding level, with the pivots chosen by tournament (0) and
+    by partial pivoting over all rows (1)."""
     import time
     import scipy.sparse.linalg as spla
     from synth.assemble import assemble_jacobian
@@ -523,7 +525,8 @@ def test_coarse_solve_3d_box_size(vk):
     lv = Level(mesh=m, J=J, P=None, R=None, cell_dofs=m.cell_dofs(), colours=m.colours(), state=V)
     S = vk.Solver([vk.upload_level(lv, DEV)])
     S.vk_set_workspace("f64", 30, device=DEV)
-    _say("coarse 8450 setup")
+    S.vk_set_coarse_pivoting(pivoting)
+    _say(f"coarse 8450 setup, pivoting {pivoting}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     S.vanka_setup(0.7, "additive")
@@ -558,6 +561,85 @@ def test_coarse_inverse_with_tied_pivots(vk, n):
     # H is orthogonal up to the factor n (condition number 1): a wrong or inconsistent pivot choice
     # shows as an O(1) error or a singular-block report, rounding stays far below this bound
     assert rel(out.cpu().numpy(), H.T / n) <= 1e-10
+    S.close()
+
+
+def _dense_level(A):
+    import types
+    import scipy.sparse as sp
+    return types.SimpleNamespace(J=sp.csr_matrix(A), P=None, R=None, cell_dofs=np.zeros((1, 1), np.int32),
+                                 colours=np.zeros(1, np.int32))
+
+
+def _saddle(n, m, seed):
+    """[[K, B^T], [B, 0]] with K symmetric positive definite and B of full rank: the zero block
+    makes pivoting across distant rows necessary (no pressure row can pivot its own column)."""
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((n, n))
+    K = G @ G.T / n + np.eye(n)
+    B = rng.standard_normal((m, n))
+    A = np.zeros((n + m, n + m))
+    A[:n, :n] = K
+    A[:n, n:] = B.T
+    A[n:, :n] = B
+    perm = rng.permutation(n + m)  # interleave the two kinds of rows
+    return A[np.ix_(perm, perm)]
+
+
+@pytest.mark.parametrize("n, kind", [(2049, "gauss"), (3001, "gauss"), (2600, "saddle"), (4100, "saddle")])
+def test_wide_coarse_inverse_pivoting_modes(vk, n, kind):
+    """Dense blocks wider than 2048 rows (ragged against the 16-column panels, the 64-column tiles and
+    the 256-row leaves): the inverse by tournament pivoting (0) and by partial pivoting over all rows
+    (1) both match numpy's inverse, within 1e4 eps times the condition number."""
+    if kind == "gauss":
+        A = np.random.default_rng(n).standard_normal((n, n))
+    else:
+        A = _saddle(n - n // 5, n // 5, n)
+    ref = np.linalg.inv(A)
+    cond = np.linalg.cond(A)
+    outs = []
+    for mode in (0, 1):
+        S = vk.Solver([vk.upload_level(_dense_level(A), DEV)])
+        S.vk_set_workspace("f64", 30, device=DEV)
+        S.vk_set_coarse_pivoting(mode)
+        S.vanka_setup(0.7, "additive")
+        out = torch.empty((n, n), dtype=torch.float64, device=DEV)
+        S.vk_get_coarse_inverse(out)
+        outs.append(out.cpu().numpy())
+        S.close()
+        # a wrong pivot or a skipped step shows as an O(1) error; rounding stays within eps cond
+        assert rel(outs[-1], ref) <= 1e4 * 2.2e-16 * cond, (mode, rel(outs[-1], ref), cond)
+    assert rel(outs[0], outs[1]) <= 1e4 * 2.2e-16 * cond
+
+
+@pytest.mark.parametrize("pivoting", [0, 1])
+@pytest.mark.parametrize("defect", ["column", "row"])
+def test_singular_wide_coarse_block_reported(vk, pivoting, defect):
+    """A 3 000-row block with a zero column (or row), which the elimination keeps exactly zero: no
+    nonzero pivot is left for that column (for the last column), so the first solve reports the block
+    as singular under both pivot choices."""
+    n = 3000
+    A = np.random.default_rng(5).standard_normal((n, n))
+    if defect == "column":
+        A[:, 2500] = 0.0
+    else:
+        A[1234, :] = 0.0
+    S = vk.Solver([vk.upload_level(_dense_level(A), DEV)])
+    S.vk_set_workspace("f64", 30, device=DEV)
+    S.vk_set_coarse_pivoting(pivoting)
+    S.vanka_setup(0.7, "additive")
+    b = t(np.ones(n))
+    x = torch.zeros_like(b)
+    with pytest.raises(vk.VkError, match="singular"):
+        S.vcycle(b, x, 0, 0)
+    S.close()
+
+
+def test_coarse_pivoting_mode_rejected(vk):
+    P, _ = problem("cfg0")
+    S = make_solver(vk, P)
+    with pytest.raises(vk.VkError, match="pivoting"):
+        S.vk_set_coarse_pivoting(2)
     S.close()
 
 
