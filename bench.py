@@ -520,7 +520,10 @@ def measure(torch, vk, S, P, b, x, nu, restart, max_iter, steps, warmup, prec, l
         its, rel = run_step(S, b, x, nu, restart, max_iter)
         log(f"[bench] {label} warmup {w}: {its} its, rel {rel:.2e}")
     kinds = ["sweep", "spmv", "patch_gemv", "dof_gather", "patch_setup"]
-    S.vk_timing_kinds(kinds)
+    # A 2D step is a few ms of short launches: events on every bracketed launch would cost about
+    # 1 ms per step there, so one bracketed launch in seven is timed (7 is prime to the four sweeps
+    # per level and V-cycle, so every sweep position is sampled).  3D launches last 0.03-1 ms: all.
+    S.vk_timing_kinds(kinds, every=7 if fine.mesh.d == 2 else 1)
     S.vk_timing_enable(True, L)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

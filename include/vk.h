@@ -268,13 +268,13 @@ vk_status vk_set_sweep_variant(vk_ctx* ctx, int32_t variant);
 vk_status vk_set_setup_variant(vk_ctx* ctx, int32_t variant);
 
 /* Pivot choice of the directly solved blocks' Gauss-Jordan inversion (the
- * coarsest level's direct solve, Sec. 3).  0 (default): blocks wider than 2048
- * rows take the pivots of each 16-column panel by tournament (each 64-row leaf
- * proposes the rows its own partial pivoting chose, the proposals are played
- * off until one wavefront picks the panel's pivots), narrower blocks as 1;
- * 1: partial pivoting over all unused rows, column by column.  Both compute the
- * same inverse up to rounding, and both report a block whose panel has no
- * nonzero pivot.  Setup must run again after a change. */
+ * coarsest level's direct solve, Sec. 3).  0 (default): blocks wider than 4096
+ * rows take the pivots of each 16-column panel by tournament (each 512-row leaf
+ * proposes the rows its own partial pivoting chose, and one workgroup picks the
+ * panel's pivots from the proposals), narrower blocks as 1; 1: partial pivoting
+ * over all unused rows, column by column; 2: the tournament for every block.
+ * All compute the same inverse up to rounding, and all report a block whose
+ * panel has no nonzero pivot.  Setup must run again after a change. */
 vk_status vk_set_coarse_pivoting(vk_ctx* ctx, int32_t mode);
 
 /* Autotuner: after vanka_setup, times each level's SpMV kernels (J, P, R)

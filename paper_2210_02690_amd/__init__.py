@@ -338,7 +338,8 @@ class Solver:
         self._check(_lib.vk_set_setup_variant(self.ctx, variant))
 
     def vk_set_coarse_pivoting(self, mode):
-        """0: tournament pivoting for blocks wider than 2048 rows; 1: partial pivoting over all rows."""
+        """0: tournament pivoting for blocks wider than 4096 rows; 1: partial pivoting over all rows;
+        2: the tournament for every block."""
         self._check(_lib.vk_set_coarse_pivoting(self.ctx, mode))
 
     def vk_autotune(self, reps=10):

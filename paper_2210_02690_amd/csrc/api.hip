@@ -926,7 +926,7 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
     {
       Timed t(ctx, VK_KERNEL_BLOCK_INVERT, blevels[k], st);
       // the level with the largest blocks (the longest chain) gets the look-ahead stream
-      VK_TRY(launch_block_invert(st, L, ctx->status, &L.cb_W, k == 0 ? &ctx->la : nullptr, ctx->coarse_tourney));
+      VK_TRY(launch_block_invert(st, L, ctx->status, &L.cb_W, k == 0 ? &ctx->la : nullptr, ctx->coarse_min_tourney));
     }
     if (k > 0) {
       VK_TRY(hipEventRecord(ctx->xjoin[k - 1], st));
@@ -1431,8 +1431,8 @@ vk_status vk_set_setup_variant(vk_ctx* ctx, int32_t variant) {
 
 vk_status vk_set_coarse_pivoting(vk_ctx* ctx, int32_t mode) {
   if (!ctx) return VK_ERR_ARG;
-  if (mode != 0 && mode != 1) return fail(ctx, VK_ERR_ARG, "unknown coarse pivoting mode");
-  ctx->coarse_tourney = mode == 0;
+  if (mode < 0 || mode > 2) return fail(ctx, VK_ERR_ARG, "unknown coarse pivoting mode");
+  ctx->coarse_min_tourney = mode == 0 ? VK_TOURNEY_MIN_N : (mode == 1 ? INT64_MAX : 0);
   ctx->setup_done = false;
   return VK_OK;
 }

@@ -767,7 +767,7 @@ hipError_t run_blocked(hipStream_t s, const vk_level& L, int32_t* status, int32_
 int64_t vk_coarse_max_n() { return 9216; }
 
 hipError_t launch_block_invert(hipStream_t s, const vk_level& L, int32_t* status, double** result,
-                               const vk_lookahead* la, bool tourney) {
+                               const vk_lookahead* la, int64_t min_tourney) {
   const int nbk = (int)L.cb_rows.size() - 1;
   *result = L.cb_a;
   if (nbk <= 0) return hipSuccess;
@@ -785,7 +785,7 @@ hipError_t launch_block_invert(hipStream_t s, const vk_level& L, int32_t* status
   // are few workgroups wide; many blocks per level keep 64
   const int64_t m = L.cb_max;
   const bool wide = nbk <= 8;
-  if (tourney && m > VK_TOURNEY_MIN_N) {
+  if (m > min_tourney) {
     // proposals: TP per TL rows, at most one per thread of the final round
     if ((m + TL - 1) / TL * TP > 64 * TRW || L.cb_cand_stride < (m + TL - 1) / TL * TP) return hipErrorInvalidValue;
     return wide ? run_blocked<256, 1, TP, 128, true>(s, L, status, -1, la)

@@ -21,6 +21,9 @@
 // blocked Gauss-Jordan of the directly solved blocks: outer block width, widest inner panel
 #define VK_GJ_NBO 128  // widest outer block of the blocked Gauss-Jordan inversion (buffer sizes)
 #define VK_GJ_NBI_MAX 16
+// blocks wider than this choose their pivots by tournament by default (below it the single-workgroup
+// panels, which run a level's blocks side by side, are as fast)
+#define VK_TOURNEY_MIN_N 4096
 
 // ---- wavefront reductions through DPP (row shifts, then row broadcasts);
 // the result of lane 63 is returned to every lane ----
@@ -193,7 +196,7 @@ struct vk_ctx {
   int32_t sweep_variant = 0;  // additive sweep: 0 DoF gather, 1 coloured scatter
   bool fast_setup = true;     // register-resident patch inversion where compiled
   bool mfma_setup = true;     // the matrix-core kernel where one is compiled for the patch width
-  bool coarse_tourney = true; // tournament pivoting for wide directly solved blocks
+  int64_t coarse_min_tourney = VK_TOURNEY_MIN_N;  // blocks wider than this choose pivots by tournament
   bool maps_ready = false;    // multiplicities and DoF lists (depend on the mesh only)
   // the block inversions of the last setup run on `side`; the first call that applies a
   // block makes `stream` wait for them, and the first synchronisation after that checks
@@ -291,10 +294,9 @@ int vk_prec_vw(vk_prec prec);
 int vk_prec_bytes(vk_prec prec);
 // directly solved blocks (the coarsest level, and in batches every system's coarsest level)
 int64_t vk_coarse_max_n();
-// tourney: blocks wider than VK_TOURNEY_MIN_N rows choose their pivots by tournament
-#define VK_TOURNEY_MIN_N 2048
+// tourney: blocks wider than min_tourney rows choose their pivots by tournament
 hipError_t launch_block_invert(hipStream_t s, const vk_level& L, int32_t* status, double** result,
-                               const vk_lookahead* la = nullptr, bool tourney = true);
+                               const vk_lookahead* la = nullptr, int64_t min_tourney = VK_TOURNEY_MIN_N);
 // Blocked Gauss-Jordan inversion of L's blocks (cb_rows, cb_max <= 512), whose dense column-major
 // matrices are already in L.cb_a; a failing pivot sets status[0] to min(bad_base + block).
 hipError_t launch_blocks_invert_dense(hipStream_t s, const vk_level& L, int32_t* status, int32_t bad_base);

@@ -542,11 +542,13 @@ def test_coarse_solve_3d_box_size(vk, pivoting):
     S.close()
 
 
+@pytest.mark.parametrize("pivoting", [0, 2])
 @pytest.mark.parametrize("n", [64, 256, 1024, 2048, 4096])
-def test_coarse_inverse_with_tied_pivots(vk, n):
+def test_coarse_inverse_with_tied_pivots(vk, n, pivoting):
     """A Hadamard matrix (all entries +-1: every column's candidates tie in |a| at the first step,
-    and ties recur) through the blocked Gauss-Jordan path of each block size: its inverse is H^T / n.
-    Sizes cover one panel width and several outer blocks (64 columns each) per block kernel shape."""
+    and ties recur) through the blocked Gauss-Jordan path of each block size, with the default pivot
+    choice and with the tournament (2): its inverse is H^T / n.  Sizes cover one panel width and several
+    outer blocks (64 columns each) per block kernel shape."""
     import types
     import scipy.linalg
     import scipy.sparse as sp
@@ -555,6 +557,7 @@ def test_coarse_inverse_with_tied_pivots(vk, n):
                                colours=np.zeros(1, np.int32))
     S = vk.Solver([vk.upload_level(lv, DEV)])
     S.vk_set_workspace("f64", 30, device=DEV)
+    S.vk_set_coarse_pivoting(pivoting)
     S.vanka_setup(0.7, "additive")
     out = torch.empty((n, n), dtype=torch.float64, device=DEV)
     S.vk_get_coarse_inverse(out)
@@ -588,9 +591,10 @@ def _saddle(n, m, seed):
 
 @pytest.mark.parametrize("n, kind", [(2049, "gauss"), (3001, "gauss"), (2600, "saddle"), (4100, "saddle")])
 def test_wide_coarse_inverse_pivoting_modes(vk, n, kind):
-    """Dense blocks wider than 2048 rows (ragged against the 16-column panels, the 64-column tiles and
-    the 256-row leaves): the inverse by tournament pivoting (0) and by partial pivoting over all rows
-    (1) both match numpy's inverse, within 1e4 eps times the condition number."""
+    """Dense blocks of 2 049 to 4 100 rows (ragged against the 16-column panels, the 64-column tiles
+    and the 512-row leaves): the inverse with the default pivot choice (0: the tournament above 4 096
+    rows), partial pivoting over all rows (1) and the tournament (2) all match numpy's inverse, within
+    1e4 eps times the condition number, and agree with each other."""
     if kind == "gauss":
         A = np.random.default_rng(n).standard_normal((n, n))
     else:
@@ -598,7 +602,7 @@ def test_wide_coarse_inverse_pivoting_modes(vk, n, kind):
     ref = np.linalg.inv(A)
     cond = np.linalg.cond(A)
     outs = []
-    for mode in (0, 1):
+    for mode in (0, 1, 2):
         S = vk.Solver([vk.upload_level(_dense_level(A), DEV)])
         S.vk_set_workspace("f64", 30, device=DEV)
         S.vk_set_coarse_pivoting(mode)
@@ -609,10 +613,11 @@ def test_wide_coarse_inverse_pivoting_modes(vk, n, kind):
         S.close()
         # a wrong pivot or a skipped step shows as an O(1) error; rounding stays within eps cond
         assert rel(outs[-1], ref) <= 1e4 * 2.2e-16 * cond, (mode, rel(outs[-1], ref), cond)
-    assert rel(outs[0], outs[1]) <= 1e4 * 2.2e-16 * cond
+    assert rel(outs[2], outs[1]) <= 1e4 * 2.2e-16 * cond
+    assert rel(outs[0], outs[2 if n > 4096 else 1]) == 0.0  # the default picks one of the two
 
 
-@pytest.mark.parametrize("pivoting", [0, 1])
+@pytest.mark.parametrize("pivoting", [1, 2])
 @pytest.mark.parametrize("defect", ["column", "row"])
 def test_singular_wide_coarse_block_reported(vk, pivoting, defect):
     """A 3 000-row block with a zero column (or row), which the elimination keeps exactly zero: no
@@ -639,7 +644,7 @@ def test_coarse_pivoting_mode_rejected(vk):
     P, _ = problem("cfg0")
     S = make_solver(vk, P)
     with pytest.raises(vk.VkError, match="pivoting"):
-        S.vk_set_coarse_pivoting(2)
+        S.vk_set_coarse_pivoting(3)
     S.close()
 
 
