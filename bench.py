@@ -566,11 +566,14 @@ def measure(torch, vk, S, P, b, x, nu, restart, max_iter, steps, warmup, prec, l
                                                   "2 n_K^3 flop per cell")
     n0 = P.levels[0].n
     if avg["block_invert"]:
-        fl = 2.0 * n0 ** 3
-        kern["block_invert"] = roofline_entry("mfma", fl / (avg["block_invert"] * 1e-3) / 1e12, FP64_PEAK_TFS,
-                                              "TFLOP/s", flops_per_launch=fl, avg_ms=avg["block_invert"],
-                                              note=f"coarsest-level {n0}-unknown FP64 Gauss-Jordan inverse (a "
-                                                   f"chain of panel and update launches, bracketed as one)")
+        nb, fl = S.vk_coarse_plan(0)
+        what = (f"block-tridiagonal factorisation of the coarsest level's {n0} unknowns in {nb} level-set "
+                f"blocks (dense Gauss-Jordan inverses of the Schur-complement blocks and the coupling "
+                f"products)") if nb > 0 else f"FP64 Gauss-Jordan inverse of the coarsest level's {n0} unknowns"
+        kern["block_invert"] = roofline_entry("mfma" if nb == 0 else "alu", fl / (avg["block_invert"] * 1e-3) / 1e12,
+                                              FP64_PEAK_TFS, "TFLOP/s", flops_per_launch=fl,
+                                              avg_ms=avg["block_invert"], blocks=nb,
+                                              note=what + ": a chain of launches, bracketed as one")
     setup_ms, gmres_ms, its_h, rel_h = phase_times(torch, S, b, x, nu, restart, max_iter)
     # HBM bytes per launch from the committed counter summary (None when it does not apply)
     tr = pmc_traffic(prec, P.name)

@@ -277,6 +277,28 @@ vk_status vk_set_setup_variant(vk_ctx* ctx, int32_t variant);
  * panel has no nonzero pivot.  Setup must run again after a change. */
 vk_status vk_set_coarse_pivoting(vk_ctx* ctx, int32_t mode);
 
+/* Direct solver of a level whose directly solved rows form one block wider
+ * than 4096 unknowns (the coarsest level's direct solve, Sec. 3).  0 (default):
+ * where the block's sparsity allows it, a block-tridiagonal factorisation:
+ * breadth-first level sets of the symmetrised pattern, grouped into blocks of
+ * at least 256 and at most 2048 unknowns, are eliminated in order (each
+ * Schur-complement block inverted densely by Gauss-Jordan with partial
+ * pivoting inside the block); the solve runs forward and back over the blocks.
+ * The plan is made on the host at the first vanka_setup after vk_set_level or
+ * vk_set_workspace (the pattern is copied to the host once).  Blocks without
+ * such a structure, and every block under mode 1, get the dense inverse.  Both
+ * compute J_0^{-1} b up to rounding; a singular block is reported by the first
+ * solve either way.  vk_get_coarse_inverse needs the dense inverse.  Setup must
+ * run again after a change. */
+vk_status vk_set_coarse_solver(vk_ctx* ctx, int32_t mode);
+
+/* After vanka_setup: the number of blocks of level `level`'s block-tridiagonal
+ * factorisation (0 when its directly solved blocks are inverted densely, -1 for
+ * an invalid call), and in *setup_flops (if not null) the algorithmic flop
+ * count of one factorisation or inversion (2 sum s_i^3 + 4 sum s_i^2 s_(i+1),
+ * or 2 sum m_b^3 for dense inverses of blocks of m_b rows). */
+int32_t vk_coarse_plan(vk_ctx* ctx, int32_t level, double* setup_flops);
+
 /* Autotuner: after vanka_setup, times each level's SpMV kernels (J, P, R)
  * with 4, 8, 16, 32 and 64 lanes per row and the patch GEMV with 1, 2, 4 and
  * 8 cells per workgroup (`reps` launches each, HIP events) and keeps the

@@ -71,6 +71,8 @@ _SIGS = {
     "vk_set_sweep_variant": (ctypes.c_int, [_P, _I32]),
     "vk_set_setup_variant": (ctypes.c_int, [_P, _I32]),
     "vk_set_coarse_pivoting": (ctypes.c_int, [_P, _I32]),
+    "vk_set_coarse_solver": (ctypes.c_int, [_P, _I32]),
+    "vk_coarse_plan": (ctypes.c_int, [_P, _I32, _PD]),
     "vk_autotune": (ctypes.c_int, [_P, _I32]),
     "vk_set_graphs": (ctypes.c_int, [_P, _I32]),
     "vk_graph_stats": (ctypes.c_int, [_P, _PI64, _PI64]),
@@ -341,6 +343,18 @@ class Solver:
         """0: tournament pivoting for blocks wider than 4096 rows; 1: partial pivoting over all rows;
         2: the tournament for every block."""
         self._check(_lib.vk_set_coarse_pivoting(self.ctx, mode))
+
+    def vk_set_coarse_solver(self, mode):
+        """0: block-tridiagonal factorisation of a wide coarse block where its pattern allows; 1: dense inverse."""
+        self._check(_lib.vk_set_coarse_solver(self.ctx, mode))
+
+    def vk_coarse_plan(self, level=0):
+        """(blocks of the level's block-tridiagonal factorisation, 0 for dense inverses; setup flops)."""
+        f = _D(0.0)
+        nb = _lib.vk_coarse_plan(self.ctx, level, ctypes.byref(f))
+        if nb < 0:
+            raise VkError(VK_ERR_ARG, "invalid level")
+        return int(nb), float(f.value)
 
     def vk_autotune(self, reps=10):
         self._check(_lib.vk_autotune(self.ctx, reps))

@@ -142,6 +142,7 @@ size_t plan_workspace(vk_ctx* ctx, vk_prec prec, int32_t restart, char* base) {
     const int nbk = (int)L.cb_rows.size() - 1;
     if (nbk > 0) {
       L.cb_a = cv.take<double>(L.cb_sq);
+      L.bt = vk_bt();  // a block-tridiagonal plan lives in cb_a: made again for the new buffer
       L.cb_gi = cv.take<double>((int64_t)nbk * VK_GJ_NBI_MAX * VK_GJ_NBO);
       L.cb_go = cv.take<double>((int64_t)VK_GJ_NBO * (L.cb_rows[nbk] - L.cb_rows[0]));
       L.d_cb_rows = cv.take<int64_t>(nbk + 1);
@@ -334,7 +335,8 @@ vk_status vcycle_level(vk_ctx* ctx, int l, const double* b, double* x, int32_t n
   vk_level& L = ctx->lv[l];
   if (l == 0) {
     if (ctx->coarse_pending) VK_CHECK(coarse_wait(ctx, false));  // only now wait for the inversion
-    VK_TRY(launch_block_apply(s, L, b, x));
+    if (L.bt.active) VK_TRY(launch_bt_solve(s, L, b, x));
+    else VK_TRY(launch_block_apply(s, L, b, x));
     return VK_OK;
   }
   vk_level& C = ctx->lv[l - 1];
@@ -342,7 +344,8 @@ vk_status vcycle_level(vk_ctx* ctx, int l, const double* b, double* x, int32_t n
   else VK_TRY(launch_fill(s, L.J.n_rows, 0.0, x));
   // systems whose coarsest level is this one are solved directly (their rows carry no cells)
   if (ctx->coarse_pending && L.cb_rows.size() > 1) VK_CHECK(coarse_wait(ctx, false));
-  VK_TRY(launch_block_apply(s, L, b, x));
+  if (L.bt.active) VK_TRY(launch_bt_solve(s, L, b, x));
+  else VK_TRY(launch_block_apply(s, L, b, x));
   VK_TRY(launch_spmv(s, L.J, L.lpr_J, -1.0, x, 1.0, b, L.r));
   VK_TRY(launch_spmv(s, L.R, L.lpr_R, 1.0, L.r, 0.0, nullptr, C.b));
   VK_CHECK(vcycle_level(ctx, l - 1, C.b, C.d, nu1, nu2));
@@ -507,9 +510,10 @@ vk_status ready(vk_ctx* ctx) {
 
 // The patch inversions fill every CU they may use, and the block inversions, one workgroup per
 // block and a long chain of short launches, are slowed down by them.  Their stream therefore
-// leaves 1/4 of the CUs (64 of 256) out of its mask: measured on the workloads here, 1/8 and
-// 1/4 both shorten the setup (1/4 slightly more), 1/16 and 1/32 do not.  Without CU masking
-// the patch inversions stay on the caller's stream.
+// leaves 1/8 of the CUs (32 of 256) out of its mask: with the 3D coarse block factorised block by
+// block, the 3D setup measured 55.7 ms with 1/4 left out, 47.6 with 1/8 and with 1/16, and 56 ms
+// with all CUs (the chain then waits behind the patch inversions).  Without CU masking the patch
+// inversions stay on the caller's stream.
 // A stream restricted to the first n_cu - n_cu / leave_out CUs; null if CU masking is unavailable.
 // (One such stream per context: with a second one, measured here, the side stream's launches waited
 // for the whole patch inversion.)
@@ -531,7 +535,7 @@ hipStream_t create_masked_stream(int leave_out) {
   return st;
 }
 
-void create_setup_stream(vk_ctx* ctx) { ctx->setup = create_masked_stream(4); }
+void create_setup_stream(vk_ctx* ctx) { ctx->setup = create_masked_stream(8); }
 
 extern "C" {
 
@@ -900,6 +904,22 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
   std::vector<int> blevels;
   for (int l = 0; l < ctx->n_levels; ++l)
     if (ctx->lv[l].cb_rows.size() > 1) blevels.push_back(l);
+  // a single wide block goes through its block-tridiagonal structure where it has one (planned
+  // once per pattern and workspace, on the host: the pattern's level sets)
+  for (int l : blevels) {
+    vk_level& L = ctx->lv[l];
+    if (!L.bt.planned) {
+      const bool was = L.bt.active;
+      if (ctx->coarse_solver == 0) {
+        VK_TRY(hipStreamSynchronize(ctx->side));  // the last setup's factorisation still reads the buffers
+        (void)vk_bt_plan(L);
+      } else {
+        L.bt = vk_bt();
+        L.bt.planned = true;
+      }
+      if (L.bt.active || was) ++ctx->gen;
+    }
+  }
   std::stable_sort(blevels.begin(), blevels.end(),
                    [&](int a, int b) { return ctx->lv[a].cb_max > ctx->lv[b].cb_max; });
   ctx->n_xside = 0;
@@ -926,7 +946,8 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
     {
       Timed t(ctx, VK_KERNEL_BLOCK_INVERT, blevels[k], st);
       // the level with the largest blocks (the longest chain) gets the look-ahead stream
-      VK_TRY(launch_block_invert(st, L, ctx->status, &L.cb_W, k == 0 ? &ctx->la : nullptr, ctx->coarse_min_tourney));
+      if (L.bt.active) VK_TRY(launch_bt_factor(st, L, ctx->status));
+      else VK_TRY(launch_block_invert(st, L, ctx->status, &L.cb_W, k == 0 ? &ctx->la : nullptr, ctx->coarse_min_tourney));
     }
     if (k > 0) {
       VK_TRY(hipEventRecord(ctx->xjoin[k - 1], st));
@@ -1270,6 +1291,10 @@ vk_status vk_get_patch_inverses(vk_ctx* ctx, int32_t l, int32_t cell0, int32_t n
 vk_status vk_get_coarse_inverse(vk_ctx* ctx, double* out) {
   VK_CHECK(ready(ctx));
   if (!out) return fail(ctx, VK_ERR_ARG, "null output");
+  if (ctx->lv[0].bt.active)
+    return fail(ctx, VK_ERR_STATE,
+                "the coarsest level is factorised block by block, not inverted (vk_set_coarse_solver 1 keeps the "
+                "dense inverse)");
   VK_CHECK(coarse_wait(ctx, true));
   VK_TRY(launch_block_export(ctx->stream, ctx->lv[0], 0, out));
   return VK_OK;
@@ -1427,6 +1452,36 @@ vk_status vk_set_setup_variant(vk_ctx* ctx, int32_t variant) {
   ctx->mfma_setup = variant == 0;
   ctx->setup_done = false;
   return VK_OK;
+}
+
+vk_status vk_set_coarse_solver(vk_ctx* ctx, int32_t mode) {
+  if (!ctx) return VK_ERR_ARG;
+  if (mode != 0 && mode != 1) return fail(ctx, VK_ERR_ARG, "unknown coarse solver");
+  if (mode != ctx->coarse_solver) {
+    if (ctx->side) (void)hipStreamSynchronize(ctx->side);
+    for (vk_level& L : ctx->lv) L.bt.planned = false;
+  }
+  ctx->coarse_solver = mode;
+  ctx->setup_done = false;
+  return VK_OK;
+}
+
+int32_t vk_coarse_plan(vk_ctx* ctx, int32_t level, double* setup_flops) {
+  if (!ctx || level < 0 || level >= ctx->n_levels) return -1;
+  const vk_level& L = ctx->lv[level];
+  if (L.bt.active) {
+    if (setup_flops) *setup_flops = L.bt.flops;
+    return L.bt.nb;
+  }
+  if (setup_flops) {
+    double f = 0.0;
+    for (size_t b = 0; b + 1 < L.cb_rows.size(); ++b) {
+      const double m = (double)(L.cb_rows[b + 1] - L.cb_rows[b]);
+      f += 2.0 * m * m * m;
+    }
+    *setup_flops = f;
+  }
+  return 0;
 }
 
 vk_status vk_set_coarse_pivoting(vk_ctx* ctx, int32_t mode) {

@@ -788,7 +788,7 @@ hipError_t launch_block_invert(hipStream_t s, const vk_level& L, int32_t* status
   if (m > min_tourney) {
     // proposals: TP per TL rows, at most one per thread of the final round
     if ((m + TL - 1) / TL * TP > 64 * TRW || L.cb_cand_stride < (m + TL - 1) / TL * TP) return hipErrorInvalidValue;
-    return wide ? run_blocked<256, 1, TP, 128, true>(s, L, status, -1, la)
+    return wide ? run_blocked<256, 1, TP, VK_TOURNEY_NBO, true>(s, L, status, -1, la)
                 : run_blocked<256, 1, TP, 64, true>(s, L, status, -1, la);
   }
   if (m <= 1024)
@@ -802,6 +802,19 @@ hipError_t launch_block_invert(hipStream_t s, const vk_level& L, int32_t* status
   else
     e = wide ? run_blocked<1024, 9, 4, 128>(s, L, status, -1, la) : run_blocked<1024, 9, 4, 64>(s, L, status, -1, la);
   return e;
+}
+
+hipError_t launch_block_invert_dense_any(hipStream_t s, const vk_level& L, int32_t* status) {
+  const int nbk = (int)L.cb_rows.size() - 1;
+  if (nbk <= 0) return hipSuccess;
+  const hipError_t e = launch_fill_i32(s, L.cb_rows[nbk] - L.cb_rows[0], 0, L.cb_used);
+  if (e != hipSuccess) return e;
+  const int64_t m = L.cb_max;
+  if (m <= 1024) return run_blocked<512, 2, 16, 128>(s, L, status);
+  if (m <= 2048) return run_blocked<256, 8, 8, 128>(s, L, status);
+  if (m <= 4096) return run_blocked<512, 8, 8, 128>(s, L, status);
+  if (m <= 8192) return run_blocked<1024, 8, 4, 128>(s, L, status);
+  return run_blocked<1024, 9, 4, 128>(s, L, status);
 }
 
 hipError_t launch_blocks_invert_dense(hipStream_t s, const vk_level& L, int32_t* status, int32_t bad_base) {

@@ -19,7 +19,11 @@
 #define VK_MAX_NK 512
 #define VK_MAX_RESTART 64
 // blocked Gauss-Jordan of the directly solved blocks: outer block width, widest inner panel
-#define VK_GJ_NBO 128  // widest outer block of the blocked Gauss-Jordan inversion (buffer sizes)
+#define VK_GJ_NBO 256  // widest outer block of the blocked Gauss-Jordan inversion (buffer sizes)
+// outer block width with tournament panels on levels of a few blocks: each outer pass reads and
+// writes the whole block once, so wider outer blocks halve those passes (3D coarse inversion
+// 85.8 -> 81.0 ms beside the patch inversions, 128 -> 256)
+#define VK_TOURNEY_NBO 256
 #define VK_GJ_NBI_MAX 16
 // blocks wider than this choose their pivots by tournament by default (below it the single-workgroup
 // panels, which run a level's blocks side by side, are as fast)
@@ -105,6 +109,24 @@ struct vk_blocked_ws {
   int64_t* woff = nullptr;    // blocks_cap dense-matrix offsets
 };
 
+// Block-tridiagonal factorisation of a level's single wide directly solved block (coarse_bt.hip):
+// the plan (level-set blocks, permutation) is made once per pattern and workspace; the buffers are
+// carved from the level's dense-inverse buffer.
+#define VK_BT_MIN_BLOCK 256   // consecutive level sets are grouped into blocks of at least this size
+#define VK_BT_MAX_BLOCK 2048  // widest block the factorisation accepts
+struct vk_bt {
+  bool planned = false;  // a plan was attempted for the current pattern and workspace
+  bool active = false;   // the block is solved through the factorisation
+  int nb = 0;
+  int64_t smax = 0;
+  double flops = 0.0;                     // algorithmic flop count of one factorisation
+  std::vector<int64_t> off, oD, oU, oL;   // block offsets (new order); element offsets of D_i, U_i, L_i
+  double *D = nullptr, *Dinv = nullptr, *U = nullptr, *X = nullptr, *Lc = nullptr;
+  double *bp = nullptr, *y = nullptr, *xp = nullptr, *w = nullptr;  // solve vectors
+  int32_t *perm = nullptr, *iperm = nullptr;                         // new -> old, old -> new
+  int64_t *d_off = nullptr, *d_oD = nullptr, *d_oU = nullptr, *d_oL = nullptr, *d_rows = nullptr;
+};
+
 struct vk_level {
   bool set = false;
   vk_csr J{}, P{}, R{};
@@ -139,6 +161,7 @@ struct vk_level {
   int64_t cb_cand_stride = 0;
   double* cb_prs = nullptr;
   int32_t* cb_pq = nullptr;
+  vk_bt bt;
 };
 
 // A second stream for the look-ahead of the blocked inversion: after each outer block of columns
@@ -197,6 +220,7 @@ struct vk_ctx {
   bool fast_setup = true;     // register-resident patch inversion where compiled
   bool mfma_setup = true;     // the matrix-core kernel where one is compiled for the patch width
   int64_t coarse_min_tourney = VK_TOURNEY_MIN_N;  // blocks wider than this choose pivots by tournament
+  int32_t coarse_solver = 0;  // 0: block-tridiagonal factorisation where it applies, 1: dense inverse
   bool maps_ready = false;    // multiplicities and DoF lists (depend on the mesh only)
   // the block inversions of the last setup run on `side`; the first call that applies a
   // block makes `stream` wait for them, and the first synchronisation after that checks
@@ -301,6 +325,15 @@ hipError_t launch_block_invert(hipStream_t s, const vk_level& L, int32_t* status
 // matrices are already in L.cb_a; a failing pivot sets status[0] to min(bad_base + block).
 hipError_t launch_blocks_invert_dense(hipStream_t s, const vk_level& L, int32_t* status, int32_t bad_base);
 hipError_t launch_block_apply(hipStream_t s, const vk_level& L, const double* x, double* y);
+// Gauss-Jordan inversion of L's blocks whose dense column-major matrices are already in L.cb_a
+// (any width up to vk_coarse_max_n(), partial pivoting over all rows); status[0] = -1 on failure.
+hipError_t launch_block_invert_dense_any(hipStream_t s, const vk_level& L, int32_t* status);
+// block-tridiagonal factorisation of a single wide block (coarse_bt.hip): plan (host, once per
+// pattern and workspace; false: the block is not suited and stays with the dense inverse),
+// factorisation (every setup) and solve x = J^{-1} b on the block's rows
+bool vk_bt_plan(vk_level& L);
+hipError_t launch_bt_factor(hipStream_t s, const vk_level& L, int32_t* status);
+hipError_t launch_bt_solve(hipStream_t s, const vk_level& L, const double* b, double* x);
 hipError_t launch_block_export(hipStream_t s, const vk_level& L, int32_t block, double* out);
 // Krylov
 hipError_t launch_dot(hipStream_t s, int64_t n, const double* x, const double* y, double* partial,

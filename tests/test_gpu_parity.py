@@ -507,12 +507,13 @@ def test_autotuned_matches_oracle(vk):
     assert rel(x.cpu().numpy(), oracle.vcycle(H, b, 2, 2)) <= 1e-10
 
 
-@pytest.mark.parametrize("pivoting", [0, 1])
-def test_coarse_solve_3d_box_size(vk, pivoting):
+@pytest.mark.parametrize("solver, pivoting", [(0, 0), (1, 0), (1, 1)])
+def test_coarse_solve_3d_box_size(vk, solver, pivoting):
     """The 3D box's coarsest level (25 x 2 x 2 hexahedra, dG(1), n = 8 450, the largest directly
     solved block) on its own: the one-level V-cycle is the direct solve; it agrees with a sparse
-    LU solve and leaves a residual at rounding level, with the pivots chosen by tournament (0) and
-    by partial pivoting over all rows (1)."""
+    LU solve and leaves a residual at rounding level, through the block-tridiagonal factorisation
+    (solver 0: level-set blocks) and through the dense inverse with the pivots chosen by tournament
+    (pivoting 0) and by partial pivoting over all rows (1)."""
     import time
     import scipy.sparse.linalg as spla
     from synth.assemble import assemble_jacobian
@@ -525,13 +526,19 @@ def test_coarse_solve_3d_box_size(vk, pivoting):
     lv = Level(mesh=m, J=J, P=None, R=None, cell_dofs=m.cell_dofs(), colours=m.colours(), state=V)
     S = vk.Solver([vk.upload_level(lv, DEV)])
     S.vk_set_workspace("f64", 30, device=DEV)
+    S.vk_set_coarse_solver(solver)
     S.vk_set_coarse_pivoting(pivoting)
-    _say(f"coarse 8450 setup, pivoting {pivoting}")
+    _say(f"coarse 8450 setup, solver {solver}, pivoting {pivoting}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     S.vanka_setup(0.7, "additive")
     torch.cuda.synchronize()
     _say(f"coarse 8450 setup {1e3 * (time.perf_counter() - t0):.1f} ms")
+    nb, flops = S.vk_coarse_plan(0)
+    if solver == 0:
+        assert nb >= 3 and flops < 2.0 * 8450.0 ** 3 / 10  # level-set blocks, a fraction of the dense flops
+    else:
+        assert nb == 0 and flops == 2.0 * 8450.0 ** 3
     b = np.random.default_rng(7).standard_normal(J.shape[0])
     x = torch.empty(J.shape[0], dtype=torch.float64, device=DEV)
     S.vcycle(t(b), x, 0, 0)
@@ -564,6 +571,69 @@ def test_coarse_inverse_with_tied_pivots(vk, n, pivoting):
     # H is orthogonal up to the factor n (condition number 1): a wrong or inconsistent pivot choice
     # shows as an O(1) error or a singular-block report, rounding stays far below this bound
     assert rel(out.cpu().numpy(), H.T / n) <= 1e-10
+    S.close()
+
+
+def _channel_coarse_level(shape=(44, 8), singular_row=None):
+    """One level of the 2D channel (k = 1) as a directly solved block: n = 8 164 on 44 x 8 cells."""
+    from synth.assemble import assemble_jacobian
+    from synth.mesh import StructuredMesh
+    from synth.problems import Level, inflow_state, H_CHANNEL
+    m = StructuredMesh(shape, (2.2, H_CHANNEL), 1)
+    V = inflow_state(m, 0.3, np.random.default_rng(1003))
+    J = assemble_jacobian(m, V, 1e-3, 0.01).tocsr()
+    if singular_row is not None:
+        J.data[J.indptr[singular_row]:J.indptr[singular_row + 1]] = 0.0
+    return Level(mesh=m, J=J, P=None, R=None, cell_dofs=m.cell_dofs(), colours=m.colours(), state=V)
+
+
+@pytest.mark.parametrize("solver", [0, 1])
+def test_block_tridiagonal_coarse_solve_2d(vk, solver):
+    """The 44 x 8 channel (n = 8 164) as the coarsest level: its level sets along the channel make a
+    block-tridiagonal factorisation (solver 0); the direct solve agrees with a sparse LU solve and
+    with the dense inverse's solve (solver 1) to rounding."""
+    import scipy.sparse.linalg as spla
+    lv = _channel_coarse_level()
+    J = lv.J
+    S = vk.Solver([vk.upload_level(lv, DEV)])
+    S.vk_set_workspace("f64", 30, device=DEV)
+    S.vk_set_coarse_solver(solver)
+    S.vanka_setup(0.7, "additive")
+    nb, _ = S.vk_coarse_plan(0)
+    assert (nb >= 3) if solver == 0 else (nb == 0)
+    b = np.random.default_rng(11).standard_normal(J.shape[0])
+    x = torch.empty(J.shape[0], dtype=torch.float64, device=DEV)
+    for rep in range(2):  # a second setup and solve reuse the plan
+        S.vcycle(t(b), x, 0, 0)
+        xs = spla.spsolve(J.tocsc(), b)
+        assert np.linalg.norm(x.cpu().numpy() - xs) <= 1e-9 * np.linalg.norm(xs), rep
+        S.vanka_setup(0.7, "additive")
+    if solver == 0:
+        with pytest.raises(vk.VkError, match="factorised"):
+            S.vk_get_coarse_inverse(torch.empty((J.shape[0], J.shape[0]), dtype=torch.float64, device=DEV))
+    S.close()
+
+
+def test_block_tridiagonal_singular_reported(vk):
+    """A zero row in the 44 x 8 channel's matrix: a Schur-complement block of the factorisation has no
+    nonzero pivot left, and the first solve reports the coarse block as singular."""
+    lv = _channel_coarse_level(singular_row=1234)
+    S = vk.Solver([vk.upload_level(lv, DEV)])
+    S.vk_set_workspace("f64", 30, device=DEV)
+    S.vanka_setup(0.7, "additive")
+    assert S.vk_coarse_plan(0)[0] >= 3
+    b = t(np.ones(lv.J.shape[0]))
+    x = torch.zeros_like(b)
+    with pytest.raises(vk.VkError, match="singular"):
+        S.vcycle(b, x, 0, 0)
+    S.close()
+
+
+def test_coarse_solver_mode_rejected(vk):
+    P, _ = problem("cfg0")
+    S = make_solver(vk, P)
+    with pytest.raises(vk.VkError, match="coarse solver"):
+        S.vk_set_coarse_solver(2)
     S.close()
 
 
