@@ -277,6 +277,26 @@ vk_status vk_set_setup_variant(vk_ctx* ctx, int32_t variant);
  * panel has no nonzero pivot.  Setup must run again after a change. */
 vk_status vk_set_coarse_pivoting(vk_ctx* ctx, int32_t mode);
 
+/* Storage read by the products with a level's J (the sweeps' defects r = b - J d,
+ * the V-cycle residuals and GMRES's J z; Sec. 3).  1 (default): on levels with at
+ * least 4 Mi nonzeros, a grouped CSR planned on the host at the first vanka_setup
+ * after vk_set_level or vk_set_workspace: up to four consecutive rows whose
+ * columns agree entry by entry up to a shift of 0 or 1 per entry (the velocity
+ * components of one node, the pressure modes of one cell) share one column
+ * list, so one 4-byte column word serves up to four 8-byte values; the values
+ * are J's CSR values as given.  The autotuner then times it against CSR.
+ * 0: CSR everywhere.  Both compute the same products up to summation order. */
+vk_status vk_set_spmv_format(vk_ctx* ctx, int32_t grouped);
+
+/* 0 if level `level`'s J products use CSR, else the lanes per row group of the
+ * grouped CSR in use; -1 for an invalid call. */
+int32_t vk_spmv_format(vk_ctx* ctx, int32_t level);
+
+/* The algorithmic bytes of one product with level `level`'s J in the storage in
+ * use: CSR 12 nnz + 8 (n + 1) + 24 n; grouped CSR 8 nnz + 4 (column words) +
+ * 28 per group + 24 n (x, z read, y written once).  -1 for an invalid call. */
+double vk_spmv_bytes(vk_ctx* ctx, int32_t level);
+
 /* Direct solver of a level whose directly solved rows form one block wider
  * than 4096 unknowns (the coarsest level's direct solve, Sec. 3).  0 (default):
  * where the block's sparsity allows it, a block-tridiagonal factorisation:

@@ -72,6 +72,9 @@ _SIGS = {
     "vk_set_setup_variant": (ctypes.c_int, [_P, _I32]),
     "vk_set_coarse_pivoting": (ctypes.c_int, [_P, _I32]),
     "vk_set_coarse_solver": (ctypes.c_int, [_P, _I32]),
+    "vk_set_spmv_format": (ctypes.c_int, [_P, _I32]),
+    "vk_spmv_format": (ctypes.c_int, [_P, _I32]),
+    "vk_spmv_bytes": (ctypes.c_double, [_P, _I32]),
     "vk_coarse_plan": (ctypes.c_int, [_P, _I32, _PD]),
     "vk_autotune": (ctypes.c_int, [_P, _I32]),
     "vk_set_graphs": (ctypes.c_int, [_P, _I32]),
@@ -343,6 +346,24 @@ class Solver:
         """0: tournament pivoting for blocks wider than 4096 rows; 1: partial pivoting over all rows;
         2: the tournament for every block."""
         self._check(_lib.vk_set_coarse_pivoting(self.ctx, mode))
+
+    def vk_set_spmv_format(self, grouped):
+        """1: grouped CSR for the J products of large levels (default); 0: CSR everywhere."""
+        self._check(_lib.vk_set_spmv_format(self.ctx, 1 if grouped else 0))
+
+    def vk_spmv_format(self, level):
+        """0: CSR; otherwise the lanes per row group of the grouped CSR in use on that level."""
+        v = _lib.vk_spmv_format(self.ctx, level)
+        if v < 0:
+            raise VkError(VK_ERR_ARG, "invalid level")
+        return int(v)
+
+    def vk_spmv_bytes(self, level):
+        """Algorithmic bytes of one product with level `level`'s J in the storage in use."""
+        v = _lib.vk_spmv_bytes(self.ctx, level)
+        if v < 0:
+            raise VkError(VK_ERR_ARG, "invalid level")
+        return float(v)
 
     def vk_set_coarse_solver(self, mode):
         """0: block-tridiagonal factorisation of a wide coarse block where its pattern allows; 1: dense inverse."""

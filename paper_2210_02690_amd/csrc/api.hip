@@ -121,6 +121,15 @@ size_t plan_workspace(vk_ctx* ctx, vk_prec prec, int32_t restart, char* base) {
     L.b = cv.take<double>(n);
     L.d = cv.take<double>(n);
     L.r = cv.take<double>(n);
+    L.gJ = vk_gcsr();  // a grouped-CSR plan lives in this workspace: made again for the new one
+    L.use_gJ = false;
+    if (L.J.nnz >= VK_GCSR_MIN_NNZ) {
+      L.gJ.cap_words = L.J.nnz / VK_GCSR_MAX_FRAC;
+      L.gJ.cap_groups = n;
+      L.gJ.gcol = cv.take<uint32_t>(L.gJ.cap_words);
+      L.gJ.g_row = cv.take<int32_t>(n + 1);
+      L.gJ.g_coff = cv.take<int64_t>(n + 1);
+    }
     if (!L.groups.empty()) {
       L.inv_p = cv.take<double>(n);
       L.dof_off = cv.take<int32_t>(n + 1);
@@ -290,7 +299,7 @@ vk_status smooth_with(vk_ctx* ctx, int l, const double* b, double* d, int32_t sw
       Timed tsw(ctx, VK_KERNEL_SWEEP, (it == 0 && zero) ? -2 : l);
       if (!(it == 0 && zero)) {
         Timed t(ctx, VK_KERNEL_SPMV, l);
-        VK_TRY(launch_spmv(s, L.J, L.lpr_J, -1.0, d, 1.0, b, buf.r));
+        VK_TRY(launch_spmv_J(s, L, -1.0, d, 1.0, b, buf.r));
         r = buf.r;
       }
       if (gather) {
@@ -346,7 +355,7 @@ vk_status vcycle_level(vk_ctx* ctx, int l, const double* b, double* x, int32_t n
   if (ctx->coarse_pending && L.cb_rows.size() > 1) VK_CHECK(coarse_wait(ctx, false));
   if (L.bt.active) VK_TRY(launch_bt_solve(s, L, b, x));
   else VK_TRY(launch_block_apply(s, L, b, x));
-  VK_TRY(launch_spmv(s, L.J, L.lpr_J, -1.0, x, 1.0, b, L.r));
+  VK_TRY(launch_spmv_J(s, L, -1.0, x, 1.0, b, L.r));
   VK_TRY(launch_spmv(s, L.R, L.lpr_R, 1.0, L.r, 0.0, nullptr, C.b));
   VK_CHECK(vcycle_level(ctx, l - 1, C.b, C.d, nu1, nu2));
   VK_TRY(launch_spmv(s, L.P, L.lpr_P, 1.0, C.d, 1.0, x, x));
@@ -904,6 +913,20 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
   std::vector<int> blevels;
   for (int l = 0; l < ctx->n_levels; ++l)
     if (ctx->lv[l].cb_rows.size() > 1) blevels.push_back(l);
+  // grouped CSR for the large levels' J (planned once per pattern and workspace, on the host)
+  for (int l = 0; l < ctx->n_levels; ++l) {
+    vk_level& L = ctx->lv[l];
+    if (!L.gJ.planned && L.gJ.gcol) {
+      VK_TRY(hipStreamSynchronize(s));  // the last solve may still read the old plan
+      if (vk_gcsr_plan(L)) {
+        L.use_gJ = ctx->spmv_grouped;
+        L.lpr_gJ = vk_pick_lpr_g(L.J.nnz, L.J.n_rows);
+      } else {
+        L.use_gJ = false;
+      }
+      ++ctx->gen;
+    }
+  }
   // a single wide block goes through its block-tridiagonal structure where it has one (planned
   // once per pattern and workspace, on the host: the pattern's level sets)
   for (int l : blevels) {
@@ -1063,7 +1086,7 @@ vk_status gmres_solve(vk_ctx* ctx, const double* b, double* x, int32_t restart, 
   double r_start = 0.0, r_last = 0.0;  // residual estimates: at the first restart's start, latest
   for (;;) {
     double* V0 = ctx->V;
-    VK_TRY(launch_spmv(s, F.J, F.lpr_J, -1.0, x, 1.0, b, V0));
+    VK_TRY(launch_spmv_J(s, F, -1.0, x, 1.0, b, V0));
     VK_TRY(launch_dot(s, n, V0, V0, ctx->partial, ctx->n_partial, sc + 1, true));
     VK_CHECK(read_scalars(ctx, sc + 1, 1, hb));
     beta = hb[0];
@@ -1101,7 +1124,7 @@ vk_status gmres_solve(vk_ctx* ctx, const double* b, double* x, int32_t restart, 
         auto step = [&]() -> vk_status {
           hipStream_t qs = ctx->stream;
           VK_CHECK(vcycle_level(ctx, L, Vj, Zj, nu_pre, nu_post));
-          VK_TRY(launch_spmv(qs, F.J, F.lpr_J, 1.0, Zj, 0.0, nullptr, Vn));
+          VK_TRY(launch_spmv_J(qs, F, 1.0, Zj, 0.0, nullptr, Vn));
           // classical Gram-Schmidt, applied twice
           VK_TRY(launch_mdot(qs, n, ctx->V, ldv, jj + 1, Vn, ctx->partial, ctx->n_partial, Hc));
           VK_TRY(launch_maxpy(qs, n, ctx->V, ldv, jj + 1, Hc, -1.0, Vn));
@@ -1186,7 +1209,7 @@ vk_status gmres_solve_batched(vk_ctx* ctx, const double* b, double* x, int32_t r
   int32_t done_steps = 0;  // Arnoldi steps over all cycles (every system starts at step 0)
   for (;;) {
     double* V0 = ctx->V;
-    VK_TRY(launch_spmv(s, F.J, F.lpr_J, -1.0, x, 1.0, b, V0));
+    VK_TRY(launch_spmv_J(s, F, -1.0, x, 1.0, b, V0));
     VK_TRY(launch_seg_dot(s, ns, seg, max_len, V0, V0, ctx->partial, ctx->n_partial, beta, true));
     VK_TRY(launch_seg_init(s, ns, m, ctx->H, ctx->g, beta, tol, its, max_iter, active, jn));
     VK_CHECK(to_host(ctx, hi.data(), active, sizeof(int32_t) * ns));
@@ -1214,7 +1237,7 @@ vk_status gmres_solve_batched(vk_ctx* ctx, const double* b, double* x, int32_t r
         auto step = [&]() -> vk_status {
           hipStream_t q = ctx->stream;
           VK_CHECK(vcycle_level(ctx, L, Vj, Zj, nu_pre, nu_post));
-          VK_TRY(launch_spmv(q, F.J, F.lpr_J, 1.0, Zj, 0.0, nullptr, Vn));
+          VK_TRY(launch_spmv_J(q, F, 1.0, Zj, 0.0, nullptr, Vn));
           VK_TRY(launch_seg_mdot(q, ns, seg, max_len, ctx->V, ldv, jj + 1, Vn, ctx->partial, ctx->n_partial, Hc,
                                  (int32_t)hs));
           VK_TRY(launch_seg_maxpy(q, ns, seg, max_len, ctx->V, ldv, jj + 1, Hc, (int32_t)hs, nullptr, -1.0, Vn));
@@ -1254,7 +1277,7 @@ vk_status gmres_solve_batched(vk_ctx* ctx, const double* b, double* x, int32_t r
     VK_TRY(launch_seg_maxpy(s, ns, seg, max_len, ctx->Z, ldv, j_end, ctx->y, m, nullptr, 1.0, x));
   }
   // final true residuals
-  VK_TRY(launch_spmv(s, F.J, F.lpr_J, -1.0, x, 1.0, b, ctx->V));
+  VK_TRY(launch_spmv_J(s, F, -1.0, x, 1.0, b, ctx->V));
   VK_TRY(launch_seg_dot(s, ns, seg, max_len, ctx->V, ctx->V, ctx->partial, ctx->n_partial, beta, true));
   VK_CHECK(to_host(ctx, hb.data(), beta, sizeof(double) * ns));
   VK_CHECK(to_host(ctx, iters, its, sizeof(int32_t) * ns));
@@ -1274,7 +1297,7 @@ vk_status vk_spmv(vk_ctx* ctx, int32_t l, double alpha, const double* x, double 
   if (!x || !y || (beta != 0.0 && !z)) return fail(ctx, VK_ERR_ARG, "null vector");
   if (x == y) return fail(ctx, VK_ERR_ARG, "x must not alias y");
   const vk_level& L = ctx->lv[l];
-  VK_TRY(launch_spmv(ctx->stream, L.J, L.lpr_J, alpha, x, beta, z, y));
+  VK_TRY(launch_spmv_J(ctx->stream, L, alpha, x, beta, z, y));
   return VK_OK;
 }
 
@@ -1356,6 +1379,18 @@ vk_status vk_autotune(vk_ctx* ctx, int32_t reps) {
       return best;
     };
     L.lpr_J = tune_csr(L.J, L.b, L.r);
+    if (L.gJ.active && ctx->spmv_grouped) {  // the grouped format against the best CSR launch
+      float tb = time_ms([&] { return launch_spmv(s, L.J, L.lpr_J, 1.0, L.b, 0.0, nullptr, L.r); });
+      L.use_gJ = false;
+      for (int lpr : {8, 16, 32, 64}) {
+        const float t = time_ms([&] { return launch_spmv_g(s, L.J, L.gJ, lpr, 1.0, L.b, 0.0, nullptr, L.r); });
+        if (t < tb) {
+          tb = t;
+          L.use_gJ = true;
+          L.lpr_gJ = lpr;
+        }
+      }
+    }
     if (l == 0) continue;
     vk_level& C = ctx->lv[l - 1];
     VK_TRY(launch_fill(s, C.J.n_rows, 1.0, C.b));
@@ -1452,6 +1487,39 @@ vk_status vk_set_setup_variant(vk_ctx* ctx, int32_t variant) {
   ctx->mfma_setup = variant == 0;
   ctx->setup_done = false;
   return VK_OK;
+}
+
+vk_status vk_set_spmv_format(vk_ctx* ctx, int32_t grouped) {
+  if (!ctx) return VK_ERR_ARG;
+  if (grouped != 0 && grouped != 1) return fail(ctx, VK_ERR_ARG, "grouped must be 0 or 1");
+  ++ctx->gen;
+  ctx->spmv_grouped = grouped != 0;
+  for (vk_level& L : ctx->lv) L.use_gJ = ctx->spmv_grouped && L.gJ.active;
+  return VK_OK;
+}
+
+double vk_spmv_bytes(vk_ctx* ctx, int32_t level) {
+  if (!ctx || level < 0 || level >= ctx->n_levels) return -1.0;
+  const vk_level& L = ctx->lv[level];
+  const double n = (double)L.J.n_rows, nnz = (double)L.J.nnz;
+  if (L.use_gJ && L.gJ.active) {
+    int64_t words = 0;
+    if (hipMemcpy(&words, L.gJ.g_coff + L.gJ.n_groups, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess) {
+      (void)hipGetLastError();
+      return -1.0;
+    }
+    const double ng = (double)L.gJ.n_groups;
+    // values, column words, per group its first row, column offset and two row pointers; x, z read,
+    // y written
+    return 8.0 * nnz + 4.0 * (double)words + ng * (4.0 + 8.0 + 16.0) + 24.0 * n;
+  }
+  return 12.0 * nnz + 8.0 * (n + 1.0) + 24.0 * n;
+}
+
+int32_t vk_spmv_format(vk_ctx* ctx, int32_t level) {
+  if (!ctx || level < 0 || level >= ctx->n_levels) return -1;
+  const vk_level& L = ctx->lv[level];
+  return L.use_gJ && L.gJ.active ? L.lpr_gJ : 0;
 }
 
 vk_status vk_set_coarse_solver(vk_ctx* ctx, int32_t mode) {

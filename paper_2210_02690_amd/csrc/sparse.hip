@@ -56,6 +56,56 @@ __global__ __launch_bounds__(256) void spmv_kernel(int64_t n_rows, const int64_t
   }
 }
 
+// Grouped CSR (gcsr): g_row[g] .. g_row[g + 1] - 1 are G <= 4 consecutive rows of equal length m
+// whose columns agree entry by entry up to a shift, col[r + c][j] = col[r][j] + c d_j with d_j in
+// {0, 1} (in a dG slab matrix: the velocity components of one node, or the pressure modes of one
+// cell).  The group's column list is stored once, gcol[g_coff[g] + j] = col[r][j] | d_j << 31; the
+// values are the CSR values as they are (the rows are consecutive, so row r + c's entries start at
+// row_ptr[r] + c m).  LPR lanes per group, each takes entry j of all G rows: one 4-byte column word
+// serves G values.
+template <int LPR>
+__global__ __launch_bounds__(256) void spmv_g_kernel(int64_t n_groups, const int32_t* __restrict__ g_row,
+                                                     const int64_t* __restrict__ g_coff,
+                                                     const int64_t* __restrict__ row_ptr,
+                                                     const uint32_t* __restrict__ gcol,
+                                                     const double* __restrict__ val, const double* __restrict__ x,
+                                                     double alpha, double beta, const double* z, double* y) {
+  const int64_t gid = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const int64_t g = gid / LPR;
+  const int lane = threadIdx.x & (LPR - 1);
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t r = 0;
+  int G = 0;
+  if (g < n_groups) {
+    r = g_row[g];
+    G = g_row[g + 1] - (int)r;
+    const int64_t v0 = row_ptr[r], m = row_ptr[r + 1] - v0, c0 = g_coff[g];
+    const double* v = val + v0;
+    for (int64_t j = lane; j < m; j += LPR) {
+      const uint32_t cw = gcol[c0 + j];
+      const int64_t cb = (int64_t)(cw & 0x7fffffffu);
+      const int64_t d = (int64_t)(cw >> 31);
+      s0 = fma(v[j], x[cb], s0);
+      if (G > 1) s1 = fma(v[m + j], x[cb + d], s1);
+      if (G > 2) s2 = fma(v[2 * m + j], x[cb + 2 * d], s2);
+      if (G > 3) s3 = fma(v[3 * m + j], x[cb + 3 * d], s3);
+    }
+  }
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) {
+    s0 += __shfl_xor(s0, o, LPR);
+    s1 += __shfl_xor(s1, o, LPR);
+    s2 += __shfl_xor(s2, o, LPR);
+    s3 += __shfl_xor(s3, o, LPR);
+  }
+  if (g < n_groups && lane < G) {
+    const double sum = lane == 0 ? s0 : (lane == 1 ? s1 : (lane == 2 ? s2 : s3));
+    double out = alpha * sum;
+    if (beta != 0.0) out += beta * z[r + lane];
+    y[r + lane] = out;
+  }
+}
+
 __global__ void validate_csr_kernel(int64_t n_rows, int64_t n_cols, int64_t nnz,
                                     const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                                     int32_t* flag) {
@@ -146,6 +196,24 @@ hipError_t launch_spmv(hipStream_t s, const vk_csr& A, int lpr, double alpha, co
     case 32: spmv_kernel<32><<<grid, 256, 0, s>>>(A.n_rows, A.row_ptr, A.col, A.val, x, alpha, beta, z, y); break;
     default: spmv_kernel<64><<<grid, 256, 0, s>>>(A.n_rows, A.row_ptr, A.col, A.val, x, alpha, beta, z, y); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv_g(hipStream_t s, const vk_csr& A, const vk_gcsr& g, int lpr, double alpha, const double* x,
+                         double beta, const double* z, double* y) {
+  if (g.n_groups == 0) return hipSuccess;
+  const unsigned grid = grid_for(g.n_groups * lpr, 256);
+#define VK_SPMV_G(LL)                                                                                 \
+  spmv_g_kernel<LL><<<grid, 256, 0, s>>>(g.n_groups, g.g_row, g.g_coff, A.row_ptr, g.gcol, A.val, x, alpha, \
+                                        beta, z, y)
+  switch (lpr) {
+    case 4: VK_SPMV_G(4); break;
+    case 8: VK_SPMV_G(8); break;
+    case 16: VK_SPMV_G(16); break;
+    case 32: VK_SPMV_G(32); break;
+    default: VK_SPMV_G(64); break;
+  }
+#undef VK_SPMV_G
   return hipGetLastError();
 }
 

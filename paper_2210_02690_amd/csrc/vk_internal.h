@@ -109,6 +109,20 @@ struct vk_blocked_ws {
   int64_t* woff = nullptr;    // blocks_cap dense-matrix offsets
 };
 
+// Grouped CSR of a level's J (sparse.hip, spmv_g_kernel): planned on the host once per pattern and
+// workspace for levels with at least VK_GCSR_MIN_NNZ entries; the arrays live in workspace space
+// reserved for them (gcol at most VK_GCSR_MAX_FRAC of nnz; a pattern that needs more keeps CSR).
+#define VK_GCSR_MIN_NNZ (4 << 20)
+#define VK_GCSR_MAX_FRAC 2  // column words reserved: nnz / 2
+struct vk_gcsr {
+  bool planned = false, active = false;
+  int64_t n_groups = 0;
+  int64_t cap_words = 0, cap_groups = 0;  // reserved space
+  int32_t* g_row = nullptr;               // n_groups + 1 first rows
+  int64_t* g_coff = nullptr;              // n_groups + 1 column-list offsets
+  uint32_t* gcol = nullptr;               // column words
+};
+
 // Block-tridiagonal factorisation of a level's single wide directly solved block (coarse_bt.hip):
 // the plan (level-set blocks, permutation) is made once per pattern and workspace; the buffers are
 // carved from the level's dense-inverse buffer.
@@ -137,6 +151,9 @@ struct vk_level {
   int64_t cb_max = 0;               // largest block
   int64_t cb_sq = 0;                // sum of squared block sizes
   int lpr_J = 4, lpr_P = 4, lpr_R = 4;
+  vk_gcsr gJ;           // grouped CSR of J, used by the J products while gJ.active and use_gJ
+  bool use_gJ = false;
+  int lpr_gJ = 16;
   // carved from the workspace
   double* inv_p = nullptr;      // 1 / multiplicity
   int32_t* dof_off = nullptr;   // DoF -> (cell, local) lists: offsets (n + 1)
@@ -221,6 +238,7 @@ struct vk_ctx {
   bool mfma_setup = true;     // the matrix-core kernel where one is compiled for the patch width
   int64_t coarse_min_tourney = VK_TOURNEY_MIN_N;  // blocks wider than this choose pivots by tournament
   int32_t coarse_solver = 0;  // 0: block-tridiagonal factorisation where it applies, 1: dense inverse
+  bool spmv_grouped = true;   // J products through the grouped CSR where a plan exists
   bool maps_ready = false;    // multiplicities and DoF lists (depend on the mesh only)
   // the block inversions of the last setup run on `side`; the first call that applies a
   // block makes `stream` wait for them, and the first synchronisation after that checks
@@ -277,6 +295,14 @@ int vk_pick_lpr(int64_t n_rows, int64_t nnz);
 hipError_t launch_spmv(hipStream_t s, const vk_csr& A, int lpr, double alpha, const double* x,
                        double beta, const double* z, double* y);
 hipError_t launch_validate_csr(hipStream_t s, const vk_csr& A, int32_t* flag);
+hipError_t launch_spmv_g(hipStream_t s, const vk_csr& A, const vk_gcsr& g, int lpr, double alpha, const double* x,
+                         double beta, const double* z, double* y);
+// y = alpha J x + beta z with the level's chosen format (grouped CSR or CSR)
+hipError_t launch_spmv_J(hipStream_t s, const vk_level& L, double alpha, const double* x, double beta,
+                         const double* z, double* y);
+// plan the grouped CSR of L.J in the space reserved for it (host, once per pattern and workspace)
+bool vk_gcsr_plan(vk_level& L);
+int vk_pick_lpr_g(int64_t nnz, int64_t n_rows);
 hipError_t launch_validate_cells(hipStream_t s, int32_t n_cells, int32_t n_K, const int32_t* cell_dofs,
                                  int64_t n, const int32_t* colour_cells, int32_t* flag);
 hipError_t launch_fill(hipStream_t s, int64_t n, double v, double* x);

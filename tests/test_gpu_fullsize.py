@@ -88,6 +88,41 @@ def test_channel_176x32_k2_full(vk):
             S2.close()
 
 
+def test_grouped_csr_products_176x32(vk):
+    """The grouped CSR of the 176 x 32 channel's finest J (10.5 M nonzeros): the products y = J x and
+    y = z - J x equal scipy's CSR products and the library's own CSR products to rounding, on the
+    finest level and the next one."""
+    P = build_problem("channel2d_176x32_k2")
+    S = vk.Solver([vk.upload_level(L, DEV) for L in P.levels])
+    S.vk_set_workspace("f64", 30, device=DEV)
+    S.vanka_setup(0.7, "additive")
+    rng = np.random.default_rng(21)
+    for l in (len(P.levels) - 1, len(P.levels) - 2):
+        J = P.levels[l].J
+        if J.nnz < 4 << 20:
+            assert S.vk_spmv_format(l) == 0
+            continue
+        assert S.vk_spmv_format(l) > 0, l
+        x = rng.standard_normal(J.shape[0])
+        z = rng.standard_normal(J.shape[0])
+        xt = torch.from_numpy(x).to(DEV)
+        zt = torch.from_numpy(z).to(DEV)
+        y = torch.empty_like(xt)
+        S.vk_spmv(l, xt, y)
+        ref = J @ x
+        assert np.abs(y.cpu().numpy() - ref).max() <= 1e-13 * np.abs(ref).max()
+        S.vk_spmv(l, xt, y, alpha=-1.0, beta=1.0, z=zt)
+        ref2 = z - J @ x
+        assert np.abs(y.cpu().numpy() - ref2).max() <= 1e-13 * np.abs(ref2).max()
+        S.vk_set_spmv_format(0)
+        assert S.vk_spmv_format(l) == 0
+        y2 = torch.empty_like(xt)
+        S.vk_spmv(l, xt, y2)
+        assert np.abs(y2.cpu().numpy() - ref).max() <= 1e-13 * np.abs(ref).max()
+        S.vk_set_spmv_format(1)
+    S.close()
+
+
 def test_box3d_full_sampled(vk):
     _say("build box3d_100x16x16_k1")
     P = build_problem("box3d_100x16x16_k1")
