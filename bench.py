@@ -546,10 +546,18 @@ def measure(torch, vk, S, P, b, x, nu, restart, max_iter, steps, warmup, prec, l
         f"{avg['sweep']} ms, spmv {avg['spmv']} ms, gemv {avg['patch_gemv']} ms, setup {avg['patch_setup']} ms")
     bs = sweep_bytes(fine, prec)
     sweep_gbs = bs / (avg["sweep"] * 1e-3) / 1e9
+    # bytes the finest J actually occupies in the storage in use (grouped CSR shares column lists,
+    # so it moves less than the CSR figure the roofline is defined on)
+    lf = len(P.levels) - 1
+    stored = S.vk_spmv_bytes(lf)
+    lpr_g = S.vk_spmv_format(lf)
     kern = {
         "spmv": roofline_entry("hbm", spmv_bytes(fine) / (avg["spmv"] * 1e-3) / 1e9, HBM_PEAK_GBS, "GB/s",
                                bytes_per_launch=spmv_bytes(fine), avg_launch_ms=avg["spmv"],
-                               launches=live["spmv"][0]),
+                               launches=live["spmv"][0],
+                               storage=(f"grouped CSR, {lpr_g} lanes per group" if lpr_g else "CSR"),
+                               stored_bytes_per_launch=stored,
+                               stored_gbs=stored / (avg["spmv"] * 1e-3) / 1e9),
         "patch_gemv": roofline_entry("hbm", patch_gemv_bytes(fine, prec) / (avg["patch_gemv"] * 1e-3) / 1e9,
                                      HBM_PEAK_GBS, "GB/s", bytes_per_launch=patch_gemv_bytes(fine, prec),
                                      avg_launch_ms=avg["patch_gemv"], launches=live["patch_gemv"][0]),
@@ -590,7 +598,9 @@ def measure(torch, vk, S, P, b, x, nu, restart, max_iter, steps, warmup, prec, l
         "roofline": roofline_entry("hbm", sweep_gbs, HBM_PEAK_GBS, "GB/s",
                                    kernel="whole finest-level additive sweep with its defect (SpMV + patch GEMV "
                                           "+ DoF gather), bracketed by events as one unit",
-                                   traffic=traffic, bytes_per_sweep=bs, avg_sweep_ms=avg["sweep"],
+                                   traffic=traffic, bytes_per_sweep=bs,
+                                   stored_bytes_per_sweep=bs - spmv_bytes(fine) + stored,
+                                   avg_sweep_ms=avg["sweep"],
                                    sweeps=live["sweep"][0], kernels=kern),
         "finest_cell_sweeps_per_s": fine.mesh.n_cells / (avg["sweep"] * 1e-3),
     }

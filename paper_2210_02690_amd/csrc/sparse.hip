@@ -81,14 +81,34 @@ __global__ __launch_bounds__(256) void spmv_g_kernel(int64_t n_groups, const int
     G = g_row[g + 1] - (int)r;
     const int64_t v0 = row_ptr[r], m = row_ptr[r + 1] - v0, c0 = g_coff[g];
     const double* v = val + v0;
-    for (int64_t j = lane; j < m; j += LPR) {
-      const uint32_t cw = gcol[c0 + j];
-      const int64_t cb = (int64_t)(cw & 0x7fffffffu);
-      const int64_t d = (int64_t)(cw >> 31);
-      s0 = fma(v[j], x[cb], s0);
-      if (G > 1) s1 = fma(v[m + j], x[cb + d], s1);
-      if (G > 2) s2 = fma(v[2 * m + j], x[cb + 2 * d], s2);
-      if (G > 3) s3 = fma(v[3 * m + j], x[cb + 3 * d], s3);
+    int64_t j = lane;
+    // two entries per lane and iteration: 2 G value loads and gathers in flight
+    for (; j + LPR < m; j += 2 * LPR) {
+      const uint32_t ca = gcol[c0 + j], cc = gcol[c0 + j + LPR];
+      const int64_t ba = (int64_t)(ca & 0x7fffffffu), da = (int64_t)(ca >> 31);
+      const int64_t bb = (int64_t)(cc & 0x7fffffffu), db = (int64_t)(cc >> 31);
+      s0 = fma(v[j], x[ba], s0);
+      s0 = fma(v[j + LPR], x[bb], s0);
+      if (G > 1) {
+        s1 = fma(v[m + j], x[ba + da], s1);
+        s1 = fma(v[m + j + LPR], x[bb + db], s1);
+      }
+      if (G > 2) {
+        s2 = fma(v[2 * m + j], x[ba + 2 * da], s2);
+        s2 = fma(v[2 * m + j + LPR], x[bb + 2 * db], s2);
+      }
+      if (G > 3) {
+        s3 = fma(v[3 * m + j], x[ba + 3 * da], s3);
+        s3 = fma(v[3 * m + j + LPR], x[bb + 3 * db], s3);
+      }
+    }
+    if (j < m) {
+      const uint32_t ca = gcol[c0 + j];
+      const int64_t ba = (int64_t)(ca & 0x7fffffffu), da = (int64_t)(ca >> 31);
+      s0 = fma(v[j], x[ba], s0);
+      if (G > 1) s1 = fma(v[m + j], x[ba + da], s1);
+      if (G > 2) s2 = fma(v[2 * m + j], x[ba + 2 * da], s2);
+      if (G > 3) s3 = fma(v[3 * m + j], x[ba + 3 * da], s3);
     }
   }
 #pragma unroll
