@@ -10,6 +10,11 @@
  *   - The caller owns every array it passes (level matrices, transfer
  *     matrices, cell maps, workspace, vectors) and keeps them alive and
  *     unchanged until vk_destroy; the context stores the pointers, not copies.
+ *     The values of a level matrix may change between vanka_setup calls (a
+ *     new Newton linearisation); its structure (row pointers, columns) and the
+ *     cell maps may not, since setup keeps plans made from them (grouped CSR,
+ *     patch entry maps, the coarse block structure) until the next
+ *     vk_set_level or vk_set_workspace.
  *   - Apart from one 4 KiB status block and a 64 KiB pinned host staging
  *     buffer for small reads (both allocated by vk_create), the library
  *     allocates no memory: all scratch lives in the caller-provided workspace
@@ -162,7 +167,7 @@ vk_status vk_set_workspace(vk_ctx* ctx, void* dev, size_t bytes, vk_prec prec, i
  * under-relaxation of Eq. 3.4 (the paper uses 0.7).
  * On a zero pivot in a patch returns VK_ERR_SINGULAR with *bad_level /
  * *bad_cell (host, may be NULL) naming the first failing level and cell.
- * The patch inversions run on an internal stream restricted to 3/4 of the
+ * The patch inversions run on an internal stream restricted to 7/8 of the
  * CUs (when the runtime supports CU masks), which the context's stream waits
  * for; vanka_setup synchronises for them only.  The inversion of the
  * directly solved blocks (the coarse matrix) keeps running on a second internal
@@ -257,14 +262,18 @@ vk_status vk_set_sweep_variant(vk_ctx* ctx, int32_t variant);
 /* Patch inversion kernel used by vanka_setup: 0 (default) keeps the patch
  * matrix in registers where a kernel for the patch width is compiled: blocked
  * Gauss-Jordan on the FP64 matrix cores for n_K = 170 (16 x 16 tiles over a
- * 512-thread workgroup, rank-8 panel updates), one row per lane for n_K = 42,
- * 63, spread over a 512-thread workgroup with vector FP64 for n_K = 84, 85,
- * 105, 120, 180; inverts other patches wider than 88 (up to 512) with the
- * blocked kernels of the directly solved blocks, one block per cell, and the
- * rest in LDS; 1 always uses the LDS / global-memory kernel; 2 is 0 without
- * the matrix-core kernel (n_K = 170 on the vector unit).  All compute the
- * Gauss-Jordan inverse with the same partial pivoting; setup must run again
- * after a change. */
+ * 704-thread workgroup, rank-4 panel updates), its patches gathered through a
+ * patch entry map (per cell and patch entry the entry's offset in its CSR row,
+ * 2 bytes each, kept in the workspace and built at the first vanka_setup after
+ * vk_set_level or vk_set_workspace); one row per lane for n_K = 42, 63, spread
+ * over a 512-thread workgroup with vector FP64 for n_K = 84, 85, 105, 120,
+ * 180; inverts other patches wider than 88 (up to 512) with the blocked
+ * kernels of the directly solved blocks, one block per cell, and the rest in
+ * LDS; 1 always uses the LDS / global-memory kernel; 2 is 0 without the
+ * matrix-core kernel (n_K = 170 on the vector unit); 3 is 0 with the n_K = 170
+ * patches gathered by a search of their CSR rows instead of the map.  All
+ * compute the Gauss-Jordan inverse with the same partial pivoting; setup must
+ * run again after a change. */
 vk_status vk_set_setup_variant(vk_ctx* ctx, int32_t variant);
 
 /* Pivot choice of the directly solved blocks' Gauss-Jordan inversion (the

@@ -141,6 +141,10 @@ size_t plan_workspace(vk_ctx* ctx, vk_prec prec, int32_t restart, char* base) {
       G.ld = (int32_t)round_up(G.n_K, vw);
       G.cell_stride = (int64_t)G.n_K * G.ld;
       G.inv = cv.take<char>((int64_t)G.n_cells * G.cell_stride * sb);
+      // the patch entry map lives in this workspace: planned again for the new one
+      const int64_t me = vk_patch_map_elems(G.n_K);
+      G.pmap = me > 0 ? cv.take<uint16_t>((int64_t)G.n_cells * me) : nullptr;
+      G.pmap_ok = false;
       if (G.n_K > VK_LDS_SETUP_MAX_NK) {
         if (G.n_K > big_nk) big_nk = G.n_K;
         if (G.n_cells > big_cells) big_cells = G.n_cells;
@@ -872,10 +876,18 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
     VK_TRY(launch_fill_i32(ps, 64, 0, ctx->status + 600));
     for (int l = 1; l < ctx->n_levels; ++l)
       if (!ctx->lv[l].groups.empty()) VK_TRY(launch_dof_max_count(ps, ctx->lv[l], ctx->status + 600 + l));
+    // the patch entry maps of the matrix-core inversion (status words [800 + l]: a patch row of
+    // level l too long for 16-bit offsets)
+    VK_TRY(launch_fill_i32(ps, 64, 0, ctx->status + 800));
+    for (int l = 1; l < ctx->n_levels; ++l)
+      for (const vk_group& G : ctx->lv[l].groups) VK_TRY(launch_patch_map(ps, ctx->lv[l].J, G, ctx->status + 800 + l));
     VK_TRY(hipStreamSynchronize(ps));
-    int32_t mc[64], cc[64];
+    int32_t mc[64], cc[64], tl[64];
     VK_CHECK(to_host(ctx, mc, ctx->status + 600, sizeof(mc)));
     VK_CHECK(to_host(ctx, cc, ctx->status + 700, sizeof(cc)));
+    VK_CHECK(to_host(ctx, tl, ctx->status + 800, sizeof(tl)));
+    for (int l = 1; l < ctx->n_levels; ++l)
+      for (vk_group& G : ctx->lv[l].groups) G.pmap_ok = G.pmap != nullptr && tl[l] == 0;
     for (int l = 1; l < ctx->n_levels; ++l)
       if (cc[l] != 0)
         return fail(ctx, VK_ERR_ARG, "level " + std::to_string(l) +
@@ -892,7 +904,8 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
     for (const vk_group& G : L.groups) {
       bool handled = false;
       if (ctx->fast_setup)
-        VK_TRY(launch_patch_setup_fast(ps, L.J, G, ctx->prec, ctx->status + 64 + l, &handled, ctx->mfma_setup));
+        VK_TRY(launch_patch_setup_fast(ps, L.J, G, ctx->prec, ctx->status + 64 + l, &handled, ctx->mfma_setup,
+                                       ctx->patch_map));
       // wider than LDS and no register-resident kernel: the blocked kernels of the directly
       // solved blocks, one block per cell
       if (!handled && ctx->fast_setup && G.n_K > VK_LDS_SETUP_MAX_NK && G.n_K <= 512 && ctx->blocked.cap > 0) {
@@ -1482,9 +1495,10 @@ vk_status vk_set_sweep_variant(vk_ctx* ctx, int32_t variant) {
 
 vk_status vk_set_setup_variant(vk_ctx* ctx, int32_t variant) {
   if (!ctx) return VK_ERR_ARG;
-  if (variant < 0 || variant > 2) return fail(ctx, VK_ERR_ARG, "unknown setup variant");
+  if (variant < 0 || variant > 3) return fail(ctx, VK_ERR_ARG, "unknown setup variant");
   ctx->fast_setup = variant != 1;
-  ctx->mfma_setup = variant == 0;
+  ctx->mfma_setup = variant == 0 || variant == 3;
+  ctx->patch_map = variant == 0;
   ctx->setup_done = false;
   return VK_OK;
 }

@@ -1060,10 +1060,81 @@ template <int N> struct MfCfg {
   static constexpr int PLD = NB + 1;             // LDS row length of a panel (doubles)
 };
 
-template <int P, int N>
+// The patch entry map of the matrix-core kernel, planned once per pattern: for every cell and every
+// accumulator element of its T x T tiles (the layout above: tile (I, J), lane l, element v hold
+// patch row 16 I + 4 v + l / 16, column 16 J + l % 16), the offset of that entry in the row's CSR
+// entries, 0xFFFF where J stores none (and in the padding).  Stored as [cell][I][J][lane][v]
+// uint16, so a lane reads its four elements of one tile as one 8-byte word and a wavefront one
+// tile as 512 contiguous bytes.  One workgroup per cell builds the cell's map in LDS: the cell's
+// DoFs go into the LDS hash, every wavefront walks whole CSR rows (four loads per lane in flight)
+// and records the offsets of the columns it finds.
+__device__ __forceinline__ int patch_map_pos(int i, int j, int T) {
+  const int m = i & 15, n = j & 15;
+  return (((i >> 4) * T + (j >> 4)) * 64 + n + 16 * (m & 3)) * 4 + (m >> 2);
+}
+
+template <int N>
+__global__ __launch_bounds__(512) void patch_map_kernel(const int64_t* __restrict__ row_ptr,
+                                                        const int32_t* __restrict__ col,
+                                                        const int32_t* __restrict__ cell_dofs, uint64_t* pmap,
+                                                        int32_t* too_long) {
+  constexpr int T = MfCfg<N>::T, NT = 512, ME = T * T * 256;
+  __shared__ uint16_t sm[ME];
+  __shared__ int2 htab[PatchHash::SLOTS];
+  __shared__ int64_t rbeg[N];
+  __shared__ int rlen[N];
+  const int K = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int h = tid; h < PatchHash::SLOTS; h += NT) htab[h] = make_int2(-1, 0);
+  for (int e = tid; e < ME / 2; e += NT) reinterpret_cast<uint32_t*>(sm)[e] = 0xFFFFFFFFu;
+  __syncthreads();
+  if (tid < N) {
+    const int dof = cell_dofs[(int64_t)K * N + tid];
+    const int64_t b0 = row_ptr[dof];
+    const int64_t len = row_ptr[dof + 1] - b0;
+    rbeg[tid] = b0;
+    rlen[tid] = (int)(len < 65535 ? len : 65535);
+    if (len > 65535) atomicOr(too_long, 1);
+    PatchHash::insert(htab, dof, tid);
+  }
+  __syncthreads();
+  for (int i = wv; i < N; i += NT / 64) {
+    const int len = rlen[i];
+    const int32_t* cr = col + rbeg[i];
+    for (int e0 = 0; e0 < len; e0 += 256) {
+      int c[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = e0 + 64 * q + lane;
+        c[q] = e < len ? cr[e] : -1;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (c[q] < 0) continue;
+        int h = PatchHash::slot(c[q]);
+        int loc = -1;
+        for (int probe = 0; probe < PatchHash::SLOTS; ++probe) {  // the table has empty slots: ends
+          const int2 t = htab[h];
+          if (t.x == c[q]) {
+            loc = t.y;
+            break;
+          }
+          if (t.x == -1) break;
+          h = (h + 1) & (PatchHash::SLOTS - 1);
+        }
+        if (loc >= 0) sm[patch_map_pos(i, loc, T)] = (uint16_t)(e0 + 64 * q + lane);
+      }
+    }
+  }
+  __syncthreads();
+  uint64_t* out = pmap + (int64_t)K * (ME / 4);
+  for (int e = tid; e < ME / 4; e += NT) out[e] = reinterpret_cast<const uint64_t*>(sm)[e];
+}
+
+template <int P, int N, bool MAP>
 __global__ __launch_bounds__(MfCfg<N>::NT) void patch_setup_mfma_kernel(
     const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const double* __restrict__ val,
-    const int32_t* __restrict__ cell_dofs, void* inv_out, int32_t ld, int64_t cell_stride, int32_t* status) {
+    const int32_t* __restrict__ cell_dofs, const uint64_t* __restrict__ pmap, void* inv_out, int32_t ld,
+    int64_t cell_stride, int32_t* status) {
   using C = MfCfg<N>;
   constexpr int NP = C::NP, T = C::T, NT = C::NT, NB = C::NB, R = C::R, PW = C::PW, PLD = C::PLD;
   static_assert(R <= 4 && NP <= 256, "patch width");
@@ -1081,7 +1152,8 @@ __global__ __launch_bounds__(MfCfg<N>::NT) void patch_setup_mfma_kernel(
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // this wavefront's tile row
   const int l16 = lane & 15, l4 = lane >> 4;
-  for (int h = tid; h < PatchHash::SLOTS; h += NT) htab[h] = make_int2(-1, 0);
+  if (!MAP)
+    for (int h = tid; h < PatchHash::SLOTS; h += NT) htab[h] = make_int2(-1, 0);
   for (int i = tid; i < NP; i += NT) {
     qs[i] = i < N ? i : 0;  // overwritten by every pivot; keeps the output in range otherwise
     kinv[i] = -1;
@@ -1089,6 +1161,30 @@ __global__ __launch_bounds__(MfCfg<N>::NT) void patch_setup_mfma_kernel(
   }
   for (int e = tid; e < 2 * NB * NP; e += NT) (&bs[0][0])[e] = 0.0;
   if (tid == 0) bad_s = 0;
+  f64x4_t acc[T];
+#pragma unroll
+  for (int J = 0; J < T; ++J) acc[J] = (f64x4_t){0.0, 0.0, 0.0, 0.0};
+  if constexpr (MAP) {
+    // ---- gather through the patch entry map: every load of the tile row issued at once ----
+    int64_t rb[4];  // first CSR entry of this lane's rows 16 w + 4 v + l / 16
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * w + 4 * v + l4;
+      rb[v] = i < N ? row_ptr[cell_dofs[(int64_t)K * N + i]] : 0;
+    }
+    const uint64_t* mp = pmap + ((int64_t)K * T + w) * T * 64 + lane;
+    uint64_t mw[T];
+#pragma unroll
+    for (int J = 0; J < T; ++J) mw[J] = mp[J * 64];
+#pragma unroll
+    for (int J = 0; J < T; ++J)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const uint32_t o = (uint32_t)(mw[J] >> (16 * v)) & 0xFFFFu;
+        if (o != 0xFFFFu) acc[J][v] = val[rb[v] + o];
+      }
+    __syncthreads();
+  } else {
   __syncthreads();
   if (tid < N) {
     const int dof = cell_dofs[(int64_t)K * N + tid];
@@ -1098,9 +1194,6 @@ __global__ __launch_bounds__(MfCfg<N>::NT) void patch_setup_mfma_kernel(
     PatchHash::insert(htab, dof, tid);
   }
   // ---- gather: 16 patch rows at a time through LDS, then into the tiles of that row block ----
-  f64x4_t acc[T];
-#pragma unroll
-  for (int J = 0; J < T; ++J) acc[J] = (f64x4_t){0.0, 0.0, 0.0, 0.0};
   for (int I = 0; I < T; ++I) {
     __syncthreads();
     for (int e = tid; e < 16 * NP; e += NT) stage[e] = 0.0;
@@ -1123,6 +1216,7 @@ __global__ __launch_bounds__(MfCfg<N>::NT) void patch_setup_mfma_kernel(
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[J][v] = stage[(4 * v + l4) * NP + 16 * J + l16];
     }
+  }
   }
   // ---- elimination, panel by panel ----
   uint32_t used = 0;  // the panel wavefront's record of pivotal rows (bit r: row r * 64 + lane)
@@ -1311,7 +1405,7 @@ __global__ __launch_bounds__(MfCfg<N>::NT) void patch_setup_mfma_kernel(
 
 template <int P>
 hipError_t setup_rows(hipStream_t s, const vk_csr& J, const vk_group& L, int32_t* status, bool* handled,
-                      bool mfma) {
+                      bool mfma, bool map) {
   *handled = true;
   switch (L.n_K) {
 #define VK_ROWS_CASE(NN)                                                                                \
@@ -1334,9 +1428,13 @@ hipError_t setup_rows(hipStream_t s, const vk_csr& J, const vk_group& L, int32_t
     VK_WIDE_CASE(180)
 #undef VK_WIDE_CASE
     case 170:
-      if (mfma) {
-        patch_setup_mfma_kernel<P, 170><<<L.n_cells, MfCfg<170>::NT, 0, s>>>(
-            J.row_ptr, J.col, J.val, L.cell_dofs, L.inv, L.ld, L.cell_stride, status);
+      if (mfma && map && L.pmap && L.pmap_ok) {
+        patch_setup_mfma_kernel<P, 170, true><<<L.n_cells, MfCfg<170>::NT, 0, s>>>(
+            J.row_ptr, J.col, J.val, L.cell_dofs, reinterpret_cast<const uint64_t*>(L.pmap), L.inv, L.ld,
+            L.cell_stride, status);
+      } else if (mfma) {
+        patch_setup_mfma_kernel<P, 170, false><<<L.n_cells, MfCfg<170>::NT, 0, s>>>(
+            J.row_ptr, J.col, J.val, L.cell_dofs, nullptr, L.inv, L.ld, L.cell_stride, status);
       } else {
         patch_setup_wide_kernel<P, 170><<<L.n_cells, 64 * WideCfg<170>::NW, 0, s>>>(
             J.row_ptr, J.col, J.val, L.cell_dofs, L.inv, L.ld, L.cell_stride, status);
@@ -1567,16 +1665,25 @@ hipError_t gemv_prec(hipStream_t s, const vk_group& L, int cpb, const double* r,
 
 }  // namespace
 
+int64_t vk_patch_map_elems(int32_t n_K) { return n_K == 170 ? (int64_t)MfCfg<170>::T * MfCfg<170>::T * 256 : 0; }
+
+hipError_t launch_patch_map(hipStream_t s, const vk_csr& J, const vk_group& G, int32_t* too_long) {
+  if (!G.pmap || G.n_cells == 0 || vk_patch_map_elems(G.n_K) == 0) return hipSuccess;
+  patch_map_kernel<170><<<G.n_cells, 512, 0, s>>>(J.row_ptr, J.col, G.cell_dofs,
+                                                   reinterpret_cast<uint64_t*>(G.pmap), too_long);
+  return hipGetLastError();
+}
+
 hipError_t launch_patch_setup_fast(hipStream_t s, const vk_csr& J, const vk_group& G, vk_prec prec, int32_t* status,
-                                   bool* handled, bool mfma) {
+                                   bool* handled, bool mfma, bool map) {
   if (G.n_cells == 0) {
     *handled = true;
     return hipSuccess;
   }
   switch (prec) {
-    case VK_F64: return setup_rows<VK_F64>(s, J, G, status, handled, mfma);
-    case VK_F32: return setup_rows<VK_F32>(s, J, G, status, handled, mfma);
-    default: return setup_rows<VK_BF16>(s, J, G, status, handled, mfma);
+    case VK_F64: return setup_rows<VK_F64>(s, J, G, status, handled, mfma, map);
+    case VK_F32: return setup_rows<VK_F32>(s, J, G, status, handled, mfma, map);
+    default: return setup_rows<VK_BF16>(s, J, G, status, handled, mfma, map);
   }
 }
 

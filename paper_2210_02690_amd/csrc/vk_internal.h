@@ -93,6 +93,11 @@ struct vk_group {
   int32_t ld = 0;             // leading dimension (rows, padded)
   int64_t cell_stride = 0;    // elements per cell
   int64_t y_off = 0;          // first flat (cell, local) index of the group on its level
+  // patch entry map of the matrix-core inversion (patch.hip, patch_map_kernel): per cell, per
+  // accumulator element of its 16 x 16 tiles, the entry's offset in its CSR row (0xFFFF: not
+  // stored); planned once per pattern and workspace
+  uint16_t* pmap = nullptr;
+  bool pmap_ok = false;
 };
 
 // Buffers of the blocked patch inversion: up to `cap` doubles of dense blocks (the setup scratch),
@@ -236,6 +241,7 @@ struct vk_ctx {
   int32_t sweep_variant = 0;  // additive sweep: 0 DoF gather, 1 coloured scatter
   bool fast_setup = true;     // register-resident patch inversion where compiled
   bool mfma_setup = true;     // the matrix-core kernel where one is compiled for the patch width
+  bool patch_map = true;      // ... gathering its patches through the patch entry map
   int64_t coarse_min_tourney = VK_TOURNEY_MIN_N;  // blocks wider than this choose pivots by tournament
   int32_t coarse_solver = 0;  // 0: block-tridiagonal factorisation where it applies, 1: dense inverse
   bool spmv_grouped = true;   // J products through the grouped CSR where a plan exists
@@ -322,8 +328,13 @@ hipError_t launch_dof_ell(hipStream_t s, const vk_level& L);
 hipError_t launch_patch_setup(hipStream_t s, const vk_csr& J, const vk_group& G, vk_prec prec, double* big_scratch,
                               int32_t big_chunk, int32_t* status);
 // mfma: the matrix-core kernel where one is compiled for the patch width (else the VALU kernel)
+// uint16 elements per cell of the patch entry map for patches n_K wide (0: no map for this width)
+int64_t vk_patch_map_elems(int32_t n_K);
+// plan G.pmap from J's pattern and G's cells; too_long (one int32) becomes nonzero when a row of a
+// patch has more than 65535 entries (the map cannot hold its offsets)
+hipError_t launch_patch_map(hipStream_t s, const vk_csr& J, const vk_group& G, int32_t* too_long);
 hipError_t launch_patch_setup_fast(hipStream_t s, const vk_csr& J, const vk_group& G, vk_prec prec, int32_t* status,
-                                   bool* handled, bool mfma = true);
+                                   bool* handled, bool mfma = true, bool map = false);
 // Patches of more than VK_LDS_SETUP_MAX_NK (at most 512) rows through the blocked Gauss-Jordan
 // kernels of the directly solved blocks, in chunks of the workspace's blocked-setup buffers.
 hipError_t launch_patch_setup_blocked(hipStream_t s, const vk_csr& J, const vk_group& G, vk_prec prec,

@@ -314,10 +314,10 @@ def test_singular_wide_patch_reported(vk):
     S.close()
 
 
-@pytest.mark.parametrize("variant", [0, 2])
+@pytest.mark.parametrize("variant", [0, 2, 3])
 def test_singular_170_patch_reported(vk, variant):
-    """A singular 170-wide patch (3D dG(1)) names its cell, on the matrix cores (variant 0) and on
-    the vector unit (variant 2)."""
+    """A singular 170-wide patch (3D dG(1)) names its cell, on the matrix cores (variant 0 through the
+    patch entry map, variant 3 through the LDS hash) and on the vector unit (variant 2)."""
     P = build_problem("box3d_100x16x16_k1", shape=(4, 2, 2), levels=2, k=1)
     L = P.finest
     assert L.mesh.n_K == 170
@@ -465,10 +465,11 @@ def test_dof_gather_widths_agree(vk, case):
                                   "box3d_k2", "r4_k3"])
 def test_setup_variants_agree(vk, case):
     """The register-resident (or, for the widest patches, the blocked) and the LDS / global-memory
-    Gauss-Jordan kernels give the same inverses."""
+    Gauss-Jordan kernels give the same inverses (variant 3: the matrix-core kernel gathering through
+    the LDS hash instead of the patch entry map)."""
     P, H = problem(case)
     outs = []
-    for variant in (0, 1, 2):
+    for variant in (0, 1, 2, 3):
         S = vk.Solver([vk.upload_level(L, DEV) for L in P.levels])
         S.vk_set_workspace("f64", 30, device=DEV)
         S.vk_set_setup_variant(variant)
