@@ -1053,10 +1053,10 @@ __device__ inline double recip_f64(double a) {
 template <int N> struct MfCfg {
   static constexpr int NP = (N + 15) / 16 * 16;  // padded width
   static constexpr int T = NP / 16;              // tiles per dimension = wavefronts
-  static constexpr int NT = 64 * T;
+  static constexpr int NT = 64 * (T + 1);       // T tile-row wavefronts and the panel wavefront
   static constexpr int NB = 4;                   // panel width (one MFMA depth)
   static constexpr int R = (NP + 63) / 64;       // panel rows per lane
-  static constexpr int PW = T - 1;               // the wavefront that eliminates the panels
+  static constexpr int PW = T;                   // the wavefront that eliminates the panels
   static constexpr int PLD = NB + 1;             // LDS row length of a panel (doubles)
 };
 
@@ -1139,7 +1139,7 @@ __global__ __launch_bounds__(MfCfg<N>::NT) void patch_setup_mfma_kernel(
   constexpr int NP = C::NP, T = C::T, NT = C::NT, NB = C::NB, R = C::R, PW = C::PW, PLD = C::PLD;
   static_assert(R <= 4 && NP <= 256, "patch width");
   __shared__ int qs[NP], kinv[NP];
-  __shared__ int pq[2][NB];               // the panel's pivot rows (-1: none), double-buffered
+  __shared__ __align__(16) int pq[2][NB];  // the panel's pivot rows (-1: none), double-buffered
   __shared__ double stage[16 * NP];       // gather rows / output columns
   __shared__ double pan[2][NP * PLD];     // panel columns (double-buffered)
   __shared__ double bs[2][NB * NP];       // old pivot rows (double-buffered)
@@ -1166,23 +1166,25 @@ __global__ __launch_bounds__(MfCfg<N>::NT) void patch_setup_mfma_kernel(
   for (int J = 0; J < T; ++J) acc[J] = (f64x4_t){0.0, 0.0, 0.0, 0.0};
   if constexpr (MAP) {
     // ---- gather through the patch entry map: every load of the tile row issued at once ----
-    int64_t rb[4];  // first CSR entry of this lane's rows 16 w + 4 v + l / 16
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = 16 * w + 4 * v + l4;
-      rb[v] = i < N ? row_ptr[cell_dofs[(int64_t)K * N + i]] : 0;
-    }
-    const uint64_t* mp = pmap + ((int64_t)K * T + w) * T * 64 + lane;
-    uint64_t mw[T];
-#pragma unroll
-    for (int J = 0; J < T; ++J) mw[J] = mp[J * 64];
-#pragma unroll
-    for (int J = 0; J < T; ++J)
+    if (w < T) {  // the tile-row wavefronts
+      int64_t rb[4];  // first CSR entry of this lane's rows 16 w + 4 v + l / 16
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const uint32_t o = (uint32_t)(mw[J] >> (16 * v)) & 0xFFFFu;
-        if (o != 0xFFFFu) acc[J][v] = val[rb[v] + o];
+        const int i = 16 * w + 4 * v + l4;
+        rb[v] = i < N ? row_ptr[cell_dofs[(int64_t)K * N + i]] : 0;
       }
+      const uint64_t* mp = pmap + ((int64_t)K * T + w) * T * 64 + lane;
+      uint64_t mw[T];
+#pragma unroll
+      for (int J = 0; J < T; ++J) mw[J] = mp[J * 64];
+#pragma unroll
+      for (int J = 0; J < T; ++J)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const uint32_t o = (uint32_t)(mw[J] >> (16 * v)) & 0xFFFFu;
+          if (o != 0xFFFFu) acc[J][v] = val[rb[v] + o];
+        }
+    }
     __syncthreads();
   } else {
   __syncthreads();
@@ -1218,170 +1220,17 @@ __global__ __launch_bounds__(MfCfg<N>::NT) void patch_setup_mfma_kernel(
     }
   }
   }
-  // ---- elimination, panel by panel ----
-  uint32_t used = 0;  // the panel wavefront's record of pivotal rows (bit r: row r * 64 + lane)
-#pragma unroll
-  for (int r = 0; r < R; ++r)
-    if (r * 64 + lane >= N) used |= 1u << r;
-  bool singular = false;
+  // ---- elimination, panel by panel; the panel wavefront factors panel j + 1 while the tile
+  //      wavefronts finish panel j's update.  The two kinds of wavefront run separate loops with
+  //      the same sequence of barriers (the panel wavefront holds no tiles, so none of its
+  //      registers go to them) ----
   constexpr int NPAN = (N + NB - 1) / NB;
-  for (int j = 0; j < NPAN; ++j) {
-    const int k0 = NB * j, Jp = k0 / 16, h0 = k0 % 16;  // panel columns [k0, k0 + NB) in tile column Jp
-    double* pn = pan[j & 1];
-    double* bb = bs[j & 1];
-    int* pqj = pq[j & 1];
-    const bool in_pan = l16 >= h0 && l16 < h0 + NB;
-    // 1. the panel's columns to LDS
-#pragma unroll
-    for (int J = 0; J < T; ++J)
-      if (J == Jp && in_pan) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) pn[(16 * w + 4 * v + l4) * PLD + (l16 - h0)] = acc[J][v];
-      }
-    __syncthreads();
-    // 2. the panel's elimination steps on one wavefront
-    if (w == PW) {
-      double pr[R][NB];
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int c = 0; c < NB; ++c) pr[r][c] = (r * 64 + lane < NP) ? pn[(r * 64 + lane) * PLD + c] : 0.0;
-#pragma unroll
-      for (int t = 0; t < NB; ++t) {
-        const int k = k0 + t;
-        if (k >= N) {  // uniform: a padding column of the last panel
-          if (lane == 0) pqj[t] = -1;
-          continue;
-        }
-        double key = -1.0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          int2 kb = __builtin_bit_cast(int2, fabs(pr[r][t]));
-          kb.x = (kb.x & ~0xFF) | (255 - 64 * r - lane);  // the low mantissa byte: 255 - row
-          if (!((used >> r) & 1u)) key = fmax(key, __builtin_bit_cast(double, kb));
-        }
-        const double m = wave_max(key);
-        const uint64_t mb = __builtin_bit_cast(uint64_t, m);
-        const int p = 255 - (int)(mb & 0xFFull);
-        if (!(m > 0.0) || (mb >> 8) == 0 || p >= N) {  // uniform: no nonzero finite candidate
-          singular = true;
-          if (lane == 0) pqj[t] = -1;
-          continue;
-        }
-        const int pl = p & 63, ps = p >> 6;
-        double prow[NB];
-        if (ps == 0) {
-#pragma unroll
-          for (int c = 0; c < NB; ++c) prow[c] = readlane_f64(pr[0][c], pl);
-        } else if (ps == 1 || R < 3) {
-#pragma unroll
-          for (int c = 0; c < NB; ++c) prow[c] = readlane_f64(pr[R > 1 ? 1 : 0][c], pl);
-        } else {
-#pragma unroll
-          for (int c = 0; c < NB; ++c) prow[c] = readlane_f64(pr[R > 2 ? 2 : 0][c], pl);
-        }
-        const double inv = recip_f64(prow[t]);
-#pragma unroll
-        for (int c = 0; c < NB; ++c) prow[c] = (c == t) ? inv : prow[c] * inv;
-        // the next panel column first: the next step's pivot search needs only it
-#pragma unroll
-        for (int cc = 0; cc < NB; ++cc) {
-          const int c = (t + 1 + cc) % NB;
-#pragma unroll
-          for (int r = 0; r < R; ++r)
-            pr[r][c] = (c == t) ? -pr[r][t] * inv : fma(-pr[r][t], prow[c], pr[r][c]);
-        }
-        if (lane == pl) {  // the pivot row becomes the scaled pivot row
-#pragma unroll
-          for (int r = 0; r < R; ++r)
-            if (r == ps) {
-#pragma unroll
-              for (int c = 0; c < NB; ++c) pr[r][c] = prow[c];
-            }
-          used |= 1u << ps;
-        }
-        if (lane == 0) {
-          qs[k] = p;
-          kinv[p] = k;
-          pqj[t] = p;
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int c = 0; c < NB; ++c)
-          if (r * 64 + lane < NP) pn[(r * 64 + lane) * PLD + c] = pr[r][c];
-    }
-    __syncthreads();
-    // 3. the owners of the panel's pivot rows copy their old values to LDS and clear the rows (rows
-    //    of steps without a pivot stay zero in B); the pivot rows are wave-uniform
-#pragma unroll
-    for (int t = 0; t < NB; ++t) {
-      const int q = __builtin_amdgcn_readfirstlane(pqj[t]);
-      if (q >= 0 && (q >> 4) == w) {
-        const int m = q & 15;
-        if (l4 == (m & 3)) {
-          double* dst = &bb[t * NP + l16];
-          switch (m >> 2) {
-#define VK_B_ROW(V)                                  \
-  case V:                                            \
-    _Pragma("unroll") for (int J = 0; J < T; ++J) {  \
-      dst[16 * J] = acc[J][V];                       \
-      acc[J][V] = 0.0;                               \
-    }                                                \
-    break;
-            VK_B_ROW(0)
-            VK_B_ROW(1)
-            VK_B_ROW(2)
-            VK_B_ROW(3)
-#undef VK_B_ROW
-          }
-        }
-      }
-    }
-    __syncthreads();
-    // 4. rank-NB update of every tile; the panel's own columns become M
-    double* bo = bs[(j + 1) & 1];  // the next panel's buffer: cleared while nobody reads it
-    for (int e = tid; e < NB * NP; e += NT) bo[e] = 0.0;
-    const double a = pn[(16 * w + l16) * PLD + l4];
-    double bv[T];
-#pragma unroll
-    for (int J = 0; J < T; ++J) bv[J] = bb[l4 * NP + 16 * J + l16];
-#pragma unroll
-    for (int J = 0; J < T; ++J) acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[J], acc[J], 0, 0, 0);
-    if (in_pan) {
-      double mv[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) mv[v] = pn[(16 * w + 4 * v + l4) * PLD + (l16 - h0)];
-#pragma unroll
-      for (int J = 0; J < T; ++J)
-        if (J == Jp) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[J][v] = mv[v];
-        }
-    }
-  }
-  if (singular && lane == 0) bad_s = 1;
-  __syncthreads();
-  if (tid == 0 && bad_s) atomicMin(status, K);
-  // ---- output: J_K^{-1}[kinv[i]][q_j] = W[i][j], one 16-column block at a time through LDS ----
   using S = typename PT<P>::S;
   S* out = reinterpret_cast<S*>(inv_out) + (int64_t)K * cell_stride;
-  // each of this lane's rows goes to stage row kinv[i] (i itself only after a failed pivot)
-  int dr[4];
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int i = 16 * w + 4 * v + l4;
-    const int ki = kinv[i];
-    dr[v] = i < N ? (ki >= 0 ? ki : i) : -1;
-  }
+  // output: J_K^{-1}[kinv[i]][q_j] = W[i][j], one 16-column block at a time through LDS; every
+  // thread copies its share of block J from stage to the output columns
   constexpr int OW = (16 * NP + NT - 1) / NT;  // output elements per thread and block
-#pragma unroll
-  for (int J = 0; J < T; ++J) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      if (dr[v] >= 0) stage[l16 * NP + dr[v]] = acc[J][v];
-    __syncthreads();
+  auto copy_block = [&](int J) {
     int cq[OW];
     double xv[OW];
 #pragma unroll
@@ -1399,8 +1248,211 @@ __global__ __launch_bounds__(MfCfg<N>::NT) void patch_setup_mfma_kernel(
       const int jj = e / ld, r = e - jj * ld;
       if (cq[o] >= 0) out[(int64_t)cq[o] * ld + r] = store_cvt<P>(xv[o]);
     }
-    __syncthreads();
+  };
+  // panel 0's columns to LDS
+  if (w < T && l16 < NB) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) pan[0][(16 * w + 4 * v + l4) * PLD + l16] = acc[0][v];
   }
+  __syncthreads();
+  if (w == PW) {
+    // ---- the panel wavefront ----
+    uint32_t used = 0;  // pivotal rows (bit r: row r * 64 + lane)
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (r * 64 + lane >= N) used |= 1u << r;
+    bool singular = false;
+    // the NB elimination steps of panel jj on its columns in pan[jj & 1] (panel wavefront only)
+    auto factor = [&](int jj) {
+      const int k0 = NB * jj;
+      double* pn = pan[jj & 1];
+      int* pqj = pq[jj & 1];
+      double pr[R][NB];
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) pr[r][c] = (r * 64 + lane < NP) ? pn[(r * 64 + lane) * PLD + c] : 0.0;
+#pragma unroll
+      for (int t = 0; t < NB; ++t) {
+        const int k = k0 + t;
+        // 32-bit pivot keys: |a|'s exponent and 13 leading mantissa bits, then 255 - row (0 for
+        // rows already pivotal and for non-finite entries), so one integer wavefront maximum gives
+        // the row as well
+        uint32_t key = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const uint32_t hi = (uint32_t)(__builtin_bit_cast(uint64_t, pr[r][t]) >> 32);
+          const uint32_t kr = ((hi & 0x7FFFFF80u) << 1) | (uint32_t)(255 - 64 * r - lane);
+          const bool ok = !((used >> r) & 1u) && (hi & 0x7FF00000u) != 0x7FF00000u;
+          key = max(key, ok ? kr : 0u);
+        }
+        const uint32_t mk = wave_max_u32(key);
+        const int p = 255 - (int)(mk & 0xFFu);
+        // uniform: a padding column of the last panel, or no nonzero finite candidate (the
+        // step is then a no-op on the other columns: its row of B stays zero)
+        const bool skip = k >= N || (mk >> 8) == 0 || p >= N;
+        if (skip && k < N) singular = true;
+        const int pl = p & 63, ps = p >> 6;
+        // the pivot row's entries: every lane selects its row of block ps (uniform), lane pl's
+        // are read out
+        double prow[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          double x = pr[0][c];
+#pragma unroll
+          for (int r = 1; r < R; ++r) x = (ps == r) ? pr[r][c] : x;
+          prow[c] = readlane_f64(x, pl);
+        }
+        const double inv = skip ? 0.0 : recip_f64(prow[t]);
+#pragma unroll
+        for (int c = 0; c < NB; ++c) prow[c] = (c == t) ? inv : prow[c] * inv;
+        // straight-line update, the next panel column first (the next step's pivot search needs
+        // only it); the pivot row becomes the scaled pivot row
+        bool isp[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) isp[r] = !skip && r == ps && lane == pl;
+#pragma unroll
+        for (int cc = 0; cc < NB; ++cc) {
+          const int c = (t + 1 + cc) % NB;
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const double u = (c == t) ? -pr[r][t] * inv : fma(-pr[r][t], prow[c], pr[r][c]);
+            pr[r][c] = isp[r] ? prow[c] : u;
+          }
+        }
+        used |= (!skip && lane == pl) ? 1u << ps : 0u;
+        if (lane == 0) {
+          pqj[t] = skip ? -1 : p;
+          if (!skip) {
+            qs[k] = p;
+            kinv[p] = k;
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+          if (r * 64 + lane < NP) pn[(r * 64 + lane) * PLD + c] = pr[r][c];
+    };
+    factor(0);
+    for (int j = 0; j < NPAN; ++j) {
+      __syncthreads();  // B: panel j factored
+      __syncthreads();  // C: the old pivot rows in LDS
+      __syncthreads();  // D: panel j + 1's columns in LDS
+      if (j + 1 < NPAN) factor(j + 1);
+    }
+    if (singular && lane == 0) bad_s = 1;
+    __syncthreads();
+#pragma unroll 1
+    for (int J = 0; J < T; ++J) {
+      __syncthreads();
+      __syncthreads();  // block J's columns in stage
+      copy_block(J);
+    }
+  } else {
+    // ---- the tile-row wavefronts ----
+    for (int j = 0; j < NPAN; ++j) {
+      __syncthreads();  // B: panel j factored; every tile carries the updates of panels < j
+      const int Jp = NB * j / 16, h0 = NB * j % 16;  // panel j: columns [h0, h0 + NB) of tile column Jp
+      const bool nxt = j + 1 < NPAN;
+      const int Jn = nxt ? NB * (j + 1) / 16 : -1, h1 = NB * (j + 1) % 16;
+      double* pn = pan[j & 1];
+      double* bb = bs[j & 1];
+      int* pqj = pq[j & 1];
+      // the owners of the panel's pivot rows copy their old values to LDS and clear the rows (rows
+      // of steps without a pivot stay zero in B).  Each lane finds, for each of its four rows,
+      // the step whose pivot it is (if any), so the accumulator element is fixed at compile time
+      // and only the LDS row depends on the lane.
+      {
+        const int4 q4 = *reinterpret_cast<const int4*>(pqj);
+        const int q0 = __builtin_amdgcn_readfirstlane(q4.x), q1 = __builtin_amdgcn_readfirstlane(q4.y);
+        const int q2 = __builtin_amdgcn_readfirstlane(q4.z), q3 = __builtin_amdgcn_readfirstlane(q4.w);
+        // uniform: does this wavefront hold a pivot row of the panel (-1 >> 4 is -1, never w)
+        if ((q0 >> 4) == w || (q1 >> 4) == w || (q2 >> 4) == w || (q3 >> 4) == w) {
+          int tv[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = 16 * w + 4 * v + l4;
+            tv[v] = row == q0 ? 0 : row == q1 ? 1 : row == q2 ? 2 : row == q3 ? 3 : -1;
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (tv[v] >= 0) {
+              double* dst = &bb[tv[v] * NP + l16];
+#pragma unroll
+              for (int J = 0; J < T; ++J) dst[16 * J] = acc[J][v];
+            }
+          // the rows are cleared by a multiplication, not under the lane branch (which would
+          // make the compiler copy every accumulator)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const double kv = tv[v] >= 0 ? 0.0 : 1.0;
+#pragma unroll
+            for (int J = 0; J < T; ++J) acc[J][v] *= kv;
+          }
+        }
+      }
+      __syncthreads();  // C
+      // rank-NB update of every tile, W' = W + M B; the panel's own columns become M.  The tile
+      // column of panel j + 1 goes first and hands that panel's columns to the panel wavefront.
+      const bool in_pan = l16 >= h0 && l16 < h0 + NB;
+      const bool in_nxt = l16 >= h1 && l16 < h1 + NB;
+      if (nxt) {
+        const double a = pn[(16 * w + l16) * PLD + l4];
+        const double bn = bb[l4 * NP + 16 * Jn + l16];
+        double* pnx = pan[(j + 1) & 1];
+#pragma unroll
+        for (int J = 0; J < T; ++J)
+          if (J == Jn) {
+            acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bn, acc[J], 0, 0, 0);
+            if (J == Jp && in_pan) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) acc[J][v] = pn[(16 * w + 4 * v + l4) * PLD + (l16 - h0)];
+            }
+            if (in_nxt) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) pnx[(16 * w + 4 * v + l4) * PLD + (l16 - h1)] = acc[J][v];
+            }
+          }
+      }
+      __syncthreads();  // D: panel j + 1's columns are in LDS
+      {
+        const double a = pn[(16 * w + l16) * PLD + l4];
+#pragma unroll
+        for (int J = 0; J < T; ++J)
+          if (J != Jn) {
+            acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb[l4 * NP + 16 * J + l16], acc[J], 0, 0, 0);
+            if (J == Jp && in_pan) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) acc[J][v] = pn[(16 * w + 4 * v + l4) * PLD + (l16 - h0)];
+            }
+          }
+        // the next panel's buffer of old pivot rows, cleared while nobody reads it
+        double* bo = bs[(j + 1) & 1];
+        for (int e = tid; e < NB * NP; e += 64 * T) bo[e] = 0.0;
+      }
+    }
+    __syncthreads();  // the panel wavefront's singular flag
+    // each of this lane's rows goes to stage row kinv[i] (i itself only after a failed pivot)
+    int dr[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * w + 4 * v + l4;
+      const int ki = i < N ? kinv[i] : -1;
+      dr[v] = i < N ? (ki >= 0 ? ki : i) : -1;
+    }
+#pragma unroll
+    for (int J = 0; J < T; ++J) {
+      __syncthreads();  // the previous block's copies are done with stage
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (dr[v] >= 0) stage[l16 * NP + dr[v]] = acc[J][v];
+      __syncthreads();  // block J's columns in stage
+      copy_block(J);
+    }
+  }
+  if (tid == 0 && bad_s) atomicMin(status, K);
 }
 
 template <int P>
