@@ -159,8 +159,9 @@ vk_status vk_set_workspace(vk_ctx* ctx, void* dev, size_t bytes, vk_prec prec, i
 /* Vanka setup (Sec. 3, the paragraph after Eq. 3.4): for every cell K of every
  * level l >= 1 gather J_K = J_l restricted to dof(K, .) x dof(K, .), entries
  * not stored in J_l being zero, invert it in FP64 by Gauss-Jordan elimination
- * with partial pivoting (first row of maximal |pivot|; the LU pivot sequence)
- * and store A_K in `prec`; compute 1/p_mu, p_mu = number of cells containing
+ * with partial pivoting (first row of maximal |pivot|, the LU pivot sequence;
+ * the matrix-core kernel of the 170-wide patches counts candidates within a
+ * relative 2^-13 of the largest as tied) and store A_K in `prec`; compute 1/p_mu, p_mu = number of cells containing
  * DoF mu (Eq. 3.5b); and form the FP64 inverse of J_0 for the coarsest-level
  * direct solve (blocked Gauss-Jordan with partial pivoting: the largest |pivot|
  * up to a relative 2^-38, the lowest row among those).  omega is the

@@ -1026,24 +1026,25 @@ __device__ inline double recip_f64(double a) {
 // ---------------------------------------------------------------------------
 // Wide patches on the FP64 matrix cores (compiled for n_K = 170, the 3D Q2/P1disc dG(1) patch):
 // blocked Gauss-Jordan with implicit partial pivoting.  The patch, padded to NP = 16 T, lives in
-// registers as T x T tiles of 16 x 16: wavefront w holds tile row w (T wavefronts).  Columns are
-// eliminated in panels of NB = 4:
-//   1. the tiles of the panel's column block copy the panel's columns to LDS;
-//   2. one wavefront runs the panel's NB elimination steps on it (rows in registers) and writes the
-//      eliminated panel M back, with the pivot rows q_t;
-//   3. the owners of the pivot rows copy their old values, B[t][c] = W[q_t][c], to LDS and clear
+// registers as T x T tiles of 16 x 16: tile-row wavefront w (of T) holds tile row w, and one more
+// wavefront, which holds no tiles, eliminates the panels.  Columns are eliminated in panels of
+// NB = 4; with panel j factored (its eliminated columns M and pivot rows q_t in LDS):
+//   1. the owners of the pivot rows copy their old values, B[t][c] = W[q_t][c], to LDS and clear
 //      those rows;
-//   4. every tile applies the panel as one rank-NB update on the matrix cores,
+//   2. every tile applies the panel as one rank-NB update on the matrix cores,
 //        W'[i][c] = (i pivotal in this panel ? 0 : W[i][c]) + sum_t M[i][t] B[t][c],
-//      and the panel's own columns become M.
+//      and the panel's own columns become M.  The tile column holding panel j + 1 goes first and
+//      copies that panel's columns to LDS; the panel wavefront then runs panel j + 1's NB
+//      elimination steps (rows in registers) while the other tiles finish the update.
 // This composes the NB single-column Gauss-Jordan steps exactly (for one step it reads
 // W'[i][c] = W[i][c] - W[i][k] W[p][c] / W[p][k], W'[p][c] = W[p][c] / W[p][k]).  After all steps
 // J_K^{-1}[k][q_j] = W[q_k][j], written out through LDS one 16-column block at a time so the
 // stores of a column are contiguous.
-// Pivot choice: the largest |a| among the rows not yet pivotal, compared on its bit pattern with
-// the lowest 8 mantissa bits replaced by 255 - row, so one wavefront maximum gives the row as
-// well: candidates within 2^-44 of each other count as ties and the lowest row wins (the first
-// maximal row of the LU pivot sequence whenever the maximum is unique to that precision).
+// Pivot choice: the largest |a| among the rows not yet pivotal, compared on a 32-bit key (|a|'s
+// exponent and 13 leading mantissa bits, then 255 - row), so one integer wavefront maximum gives
+// the row as well: candidates within a relative 2^-13 count as ties and the lowest row wins (the
+// first maximal row of the LU pivot sequence whenever the maximum is unique to that precision;
+// the multipliers stay below 1 + 2^-13 in magnitude).
 // The FP64 MFMA (16 x 16 x 4) computes D(m, n) = sum_k A(m, k) B(k, n) + C: lane l supplies
 // A(l % 16, l / 16) and B(l / 16, l % 16), and accumulator element v holds D(4 v + l / 16, l % 16),
 // so a tile's lane l owns rows 4 v + l / 16 of column l % 16.  Tile indices are compile-time
