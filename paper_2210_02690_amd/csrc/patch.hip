@@ -1033,9 +1033,10 @@ __device__ inline double recip_f64(double a) {
 //      those rows;
 //   2. every tile applies the panel as one rank-NB update on the matrix cores,
 //        W'[i][c] = (i pivotal in this panel ? 0 : W[i][c]) + sum_t M[i][t] B[t][c],
-//      and the panel's own columns become M.  The tile column holding panel j + 1 goes first and
-//      copies that panel's columns to LDS; the panel wavefront then runs panel j + 1's NB
-//      elimination steps (rows in registers) while the other tiles finish the update.
+//      and the panel's own columns become M; the tiles then copy the columns of panel j + 2 to LDS.
+// Meanwhile the panel wavefront applies the same update to panel j + 1's columns (copied to LDS
+// one panel earlier, B's entries in those columns read from them) and runs panel j + 1's NB
+// elimination steps on them in registers, so the tile updates never wait for a panel.
 // This composes the NB single-column Gauss-Jordan steps exactly (for one step it reads
 // W'[i][c] = W[i][c] - W[i][k] W[p][c] / W[p][k], W'[p][c] = W[p][c] / W[p][k]).  After all steps
 // J_K^{-1}[k][q_j] = W[q_k][j], written out through LDS one 16-column block at a time so the
@@ -1142,7 +1143,8 @@ __global__ __launch_bounds__(MfCfg<N>::NT) void patch_setup_mfma_kernel(
   __shared__ int qs[NP], kinv[NP];
   __shared__ __align__(16) int pq[2][NB];  // the panel's pivot rows (-1: none), double-buffered
   __shared__ double stage[16 * NP];       // gather rows / output columns
-  __shared__ double pan[2][NP * PLD];     // panel columns (double-buffered)
+  __shared__ double pan[2][NP * PLD];     // eliminated panel columns M (double-buffered)
+  __shared__ double pc[2][NP * PLD];      // the next panel's columns before its last update
   __shared__ double bs[2][NB * NP];       // old pivot rows (double-buffered)
   __shared__ int2 htab[PatchHash::SLOTS]; // DoF -> local index
   __shared__ int64_t rbeg[N];             // first CSR entry of each patch row
@@ -1250,48 +1252,50 @@ __global__ __launch_bounds__(MfCfg<N>::NT) void patch_setup_mfma_kernel(
       if (cq[o] >= 0) out[(int64_t)cq[o] * ld + r] = store_cvt<P>(xv[o]);
     }
   };
-  // panel 0's columns to LDS
-  if (w < T && l16 < NB) {
+  static_assert(NPAN >= 2 && 2 * NB <= 16, "two panels in the first tile column");
+  // panels 0 and 1: their columns to LDS
+  if (w < T) {
+    if (l16 < 2 * NB) {
+      double* dst = pc[l16 / NB];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) pan[0][(16 * w + 4 * v + l4) * PLD + l16] = acc[0][v];
+      for (int v = 0; v < 4; ++v) dst[(16 * w + 4 * v + l4) * PLD + (l16 % NB)] = acc[0][v];
+    }
   }
   __syncthreads();
   if (w == PW) {
     // ---- the panel wavefront ----
-    uint32_t used = 0;  // pivotal rows (bit r: row r * 64 + lane)
+    // per row block: all ones while the lane's row may still become a pivot, and 255 - row
+    uint32_t um[R], rid[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-      if (r * 64 + lane >= N) used |= 1u << r;
+    for (int r = 0; r < R; ++r) {
+      um[r] = r * 64 + lane < N ? 0xFFFFFFFFu : 0u;
+      rid[r] = (uint32_t)(255 - 64 * r - lane);
+    }
     bool singular = false;
-    // the NB elimination steps of panel jj on its columns in pan[jj & 1] (panel wavefront only)
+    double pr[R][NB];  // the current panel's columns, the lane's rows r * 64 + lane
+    bool zr[R];        // the lane's rows that became pivots in the current panel
+    int pv[NB];        // the current panel's pivot rows (-1: none); uniform
+    // the NB elimination steps of panel jj on pr; M and the pivot rows go to LDS
     auto factor = [&](int jj) {
       const int k0 = NB * jj;
-      double* pn = pan[jj & 1];
-      int* pqj = pq[jj & 1];
-      double pr[R][NB];
 #pragma unroll
-      for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int c = 0; c < NB; ++c) pr[r][c] = (r * 64 + lane < NP) ? pn[(r * 64 + lane) * PLD + c] : 0.0;
+      for (int r = 0; r < R; ++r) zr[r] = false;
 #pragma unroll
       for (int t = 0; t < NB; ++t) {
         const int k = k0 + t;
         // 32-bit pivot keys: |a|'s exponent and 13 leading mantissa bits, then 255 - row (0 for
-        // rows already pivotal and for non-finite entries), so one integer wavefront maximum gives
-        // the row as well
+        // rows already pivotal), so one integer wavefront maximum gives the row as well
         uint32_t key = 0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const uint32_t hi = (uint32_t)(__builtin_bit_cast(uint64_t, pr[r][t]) >> 32);
-          const uint32_t kr = ((hi & 0x7FFFFF80u) << 1) | (uint32_t)(255 - 64 * r - lane);
-          const bool ok = !((used >> r) & 1u) && (hi & 0x7FF00000u) != 0x7FF00000u;
-          key = max(key, ok ? kr : 0u);
+          key = max(key, (((hi & 0x7FFFFF80u) << 1) | rid[r]) & um[r]);
         }
         const uint32_t mk = wave_max_u32(key);
         const int p = 255 - (int)(mk & 0xFFu);
-        // uniform: a padding column of the last panel, or no nonzero finite candidate (the
-        // step is then a no-op on the other columns: its row of B stays zero)
-        const bool skip = k >= N || (mk >> 8) == 0 || p >= N;
+        // uniform: a padding column of the last panel, no nonzero candidate, or a non-finite
+        // largest one (the step is then a no-op on the other columns: its row of B stays zero)
+        const bool skip = k >= N || (mk >> 8) == 0 || (mk >> 21) == 0x7FFu || p >= N;
         if (skip && k < N) singular = true;
         const int pl = p & 63, ps = p >> 6;
         // the pivot row's entries: every lane selects its row of block ps (uniform), lane pl's
@@ -1321,26 +1325,67 @@ __global__ __launch_bounds__(MfCfg<N>::NT) void patch_setup_mfma_kernel(
             pr[r][c] = isp[r] ? prow[c] : u;
           }
         }
-        used |= (!skip && lane == pl) ? 1u << ps : 0u;
-        if (lane == 0) {
-          pqj[t] = skip ? -1 : p;
-          if (!skip) {
-            qs[k] = p;
-            kinv[p] = k;
-          }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          um[r] = isp[r] ? 0u : um[r];
+          zr[r] = zr[r] || isp[r];
         }
+        pv[t] = skip ? -1 : p;
       }
+      double* pn = pan[jj & 1];
 #pragma unroll
       for (int r = 0; r < R; ++r)
 #pragma unroll
         for (int c = 0; c < NB; ++c)
           if (r * 64 + lane < NP) pn[(r * 64 + lane) * PLD + c] = pr[r][c];
+      if (lane == 0) {
+        *reinterpret_cast<int4*>(pq[jj & 1]) = make_int4(pv[0], pv[1], pv[2], pv[3]);
+#pragma unroll
+        for (int t = 0; t < NB; ++t)
+          if (pv[t] >= 0) {
+            qs[k0 + t] = pv[t];
+            kinv[pv[t]] = k0 + t;
+          }
+      }
     };
+    // panel jj's columns from LDS buffer b (rows beyond NP read as zero)
+    auto load_cols = [&](const double* b, double (&x)[R][NB]) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) x[r][c] = (r * 64 + lane < NP) ? b[(r * 64 + lane) * PLD + c] : 0.0;
+    };
+    load_cols(pc[0], pr);
     factor(0);
     for (int j = 0; j < NPAN; ++j) {
-      __syncthreads();  // B: panel j factored
-      __syncthreads();  // C: the old pivot rows in LDS
-      __syncthreads();  // D: panel j + 1's columns in LDS
+      __syncthreads();  // B: the tiles carry the updates of panels < j; panel j + 1's columns, with
+                        // the updates of panels < j, are in pc
+      if (j + 1 < NPAN) {
+        // panel j's update applied here to panel j + 1's columns: x' = (x with the pivot rows of
+        // panel j cleared) + M B, B[t][.] = the old pivot rows restricted to these columns
+        const double* b = pc[(j + 1) & 1];
+        double x[R][NB];
+        load_cols(b, x);
+        double bv[NB][NB];
+#pragma unroll
+        for (int t = 0; t < NB; ++t)
+#pragma unroll
+          for (int c = 0; c < NB; ++c) bv[t][c] = pv[t] >= 0 ? b[pv[t] * PLD + c] : 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int c = 0; c < NB; ++c) {
+            double y = zr[r] ? 0.0 : x[r][c];
+#pragma unroll
+            for (int t = 0; t < NB; ++t) y = fma(pr[r][t], bv[t][c], y);
+            x[r][c] = y;
+          }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int c = 0; c < NB; ++c) pr[r][c] = x[r][c];
+      }
+      __syncthreads();  // C: the old pivot rows of panel j are in LDS
       if (j + 1 < NPAN) factor(j + 1);
     }
     if (singular && lane == 0) bad_s = 1;
@@ -1356,11 +1401,11 @@ __global__ __launch_bounds__(MfCfg<N>::NT) void patch_setup_mfma_kernel(
     for (int j = 0; j < NPAN; ++j) {
       __syncthreads();  // B: panel j factored; every tile carries the updates of panels < j
       const int Jp = NB * j / 16, h0 = NB * j % 16;  // panel j: columns [h0, h0 + NB) of tile column Jp
-      const bool nxt = j + 1 < NPAN;
-      const int Jn = nxt ? NB * (j + 1) / 16 : -1, h1 = NB * (j + 1) % 16;
+      const bool nxt2 = j + 2 < NPAN;
+      const int J2 = nxt2 ? NB * (j + 2) / 16 : -1, h2 = NB * (j + 2) % 16;
       double* pn = pan[j & 1];
       double* bb = bs[j & 1];
-      int* pqj = pq[j & 1];
+      const int* pqj = pq[j & 1];
       // the owners of the panel's pivot rows copy their old values to LDS and clear the rows (rows
       // of steps without a pivot stay zero in B).  Each lane finds, for each of its four rows,
       // the step whose pivot it is (if any), so the accumulator element is fixed at compile time
@@ -1395,40 +1440,29 @@ __global__ __launch_bounds__(MfCfg<N>::NT) void patch_setup_mfma_kernel(
         }
       }
       __syncthreads();  // C
-      // rank-NB update of every tile, W' = W + M B; the panel's own columns become M.  The tile
-      // column of panel j + 1 goes first and hands that panel's columns to the panel wavefront.
+      // rank-NB update of every tile, W' = W + M B; the panel's own columns become M.  Then the
+      // columns of panel j + 2 (now carrying the updates of panels <= j) go to LDS for the panel
+      // wavefront, which applies panel j + 1's update to them itself.
       const bool in_pan = l16 >= h0 && l16 < h0 + NB;
-      const bool in_nxt = l16 >= h1 && l16 < h1 + NB;
-      if (nxt) {
-        const double a = pn[(16 * w + l16) * PLD + l4];
-        const double bn = bb[l4 * NP + 16 * Jn + l16];
-        double* pnx = pan[(j + 1) & 1];
-#pragma unroll
-        for (int J = 0; J < T; ++J)
-          if (J == Jn) {
-            acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bn, acc[J], 0, 0, 0);
-            if (J == Jp && in_pan) {
-#pragma unroll
-              for (int v = 0; v < 4; ++v) acc[J][v] = pn[(16 * w + 4 * v + l4) * PLD + (l16 - h0)];
-            }
-            if (in_nxt) {
-#pragma unroll
-              for (int v = 0; v < 4; ++v) pnx[(16 * w + 4 * v + l4) * PLD + (l16 - h1)] = acc[J][v];
-            }
-          }
-      }
-      __syncthreads();  // D: panel j + 1's columns are in LDS
       {
         const double a = pn[(16 * w + l16) * PLD + l4];
 #pragma unroll
-        for (int J = 0; J < T; ++J)
-          if (J != Jn) {
-            acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb[l4 * NP + 16 * J + l16], acc[J], 0, 0, 0);
-            if (J == Jp && in_pan) {
+        for (int J = 0; J < T; ++J) {
+          acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb[l4 * NP + 16 * J + l16], acc[J], 0, 0, 0);
+          if (J == Jp && in_pan) {
 #pragma unroll
-              for (int v = 0; v < 4; ++v) acc[J][v] = pn[(16 * w + 4 * v + l4) * PLD + (l16 - h0)];
-            }
+            for (int v = 0; v < 4; ++v) acc[J][v] = pn[(16 * w + 4 * v + l4) * PLD + (l16 - h0)];
           }
+        }
+        if (nxt2 && l16 >= h2 && l16 < h2 + NB) {
+          double* dst = pc[(j + 2) & 1];
+#pragma unroll
+          for (int J = 0; J < T; ++J)
+            if (J == J2) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) dst[(16 * w + 4 * v + l4) * PLD + (l16 - h2)] = acc[J][v];
+            }
+        }
         // the next panel's buffer of old pivot rows, cleared while nobody reads it
         double* bo = bs[(j + 1) & 1];
         for (int e = tid; e < NB * NP; e += 64 * T) bo[e] = 0.0;
