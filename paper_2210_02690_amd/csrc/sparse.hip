@@ -82,33 +82,46 @@ __global__ __launch_bounds__(256) void spmv_g_kernel(int64_t n_groups, const int
     const int64_t v0 = row_ptr[r], m = row_ptr[r + 1] - v0, c0 = g_coff[g];
     const double* v = val + v0;
     int64_t j = lane;
-    // two entries per lane and iteration: 2 G value loads and gathers in flight
+    // x at the group's column of entry jj, for rows 0..3 of the group: unshifted columns (d = 0,
+    // most entries of a velocity node's rows) read x once; shifted ones read the next entries too
+    auto xg = [&](uint32_t cw, double (&xv)[4]) {
+      const int64_t b = (int64_t)(cw & 0x7fffffffu);
+      xv[0] = x[b];
+      xv[1] = xv[2] = xv[3] = xv[0];
+      if (cw >> 31) {
+        if (G > 1) xv[1] = x[b + 1];
+        if (G > 2) xv[2] = x[b + 2];
+        if (G > 3) xv[3] = x[b + 3];
+      }
+    };
+    // two entries per lane and iteration: their value loads and gathers in flight together
     for (; j + LPR < m; j += 2 * LPR) {
-      const uint32_t ca = gcol[c0 + j], cc = gcol[c0 + j + LPR];
-      const int64_t ba = (int64_t)(ca & 0x7fffffffu), da = (int64_t)(ca >> 31);
-      const int64_t bb = (int64_t)(cc & 0x7fffffffu), db = (int64_t)(cc >> 31);
-      s0 = fma(v[j], x[ba], s0);
-      s0 = fma(v[j + LPR], x[bb], s0);
+      const uint32_t ca = gcol[c0 + j], cb = gcol[c0 + j + LPR];
+      double xa[4], xb[4];
+      xg(ca, xa);
+      xg(cb, xb);
+      s0 = fma(v[j], xa[0], s0);
+      s0 = fma(v[j + LPR], xb[0], s0);
       if (G > 1) {
-        s1 = fma(v[m + j], x[ba + da], s1);
-        s1 = fma(v[m + j + LPR], x[bb + db], s1);
+        s1 = fma(v[m + j], xa[1], s1);
+        s1 = fma(v[m + j + LPR], xb[1], s1);
       }
       if (G > 2) {
-        s2 = fma(v[2 * m + j], x[ba + 2 * da], s2);
-        s2 = fma(v[2 * m + j + LPR], x[bb + 2 * db], s2);
+        s2 = fma(v[2 * m + j], xa[2], s2);
+        s2 = fma(v[2 * m + j + LPR], xb[2], s2);
       }
       if (G > 3) {
-        s3 = fma(v[3 * m + j], x[ba + 3 * da], s3);
-        s3 = fma(v[3 * m + j + LPR], x[bb + 3 * db], s3);
+        s3 = fma(v[3 * m + j], xa[3], s3);
+        s3 = fma(v[3 * m + j + LPR], xb[3], s3);
       }
     }
     if (j < m) {
-      const uint32_t ca = gcol[c0 + j];
-      const int64_t ba = (int64_t)(ca & 0x7fffffffu), da = (int64_t)(ca >> 31);
-      s0 = fma(v[j], x[ba], s0);
-      if (G > 1) s1 = fma(v[m + j], x[ba + da], s1);
-      if (G > 2) s2 = fma(v[2 * m + j], x[ba + 2 * da], s2);
-      if (G > 3) s3 = fma(v[3 * m + j], x[ba + 3 * da], s3);
+      double xa[4];
+      xg(gcol[c0 + j], xa);
+      s0 = fma(v[j], xa[0], s0);
+      if (G > 1) s1 = fma(v[m + j], xa[1], s1);
+      if (G > 2) s2 = fma(v[2 * m + j], xa[2], s2);
+      if (G > 3) s3 = fma(v[3 * m + j], xa[3], s3);
     }
   }
 #pragma unroll
