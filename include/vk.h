@@ -304,7 +304,7 @@ int32_t vk_spmv_format(vk_ctx* ctx, int32_t level);
 
 /* The algorithmic bytes of one product with level `level`'s J in the storage in
  * use: CSR 12 nnz + 8 (n + 1) + 24 n; grouped CSR 8 nnz + 4 (column words) +
- * 28 per group + 24 n (x, z read, y written once).  -1 for an invalid call. */
+ * 20 per group + 24 n (x, z read, y written once).  -1 for an invalid call. */
 double vk_spmv_bytes(vk_ctx* ctx, int32_t level);
 
 /* Direct solver of a level whose directly solved rows form one block wider

@@ -129,6 +129,7 @@ size_t plan_workspace(vk_ctx* ctx, vk_prec prec, int32_t restart, char* base) {
       L.gJ.gcol = cv.take<uint32_t>(L.gJ.cap_words);
       L.gJ.g_row = cv.take<int32_t>(n + 1);
       L.gJ.g_coff = cv.take<int64_t>(n + 1);
+      L.gJ.g_v0 = cv.take<int64_t>(n + 1);
     }
     if (!L.groups.empty()) {
       L.inv_p = cv.take<double>(n);
@@ -1523,9 +1524,9 @@ double vk_spmv_bytes(vk_ctx* ctx, int32_t level) {
       return -1.0;
     }
     const double ng = (double)L.gJ.n_groups;
-    // values, column words, per group its first row, column offset and two row pointers; x, z read,
-    // y written
-    return 8.0 * nnz + 4.0 * (double)words + ng * (4.0 + 8.0 + 16.0) + 24.0 * n;
+    // values, column words, per group its first row, column offset and first value offset; x, z
+    // read, y written
+    return 8.0 * nnz + 4.0 * (double)words + ng * (4.0 + 8.0 + 8.0) + 24.0 * n;
   }
   return 12.0 * nnz + 8.0 * (n + 1.0) + 24.0 * n;
 }

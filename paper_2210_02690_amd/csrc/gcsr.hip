@@ -24,7 +24,7 @@ bool vk_gcsr_plan(vk_level& L) {
   G.n_groups = 0;
   const vk_csr& A = L.J;
   const int64_t n = A.n_rows, nnz = A.nnz;
-  if (!G.gcol || n <= 0 || nnz < VK_GCSR_MIN_NNZ || A.n_cols > INT32_MAX) return false;
+  if (!G.gcol || !G.g_v0 || n <= 0 || nnz < VK_GCSR_MIN_NNZ || A.n_cols > INT32_MAX) return false;
   std::vector<int64_t> rp(n + 1);
   std::vector<int32_t> col(nnz);
   if (hipMemcpy(rp.data(), A.row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost) != hipSuccess ||
@@ -33,10 +33,11 @@ bool vk_gcsr_plan(vk_level& L) {
     return false;
   }
   std::vector<int32_t> grow;
-  std::vector<int64_t> gcoff;
+  std::vector<int64_t> gcoff, gv0;
   std::vector<uint32_t> words;
   grow.reserve(n / 2 + 2);
   gcoff.reserve(n / 2 + 2);
+  gv0.reserve(n / 2 + 2);
   words.reserve(G.cap_words);
   int64_t r = 0;
   while (r < n) {
@@ -56,6 +57,7 @@ bool vk_gcsr_plan(vk_level& L) {
     if ((int64_t)words.size() + m > G.cap_words) return false;
     grow.push_back((int32_t)r);
     gcoff.push_back((int64_t)words.size());
+    gv0.push_back(e0);
     for (int64_t j = 0; j < m; ++j) {
       const uint32_t d = best > 1 ? (uint32_t)(col[e0 + m + j] - col[e0 + j]) : 0u;
       words.push_back((uint32_t)col[e0 + j] | (d << 31));
@@ -64,10 +66,12 @@ bool vk_gcsr_plan(vk_level& L) {
   }
   grow.push_back((int32_t)n);
   gcoff.push_back((int64_t)words.size());
+  gv0.push_back(nnz);
   const int64_t ng = (int64_t)grow.size() - 1;
   if (ng > G.cap_groups) return false;
   if (hipMemcpy(G.g_row, grow.data(), sizeof(int32_t) * (ng + 1), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(G.g_coff, gcoff.data(), sizeof(int64_t) * (ng + 1), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(G.g_v0, gv0.data(), sizeof(int64_t) * (ng + 1), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(G.gcol, words.data(), sizeof(uint32_t) * words.size(), hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipGetLastError();
     return false;

@@ -61,12 +61,12 @@ __global__ __launch_bounds__(256) void spmv_kernel(int64_t n_rows, const int64_t
 // {0, 1} (in a dG slab matrix: the velocity components of one node, or the pressure modes of one
 // cell).  The group's column list is stored once, gcol[g_coff[g] + j] = col[r][j] | d_j << 31; the
 // values are the CSR values as they are (the rows are consecutive, so row r + c's entries start at
-// row_ptr[r] + c m).  LPR lanes per group, each takes entry j of all G rows: one 4-byte column word
-// serves G values.
+// row_ptr[r] + c m; g_v0[g] = row_ptr[r] is stored with the group).  LPR lanes per group, each
+// takes entry j of all G rows: one 4-byte column word serves G values.
 template <int LPR>
 __global__ __launch_bounds__(256) void spmv_g_kernel(int64_t n_groups, const int32_t* __restrict__ g_row,
                                                      const int64_t* __restrict__ g_coff,
-                                                     const int64_t* __restrict__ row_ptr,
+                                                     const int64_t* __restrict__ g_v0,
                                                      const uint32_t* __restrict__ gcol,
                                                      const double* __restrict__ val, const double* __restrict__ x,
                                                      double alpha, double beta, const double* z, double* y) {
@@ -79,7 +79,8 @@ __global__ __launch_bounds__(256) void spmv_g_kernel(int64_t n_groups, const int
   if (g < n_groups) {
     r = g_row[g];
     G = g_row[g + 1] - (int)r;
-    const int64_t v0 = row_ptr[r], m = row_ptr[r + 1] - v0, c0 = g_coff[g];
+    // independent loads: the group's rows, column list and first value (no chain through row_ptr)
+    const int64_t c0 = g_coff[g], m = g_coff[g + 1] - c0, v0 = g_v0[g];
     const double* v = val + v0;
     int64_t j = lane;
     // x at the group's column of entry jj, for rows 0..3 of the group: unshifted columns (d = 0,
@@ -237,7 +238,7 @@ hipError_t launch_spmv_g(hipStream_t s, const vk_csr& A, const vk_gcsr& g, int l
   if (g.n_groups == 0) return hipSuccess;
   const unsigned grid = grid_for(g.n_groups * lpr, 256);
 #define VK_SPMV_G(LL)                                                                                 \
-  spmv_g_kernel<LL><<<grid, 256, 0, s>>>(g.n_groups, g.g_row, g.g_coff, A.row_ptr, g.gcol, A.val, x, alpha, \
+  spmv_g_kernel<LL><<<grid, 256, 0, s>>>(g.n_groups, g.g_row, g.g_coff, g.g_v0, g.gcol, A.val, x, alpha, \
                                         beta, z, y)
   switch (lpr) {
     case 4: VK_SPMV_G(4); break;

@@ -135,6 +135,7 @@ struct vk_gcsr {
   int64_t cap_words = 0, cap_groups = 0;  // reserved space
   int32_t* g_row = nullptr;               // n_groups + 1 first rows
   int64_t* g_coff = nullptr;              // n_groups + 1 column-list offsets
+  int64_t* g_v0 = nullptr;                // n_groups first value offsets (row_ptr of the first row)
   uint32_t* gcol = nullptr;               // column words
 };
 
