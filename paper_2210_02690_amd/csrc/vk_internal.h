@@ -150,11 +150,17 @@ struct vk_bt {
   int nb = 0;
   int64_t smax = 0;
   double flops = 0.0;                     // algorithmic flop count of one factorisation
+  int c = 0;                              // the middle block: both chains end there
   std::vector<int64_t> off, oD, oU, oL;   // block offsets (new order); element offsets of D_i, U_i, L_i
-  double *D = nullptr, *Dinv = nullptr, *U = nullptr, *X = nullptr, *Lc = nullptr;
-  double *bp = nullptr, *y = nullptr, *xp = nullptr, *w = nullptr;  // solve vectors
+  double *D = nullptr, *Dinv = nullptr, *U = nullptr, *X = nullptr, *Lc = nullptr, *Y = nullptr;
+  double *bp = nullptr, *y = nullptr, *xp = nullptr, *w = nullptr;  // solve vectors (w: 2 smax)
   int32_t *perm = nullptr, *iperm = nullptr;                         // new -> old, old -> new
-  int64_t *d_off = nullptr, *d_oD = nullptr, *d_oU = nullptr, *d_oL = nullptr, *d_rows = nullptr;
+  int64_t *d_off = nullptr, *d_oD = nullptr, *d_oU = nullptr, *d_oL = nullptr;
+  // elimination steps: step k inverts the left chain's block pa[k] and the right chain's pb[k]
+  // (-1: none) in one launch sequence; the last step the middle block.  Per step, device row
+  // offsets (3) and dense-block offsets (2) of the pair
+  std::vector<int> pa, pb;
+  int64_t *d_prows = nullptr, *d_pwoff = nullptr;
 };
 
 struct vk_level {
