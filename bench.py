@@ -356,6 +356,7 @@ def run_pmc_probe(args, torch, vk, dev):
     print(json.dumps({"probe": args.config, "copy_bytes_per_launch": 2 * n * 8, "copy_launches": 3,
                       "sweeps": 20, "patch_gemv_bytes_per_launch": patch_gemv_bytes(P.finest, args.prec),
                       "spmv_bytes_per_launch": spmv_bytes(P.finest),
+                      "spmv_stored_bytes_per_launch": S.vk_spmv_bytes(l),
                       "dof_gather_bytes_per_launch": gather_bytes(P.finest, args.prec),
                       "sweep_bytes": sweep_bytes(P.finest, args.prec),
                       "finest_cells": P.finest.mesh.n_cells}), flush=True)
