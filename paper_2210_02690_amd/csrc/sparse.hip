@@ -63,7 +63,26 @@ __global__ __launch_bounds__(256) void spmv_kernel(int64_t n_rows, const int64_t
 // values are the CSR values as they are (the rows are consecutive, so row r + c's entries start at
 // row_ptr[r] + c m; g_v0[g] = row_ptr[r] is stored with the group).  LPR lanes per group, each
 // takes entry j of all G rows: one 4-byte column word serves G values.
-template <int LPR>
+// sum over the 64 lanes, complete in lane 63: DPP shifts within rows of 16, then row broadcasts
+__device__ inline double wave_sum_to63(double v) {
+  v += dpp_move<0x111, 0xF>(v, 0.0);
+  v += dpp_move<0x112, 0xF>(v, 0.0);
+  v += dpp_move<0x114, 0xF>(v, 0.0);
+  v += dpp_move<0x118, 0xF>(v, 0.0);
+  v += dpp_move<0x142, 0xA>(v, 0.0);
+  v += dpp_move<0x143, 0xC>(v, 0.0);
+  return v;
+}
+
+__device__ inline double readlane_d(double v, int l) {
+  const int2 a = __builtin_bit_cast(int2, v);
+  int2 r;
+  r.x = __builtin_amdgcn_readlane(a.x, l);
+  r.y = __builtin_amdgcn_readlane(a.y, l);
+  return __builtin_bit_cast(double, r);
+}
+
+template <int LPR, bool NTL>
 __global__ __launch_bounds__(256) void spmv_g_kernel(int64_t n_groups, const int32_t* __restrict__ g_row,
                                                      const int64_t* __restrict__ g_coff,
                                                      const int64_t* __restrict__ g_v0,
@@ -95,42 +114,59 @@ __global__ __launch_bounds__(256) void spmv_g_kernel(int64_t n_groups, const int
         if (G > 3) xv[3] = x[b + 3];
       }
     };
-    // two entries per lane and iteration: their value loads and gathers in flight together
+    // two entries per lane and iteration: their value loads and gathers in flight together.  For
+    // a matrix far larger than the last-level cache the values and column words, read once, are
+    // loaded non-temporally (leaving the caches to x); a smaller one stays cacheable, since the
+    // next product can find it in the 256 MB cache
+    auto ldv = [&](int64_t i) { return NTL ? __builtin_nontemporal_load(v + i) : v[i]; };
+    auto ldc = [&](int64_t i) { return NTL ? __builtin_nontemporal_load(gcol + i) : gcol[i]; };
     for (; j + LPR < m; j += 2 * LPR) {
-      const uint32_t ca = gcol[c0 + j], cb = gcol[c0 + j + LPR];
+      const uint32_t ca = ldc(c0 + j), cb = ldc(c0 + j + LPR);
       double xa[4], xb[4];
       xg(ca, xa);
       xg(cb, xb);
-      s0 = fma(v[j], xa[0], s0);
-      s0 = fma(v[j + LPR], xb[0], s0);
+      s0 = fma(ldv(j), xa[0], s0);
+      s0 = fma(ldv(j + LPR), xb[0], s0);
       if (G > 1) {
-        s1 = fma(v[m + j], xa[1], s1);
-        s1 = fma(v[m + j + LPR], xb[1], s1);
+        s1 = fma(ldv(m + j), xa[1], s1);
+        s1 = fma(ldv(m + j + LPR), xb[1], s1);
       }
       if (G > 2) {
-        s2 = fma(v[2 * m + j], xa[2], s2);
-        s2 = fma(v[2 * m + j + LPR], xb[2], s2);
+        s2 = fma(ldv(2 * m + j), xa[2], s2);
+        s2 = fma(ldv(2 * m + j + LPR), xb[2], s2);
       }
       if (G > 3) {
-        s3 = fma(v[3 * m + j], xa[3], s3);
-        s3 = fma(v[3 * m + j + LPR], xb[3], s3);
+        s3 = fma(ldv(3 * m + j), xa[3], s3);
+        s3 = fma(ldv(3 * m + j + LPR), xb[3], s3);
       }
     }
     if (j < m) {
       double xa[4];
-      xg(gcol[c0 + j], xa);
-      s0 = fma(v[j], xa[0], s0);
-      if (G > 1) s1 = fma(v[m + j], xa[1], s1);
-      if (G > 2) s2 = fma(v[2 * m + j], xa[2], s2);
-      if (G > 3) s3 = fma(v[3 * m + j], xa[3], s3);
+      xg(ldc(c0 + j), xa);
+      s0 = fma(ldv(j), xa[0], s0);
+      if (G > 1) s1 = fma(ldv(m + j), xa[1], s1);
+      if (G > 2) s2 = fma(ldv(2 * m + j), xa[2], s2);
+      if (G > 3) s3 = fma(ldv(3 * m + j), xa[3], s3);
     }
   }
+  if constexpr (LPR == 64) {
+    // one group per wavefront: DPP sums (rows of 16, then across rows), read from lane 63
+    s0 = wave_sum_to63(s0);
+    s1 = wave_sum_to63(s1);
+    s2 = wave_sum_to63(s2);
+    s3 = wave_sum_to63(s3);
+    s0 = readlane_d(s0, 63);
+    s1 = readlane_d(s1, 63);
+    s2 = readlane_d(s2, 63);
+    s3 = readlane_d(s3, 63);
+  } else {
 #pragma unroll
-  for (int o = LPR / 2; o > 0; o >>= 1) {
-    s0 += __shfl_xor(s0, o, LPR);
-    s1 += __shfl_xor(s1, o, LPR);
-    s2 += __shfl_xor(s2, o, LPR);
-    s3 += __shfl_xor(s3, o, LPR);
+    for (int o = LPR / 2; o > 0; o >>= 1) {
+      s0 += __shfl_xor(s0, o, LPR);
+      s1 += __shfl_xor(s1, o, LPR);
+      s2 += __shfl_xor(s2, o, LPR);
+      s3 += __shfl_xor(s3, o, LPR);
+    }
   }
   if (g < n_groups && lane < G) {
     const double sum = lane == 0 ? s0 : (lane == 1 ? s1 : (lane == 2 ? s2 : s3));
@@ -237,9 +273,14 @@ hipError_t launch_spmv_g(hipStream_t s, const vk_csr& A, const vk_gcsr& g, int l
                          double beta, const double* z, double* y) {
   if (g.n_groups == 0) return hipSuccess;
   const unsigned grid = grid_for(g.n_groups * lpr, 256);
-#define VK_SPMV_G(LL)                                                                                 \
-  spmv_g_kernel<LL><<<grid, 256, 0, s>>>(g.n_groups, g.g_row, g.g_coff, g.g_v0, g.gcol, A.val, x, alpha, \
-                                        beta, z, y)
+  const bool ntl = A.nnz * 12 > (1ll << 30);  // well beyond the 256 MB last-level cache
+#define VK_SPMV_G(LL)                                                                                          \
+  if (ntl)                                                                                                     \
+    spmv_g_kernel<LL, true><<<grid, 256, 0, s>>>(g.n_groups, g.g_row, g.g_coff, g.g_v0, g.gcol, A.val, x, alpha, \
+                                                  beta, z, y);                                                  \
+  else                                                                                                         \
+    spmv_g_kernel<LL, false><<<grid, 256, 0, s>>>(g.n_groups, g.g_row, g.g_coff, g.g_v0, g.gcol, A.val, x,      \
+                                                   alpha, beta, z, y)
   switch (lpr) {
     case 4: VK_SPMV_G(4); break;
     case 8: VK_SPMV_G(8); break;
