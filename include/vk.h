@@ -295,7 +295,10 @@ vk_status vk_set_coarse_pivoting(vk_ctx* ctx, int32_t mode);
  * components of one node, the pressure modes of one cell) share one column
  * list, so one 4-byte column word serves up to four 8-byte values; the values
  * are J's CSR values as given.  The autotuner then times it against CSR.
- * 0: CSR everywhere.  Both compute the same products up to summation order. */
+ * 4, 8, 16, 32 or 64: the grouped CSR with that many lanes per row group on
+ * every level that has one (the autotuner then times only that count against
+ * CSR; 1 returns the choice to the library).  0: CSR everywhere.  All compute
+ * the same products up to summation order; VK_ERR_ARG for any other value. */
 vk_status vk_set_spmv_format(vk_ctx* ctx, int32_t grouped);
 
 /* 0 if level `level`'s J products use CSR, else the lanes per row group of the

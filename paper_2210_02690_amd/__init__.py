@@ -348,8 +348,10 @@ class Solver:
         self._check(_lib.vk_set_coarse_pivoting(self.ctx, mode))
 
     def vk_set_spmv_format(self, grouped):
-        """1: grouped CSR for the J products of large levels (default); 0: CSR everywhere."""
-        self._check(_lib.vk_set_spmv_format(self.ctx, 1 if grouped else 0))
+        """1 (or True): grouped CSR for the J products of large levels, lanes per group chosen by
+        the library (default); 4, 8, 16, 32 or 64: the grouped CSR with that many lanes per group;
+        0 (or False): CSR everywhere."""
+        self._check(_lib.vk_set_spmv_format(self.ctx, int(grouped)))
 
     def vk_spmv_format(self, level):
         """0: CSR; otherwise the lanes per row group of the grouped CSR in use on that level."""

@@ -934,7 +934,8 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
       VK_TRY(hipStreamSynchronize(s));  // the last solve may still read the old plan
       if (vk_gcsr_plan(L)) {
         L.use_gJ = ctx->spmv_grouped;
-        L.lpr_gJ = vk_pick_lpr_g(L.J.nnz, L.J.n_rows);
+        L.lpr_gJ_lib = vk_pick_lpr_g(L.J.nnz, L.J.n_rows);
+        L.lpr_gJ = ctx->spmv_lanes ? ctx->spmv_lanes : L.lpr_gJ_lib;
       } else {
         L.use_gJ = false;
       }
@@ -1396,12 +1397,14 @@ vk_status vk_autotune(vk_ctx* ctx, int32_t reps) {
     if (L.gJ.active && ctx->spmv_grouped) {  // the grouped format against the best CSR launch
       float tb = time_ms([&] { return launch_spmv(s, L.J, L.lpr_J, 1.0, L.b, 0.0, nullptr, L.r); });
       L.use_gJ = false;
-      for (int lpr : {8, 16, 32, 64}) {
+      for (int lpr : {4, 8, 16, 32, 64}) {
+        if (ctx->spmv_lanes ? lpr != ctx->spmv_lanes : lpr == 4) continue;  // 4: only when asked for
         const float t = time_ms([&] { return launch_spmv_g(s, L.J, L.gJ, lpr, 1.0, L.b, 0.0, nullptr, L.r); });
         if (t < tb) {
           tb = t;
           L.use_gJ = true;
           L.lpr_gJ = lpr;
+          if (!ctx->spmv_lanes) L.lpr_gJ_lib = lpr;
         }
       }
     }
@@ -1506,10 +1509,15 @@ vk_status vk_set_setup_variant(vk_ctx* ctx, int32_t variant) {
 
 vk_status vk_set_spmv_format(vk_ctx* ctx, int32_t grouped) {
   if (!ctx) return VK_ERR_ARG;
-  if (grouped != 0 && grouped != 1) return fail(ctx, VK_ERR_ARG, "grouped must be 0 or 1");
+  if (grouped != 0 && grouped != 1 && grouped != 4 && grouped != 8 && grouped != 16 && grouped != 32 && grouped != 64)
+    return fail(ctx, VK_ERR_ARG, "grouped must be 0, 1, 4, 8, 16, 32 or 64");
   ++ctx->gen;
   ctx->spmv_grouped = grouped != 0;
-  for (vk_level& L : ctx->lv) L.use_gJ = ctx->spmv_grouped && L.gJ.active;
+  ctx->spmv_lanes = grouped > 1 ? grouped : 0;
+  for (vk_level& L : ctx->lv) {
+    L.use_gJ = ctx->spmv_grouped && L.gJ.active;
+    if (L.gJ.active) L.lpr_gJ = ctx->spmv_lanes ? ctx->spmv_lanes : L.lpr_gJ_lib;
+  }
   return VK_OK;
 }
 

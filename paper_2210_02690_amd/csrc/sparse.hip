@@ -176,6 +176,96 @@ __global__ __launch_bounds__(256) void spmv_g_kernel(int64_t n_groups, const int
   }
 }
 
+// One group per wavefront (64 lanes per group, the J of 3D patches with rows of a few hundred
+// entries).  The group is the same for the whole wavefront, so its description is read with scalar
+// loads and its size G selects straight-line code: per iteration a lane takes entries j and j + 64
+// of all G rows, issues the column words and all 2 G value loads first and then the gathers of x,
+// so the values stream while the gathers wait on their column words.  A lane past the row's end
+// reads the last entry again and keeps its sums (the order of the additions is that of
+// spmv_g_kernel).  x of a shifted entry's rows 1..G-1 is loaded only on the lanes that need it,
+// into registers that start at zero, so no loaded value is copied before the wait for it.
+template <int G, bool NTL>
+__device__ inline void group_dot64(int lane, int64_t m, const uint32_t* __restrict__ gc,
+                                   const double* __restrict__ v, const double* __restrict__ x, double (&s)[4]) {
+  auto ldv = [&](int64_t i) { return NTL ? __builtin_nontemporal_load(v + i) : v[i]; };
+  auto ldc = [&](int64_t i) { return NTL ? __builtin_nontemporal_load(gc + i) : gc[i]; };
+  for (int64_t jb = 0; jb < m; jb += 128) {
+    const int64_t ja = jb + lane, jc = ja + 64;
+    const bool oka = ja < m, okc = jc < m;
+    const int64_t ia = oka ? ja : m - 1, ic = okc ? jc : m - 1;
+    const uint32_t ca = ldc(ia), cc = ldc(ic);
+    double va[G], vc[G];
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+      va[c] = ldv(c * m + ia);
+      vc[c] = ldv(c * m + ic);
+    }
+    const int64_t ba = (int64_t)(ca & 0x7fffffffu), bc = (int64_t)(cc & 0x7fffffffu);
+    // the shifted entries' loads go first: the gathers at the columns come after the branches, so
+    // the choice between the two cannot be folded into a branch's default value (which would copy
+    // a gather, and wait for it, before the other lane set's loads issue)
+    double xa[G], xc[G];
+#pragma unroll
+    for (int c = 0; c < G; ++c) xa[c] = xc[c] = 0.0;
+    if (G > 1 && (ca >> 31)) {
+#pragma unroll
+      for (int c = 1; c < G; ++c) xa[c] = x[ba + c];
+    }
+    if (G > 1 && (cc >> 31)) {
+#pragma unroll
+      for (int c = 1; c < G; ++c) xc[c] = x[bc + c];
+    }
+    const double xa0 = x[ba], xc0 = x[bc];
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+      const double ea = c == 0 || !(ca >> 31) ? xa0 : xa[c];
+      const double ec = c == 0 || !(cc >> 31) ? xc0 : xc[c];
+      const double pa = fma(va[c], ea, s[c]);
+      s[c] = oka ? pa : s[c];
+      const double pc = fma(vc[c], ec, s[c]);
+      s[c] = okc ? pc : s[c];
+    }
+  }
+}
+
+__device__ inline int64_t uniform64(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const int hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+template <bool NTL>
+__global__ __launch_bounds__(256) void spmv_g64_kernel(int64_t n_groups, const int32_t* __restrict__ g_row,
+                                                       const int64_t* __restrict__ g_coff,
+                                                       const int64_t* __restrict__ g_v0,
+                                                       const uint32_t* __restrict__ gcol,
+                                                       const double* __restrict__ val,
+                                                       const double* __restrict__ x, double alpha, double beta,
+                                                       const double* z, double* y) {
+  const int64_t g = (int64_t)xcd_block(blockIdx.x, gridDim.x) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (g >= n_groups) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t r = g_row[g];
+  const int G = (int)(g_row[g + 1] - r);
+  const int64_t c0 = uniform64(g_coff[g]), m = uniform64(g_coff[g + 1]) - c0, v0 = uniform64(g_v0[g]);
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  switch (__builtin_amdgcn_readfirstlane(G)) {
+    case 4: group_dot64<4, NTL>(lane, m, gcol + c0, val + v0, x, s); break;
+    case 3: group_dot64<3, NTL>(lane, m, gcol + c0, val + v0, x, s); break;
+    case 2: group_dot64<2, NTL>(lane, m, gcol + c0, val + v0, x, s); break;
+    default: group_dot64<1, NTL>(lane, m, gcol + c0, val + v0, x, s); break;
+  }
+  double t[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) t[c] = c < G ? readlane_d(wave_sum_to63(s[c]), 63) : 0.0;
+  if (lane < G) {
+    const double sum = lane == 0 ? t[0] : (lane == 1 ? t[1] : (lane == 2 ? t[2] : t[3]));
+    double out = alpha * sum;
+    if (beta != 0.0) out += beta * z[r + lane];
+    y[r + lane] = out;
+  }
+}
+
 __global__ void validate_csr_kernel(int64_t n_rows, int64_t n_cols, int64_t nnz,
                                     const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                                     int32_t* flag) {
@@ -286,7 +376,14 @@ hipError_t launch_spmv_g(hipStream_t s, const vk_csr& A, const vk_gcsr& g, int l
     case 8: VK_SPMV_G(8); break;
     case 16: VK_SPMV_G(16); break;
     case 32: VK_SPMV_G(32); break;
-    default: VK_SPMV_G(64); break;
+    default:
+      if (ntl)
+        spmv_g64_kernel<true><<<grid, 256, 0, s>>>(g.n_groups, g.g_row, g.g_coff, g.g_v0, g.gcol, A.val, x, alpha,
+                                                   beta, z, y);
+      else
+        spmv_g64_kernel<false><<<grid, 256, 0, s>>>(g.n_groups, g.g_row, g.g_coff, g.g_v0, g.gcol, A.val, x, alpha,
+                                                    beta, z, y);
+      break;
   }
 #undef VK_SPMV_G
   return hipGetLastError();

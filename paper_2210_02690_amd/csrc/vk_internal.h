@@ -175,7 +175,8 @@ struct vk_level {
   int lpr_J = 4, lpr_P = 4, lpr_R = 4;
   vk_gcsr gJ;           // grouped CSR of J, used by the J products while gJ.active and use_gJ
   bool use_gJ = false;
-  int lpr_gJ = 16;
+  int lpr_gJ = 16;      // lanes per group in use
+  int lpr_gJ_lib = 16;  // the library's own choice (planned, then autotuned)
   // carved from the workspace
   double* inv_p = nullptr;      // 1 / multiplicity
   int32_t* dof_off = nullptr;   // DoF -> (cell, local) lists: offsets (n + 1)
@@ -262,6 +263,7 @@ struct vk_ctx {
   int64_t coarse_min_tourney = VK_TOURNEY_MIN_N;  // blocks wider than this choose pivots by tournament
   int32_t coarse_solver = 0;  // 0: block-tridiagonal factorisation where it applies, 1: dense inverse
   bool spmv_grouped = true;   // J products through the grouped CSR where a plan exists
+  int spmv_lanes = 0;         // lanes per group of the grouped products (0: chosen per level)
   bool maps_ready = false;    // multiplicities and DoF lists (depend on the mesh only)
   // the block inversions of the last setup run on `side`; the first call that applies a
   // block makes `stream` wait for them, and the first synchronisation after that checks

@@ -108,12 +108,16 @@ def test_grouped_csr_products_176x32(vk):
         xt = torch.from_numpy(x).to(DEV)
         zt = torch.from_numpy(z).to(DEV)
         y = torch.empty_like(xt)
-        S.vk_spmv(l, xt, y)
         ref = J @ x
-        assert np.abs(y.cpu().numpy() - ref).max() <= 1e-13 * np.abs(ref).max()
-        S.vk_spmv(l, xt, y, alpha=-1.0, beta=1.0, z=zt)
         ref2 = z - J @ x
-        assert np.abs(y.cpu().numpy() - ref2).max() <= 1e-13 * np.abs(ref2).max()
+        # the library's choice of lanes per group, then every count (64: one group per wavefront)
+        for lanes in (1, 4, 8, 16, 32, 64):
+            S.vk_set_spmv_format(lanes)
+            assert lanes == 1 or S.vk_spmv_format(l) == lanes
+            S.vk_spmv(l, xt, y)
+            assert np.abs(y.cpu().numpy() - ref).max() <= 1e-13 * np.abs(ref).max(), lanes
+            S.vk_spmv(l, xt, y, alpha=-1.0, beta=1.0, z=zt)
+            assert np.abs(y.cpu().numpy() - ref2).max() <= 1e-13 * np.abs(ref2).max(), lanes
         S.vk_set_spmv_format(0)
         assert S.vk_spmv_format(l) == 0
         y2 = torch.empty_like(xt)
@@ -140,6 +144,22 @@ def test_box3d_full_sampled(vk):
             S.vk_get_patch_inverses(l, int(K), 1, out)
             ref = np.linalg.inv(oracle.patch_matrix(lv.J, lv.cell_dofs[K]))
             assert np.abs(out[0].cpu().numpy() - ref).max() <= 1e-10 * np.abs(ref).max(), (l, K)
+    # the finest J's products in the grouped CSR with one group per wavefront (the layout the
+    # autotuned solve picks for these rows; J is beyond the cache, so its streams load
+    # non-temporally) and with the library's own choice of lanes
+    xs = rng.standard_normal(F.n)
+    zs = rng.standard_normal(F.n)
+    xt, zt = torch.from_numpy(xs).to(DEV), torch.from_numpy(zs).to(DEV)
+    ys = torch.empty_like(xt)
+    ref = F.J @ xs
+    for lanes in (64, 1):
+        S.vk_set_spmv_format(lanes)
+        assert S.vk_spmv_format(L) > 0 and (lanes == 1 or S.vk_spmv_format(L) == lanes)
+        S.vk_spmv(L, xt, ys, alpha=-1.0, beta=1.0, z=zt)
+        err = np.abs(ys.cpu().numpy() - (zs - ref)).max() / np.abs(zs - ref).max()
+        _say(f"box3d grouped J product, lanes {S.vk_spmv_format(L)}: max rel err {err:.2e}")
+        assert err <= 1e-13, lanes
+    del xt, zt, ys
     # one additive sweep from a nonzero iterate: d'_mu = d_mu + omega / p_mu sum_{K ni mu} (A_K r_K)[mu]
     d0 = rng.standard_normal(F.n)
     d = torch.from_numpy(d0).to(DEV)
