@@ -178,53 +178,60 @@ __global__ __launch_bounds__(256) void spmv_g_kernel(int64_t n_groups, const int
 
 // One group per wavefront (64 lanes per group, the J of 3D patches with rows of a few hundred
 // entries).  The group is the same for the whole wavefront, so its description is read with scalar
-// loads and its size G selects straight-line code: per iteration a lane takes entries j and j + 64
-// of all G rows, issues the column words and all 2 G value loads first and then the gathers of x,
-// so the values stream while the gathers wait on their column words.  A lane past the row's end
-// reads the last entry again and keeps its sums (the order of the additions is that of
+// loads and its size G selects straight-line code: per iteration a lane takes entries j, j + 64, ..
+// j + 64 (E - 1) of all G rows, issues the column words and all E G value loads first and then the
+// gathers of x, so the values stream while the gathers wait on their column words.  A lane past the
+// row's end reads the last entry again and keeps its sums (the order of the additions is that of
 // spmv_g_kernel).  x of a shifted entry's rows 1..G-1 is loaded only on the lanes that need it,
-// into registers that start at zero, so no loaded value is copied before the wait for it.
-template <int G, bool NTL>
+// into registers that start at zero, so no loaded value is copied before the wait for it.  E = 2
+// keeps 8 wavefronts per SIMD (54 registers; E = 4 needs 94 and was slower).  With NTL the values,
+// read once, load non-temporally; the column words stay cacheable (a line of them is shared by
+// neighbouring groups).
+template <int G, int E, bool NTL>
 __device__ inline void group_dot64(int lane, int64_t m, const uint32_t* __restrict__ gc,
                                    const double* __restrict__ v, const double* __restrict__ x, double (&s)[4]) {
   auto ldv = [&](int64_t i) { return NTL ? __builtin_nontemporal_load(v + i) : v[i]; };
-  auto ldc = [&](int64_t i) { return NTL ? __builtin_nontemporal_load(gc + i) : gc[i]; };
-  for (int64_t jb = 0; jb < m; jb += 128) {
-    const int64_t ja = jb + lane, jc = ja + 64;
-    const bool oka = ja < m, okc = jc < m;
-    const int64_t ia = oka ? ja : m - 1, ic = okc ? jc : m - 1;
-    const uint32_t ca = ldc(ia), cc = ldc(ic);
-    double va[G], vc[G];
+  for (int64_t jb = 0; jb < m; jb += 64 * E) {
+    bool ok[E];
+    int64_t ie[E];
+    uint32_t cw[E];
 #pragma unroll
-    for (int c = 0; c < G; ++c) {
-      va[c] = ldv(c * m + ia);
-      vc[c] = ldv(c * m + ic);
+    for (int e = 0; e < E; ++e) {
+      const int64_t j = jb + lane + 64 * e;
+      ok[e] = j < m;
+      ie[e] = ok[e] ? j : m - 1;
+      cw[e] = gc[ie[e]];
     }
-    const int64_t ba = (int64_t)(ca & 0x7fffffffu), bc = (int64_t)(cc & 0x7fffffffu);
+    double vv[E][G];
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+#pragma unroll
+      for (int c = 0; c < G; ++c) vv[e][c] = ldv(c * m + ie[e]);
     // the shifted entries' loads go first: the gathers at the columns come after the branches, so
     // the choice between the two cannot be folded into a branch's default value (which would copy
-    // a gather, and wait for it, before the other lane set's loads issue)
-    double xa[G], xc[G];
+    // a gather, and wait for it, before the other entries' loads issue)
+    int64_t b[E];
+    double xs[E][G];
 #pragma unroll
-    for (int c = 0; c < G; ++c) xa[c] = xc[c] = 0.0;
-    if (G > 1 && (ca >> 31)) {
+    for (int e = 0; e < E; ++e) {
+      b[e] = (int64_t)(cw[e] & 0x7fffffffu);
 #pragma unroll
-      for (int c = 1; c < G; ++c) xa[c] = x[ba + c];
+      for (int c = 0; c < G; ++c) xs[e][c] = 0.0;
+      if (G > 1 && (cw[e] >> 31)) {
+#pragma unroll
+        for (int c = 1; c < G; ++c) xs[e][c] = x[b[e] + c];
+      }
     }
-    if (G > 1 && (cc >> 31)) {
+    double x0[E];
 #pragma unroll
-      for (int c = 1; c < G; ++c) xc[c] = x[bc + c];
-    }
-    const double xa0 = x[ba], xc0 = x[bc];
+    for (int e = 0; e < E; ++e) x0[e] = x[b[e]];
 #pragma unroll
-    for (int c = 0; c < G; ++c) {
-      const double ea = c == 0 || !(ca >> 31) ? xa0 : xa[c];
-      const double ec = c == 0 || !(cc >> 31) ? xc0 : xc[c];
-      const double pa = fma(va[c], ea, s[c]);
-      s[c] = oka ? pa : s[c];
-      const double pc = fma(vc[c], ec, s[c]);
-      s[c] = okc ? pc : s[c];
-    }
+    for (int c = 0; c < G; ++c)
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const double p = fma(vv[e][c], c == 0 || !(cw[e] >> 31) ? x0[e] : xs[e][c], s[c]);
+        s[c] = ok[e] ? p : s[c];
+      }
   }
 }
 
@@ -250,10 +257,10 @@ __global__ __launch_bounds__(256) void spmv_g64_kernel(int64_t n_groups, const i
   const int64_t c0 = uniform64(g_coff[g]), m = uniform64(g_coff[g + 1]) - c0, v0 = uniform64(g_v0[g]);
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   switch (__builtin_amdgcn_readfirstlane(G)) {
-    case 4: group_dot64<4, NTL>(lane, m, gcol + c0, val + v0, x, s); break;
-    case 3: group_dot64<3, NTL>(lane, m, gcol + c0, val + v0, x, s); break;
-    case 2: group_dot64<2, NTL>(lane, m, gcol + c0, val + v0, x, s); break;
-    default: group_dot64<1, NTL>(lane, m, gcol + c0, val + v0, x, s); break;
+    case 4: group_dot64<4, 2, NTL>(lane, m, gcol + c0, val + v0, x, s); break;
+    case 3: group_dot64<3, 2, NTL>(lane, m, gcol + c0, val + v0, x, s); break;
+    case 2: group_dot64<2, 2, NTL>(lane, m, gcol + c0, val + v0, x, s); break;
+    default: group_dot64<1, 2, NTL>(lane, m, gcol + c0, val + v0, x, s); break;
   }
   double t[4];
 #pragma unroll
