@@ -741,6 +741,10 @@ def main():
     from synth import build_problem
 
     dev = torch.device("cuda:0")
+    # The workload runs on a stream of its own (default priority), as a serving loop would: on the
+    # legacy default stream every launch would also wait for the library's CU-masked setup stream
+    # (a blocking stream), so the coarser levels' patch inversions could not overlap the solve.
+    torch.cuda.set_stream(torch.cuda.Stream(dev))
     if args.config == "batch64_seed0":
         return run_batch(args, torch, vk, dev)
     if args.config == "learned_guess_88x16":

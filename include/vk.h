@@ -166,11 +166,22 @@ vk_status vk_set_workspace(vk_ctx* ctx, void* dev, size_t bytes, vk_prec prec, i
  * direct solve (blocked Gauss-Jordan with partial pivoting: the largest |pivot|
  * up to a relative 2^-38, the lowest row among those).  omega is the
  * under-relaxation of Eq. 3.4 (the paper uses 0.7).
- * On a zero pivot in a patch returns VK_ERR_SINGULAR with *bad_level /
- * *bad_cell (host, may be NULL) naming the first failing level and cell.
  * The patch inversions run on an internal stream restricted to 7/8 of the
- * CUs (when the runtime supports CU masks), which the context's stream waits
- * for; vanka_setup synchronises for them only.  The inversion of the
+ * CUs (when the runtime supports CU masks), the finest level first; the
+ * context's stream waits for the finest level's, and vanka_setup synchronises
+ * for them only.  On a zero pivot in a finest-level patch it returns
+ * VK_ERR_SINGULAR with *bad_level / *bad_cell (host, may be NULL) naming the
+ * level and the first failing cell.  The coarser levels' inversions keep
+ * running beside the next solve's finest-level sweeps: the first call that
+ * smooths on such a level orders itself after its inversions, and a zero
+ * pivot there is reported by the next call that reads the library's status
+ * once every level has been waited for (gmres_solve and gmres_solve_batched
+ * at their convergence checks, vcycle, vanka_smooth, vanka_smooth_noalloc,
+ * vk_get_patch_inverses, vk_autotune): VK_ERR_SINGULAR naming the level and
+ * cell in the message, after which setup must run again.  Without the
+ * internal stream every level is checked by vanka_setup.  The internal stream
+ * is a blocking stream: work on the legacy default stream waits for it, so
+ * the overlap needs the context's stream to be another stream.  The inversion of the
  * directly solved blocks (the coarse matrix) keeps running on a second internal
  * stream and overlaps the start of the next solve; the first call that applies
  * a block (vcycle, gmres_solve, gmres_solve_batched, vk_get_coarse_inverse)

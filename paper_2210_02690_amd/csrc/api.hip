@@ -289,10 +289,63 @@ vk_status smooth(vk_ctx* ctx, int l, const double* b, double* d, int32_t sweeps,
   return smooth_with(ctx, l, b, d, sweeps, zero, workspace_bufs(ctx, l));
 }
 
+// Orders the context stream after level l's patch inversions of the last setup (no host wait);
+// l < 0: after every level's.  Their status words are read by the next patch_check.
+vk_status patch_wait(vk_ctx* ctx, int l) {
+  for (int k = 1; k < ctx->n_levels && ctx->patch_pending; ++k) {
+    if ((l >= 0 && k != l) || !((ctx->patch_pending >> k) & 1)) continue;
+    VK_TRY(hipStreamWaitEvent(ctx->stream, ctx->patch_ev[k], 0));
+    ctx->patch_pending &= ~(1ull << k);
+  }
+  return VK_OK;
+}
+
+// For the direct entry points (which may run under a caller's graph capture): the host waits for
+// the setup stream itself and reads the status words through it, leaving the context stream
+// untouched; afterwards nothing is pending.  report = false discards what it finds.
+vk_status patch_settle(vk_ctx* ctx, bool report) {
+  if (!ctx->patch_pending && !ctx->patch_check_due) return VK_OK;
+  const bool due = ctx->patch_check_due;
+  ctx->patch_pending = 0;
+  ctx->patch_check_due = false;
+  VK_TRY(hipMemcpyAsync(ctx->pinned, ctx->status + 64, 64 * sizeof(int32_t), hipMemcpyDeviceToHost, ctx->setup));
+  VK_TRY(hipStreamSynchronize(ctx->setup));
+  if (!report || !due) return VK_OK;
+  const int32_t* st = reinterpret_cast<const int32_t*>(ctx->pinned);
+  for (int l = 1; l < ctx->n_levels; ++l)
+    if (st[l] != INT_MAX) {
+      ctx->setup_done = false;
+      char buf[128];
+      snprintf(buf, sizeof(buf), "patch matrix of cell %d on level %d is singular (zero pivot)", st[l], l);
+      return fail(ctx, VK_ERR_SINGULAR, buf);
+    }
+  return VK_OK;
+}
+
+vk_status to_host(vk_ctx* ctx, void* dst, const void* src, size_t bytes);
+
+// Singular patches of the levels whose inversions vanka_setup left running: read once every such
+// level has been waited for (synchronises the context stream then).
+vk_status patch_check(vk_ctx* ctx) {
+  if (!ctx->patch_check_due || ctx->patch_pending) return VK_OK;
+  int32_t st[64];
+  VK_CHECK(to_host(ctx, st, ctx->status + 64, sizeof(st)));
+  ctx->patch_check_due = false;
+  for (int l = 1; l < ctx->n_levels; ++l)
+    if (st[l] != INT_MAX) {
+      ctx->setup_done = false;
+      char buf[128];
+      snprintf(buf, sizeof(buf), "patch matrix of cell %d on level %d is singular (zero pivot)", st[l], l);
+      return fail(ctx, VK_ERR_SINGULAR, buf);
+    }
+  return VK_OK;
+}
+
 vk_status smooth_with(vk_ctx* ctx, int l, const double* b, double* d, int32_t sweeps, bool zero,
                       const sweep_bufs& buf) {
   vk_level& L = ctx->lv[l];
   hipStream_t s = ctx->stream;
+  if ((ctx->patch_pending >> l) & 1) VK_CHECK(patch_wait(ctx, l));
   // from d = 0 the first additive DoF-gather sweep writes d instead of adding to a zeroed d
   const bool gather = ctx->sweep_variant != VK_SWEEP_COLOURED_SCATTER;
   const bool write_first = zero && sweeps > 0 && ctx->mode == VK_ADDITIVE && gather;
@@ -437,7 +490,7 @@ vk_status replay(vk_ctx* ctx, size_t slot, const int64_t (&key)[6], F&& enqueue)
   if (!ctx->graphs || ctx->timing) return enqueue();
   // While the last setup's block inversion is still running, the step runs eagerly: its work up to
   // the coarse solve then overlaps the inversion (a replay would have to wait for it first).
-  if (ctx->coarse_pending) return enqueue();
+  if (ctx->coarse_pending || ctx->patch_pending) return enqueue();
   if (ctx->gslots.size() <= slot) ctx->gslots.resize(slot + 1);
   vk_ctx::graph_slot& g = ctx->gslots[slot];
   const bool hit = g.exec && g.gen == ctx->gen && std::equal(key, key + 6, g.key);
@@ -490,7 +543,9 @@ vk_status coarse_wait(vk_ctx* ctx, bool check_now) {
 
 // Status of the block inversions: [0] pivot failure, [1] coupling outside a block.  Call
 // after coarse_wait; synchronises the stream.
+vk_status patch_check(vk_ctx* ctx);
 vk_status coarse_check(vk_ctx* ctx) {
+  VK_CHECK(patch_check(ctx));
   if (!ctx->coarse_check_due) return VK_OK;
   int32_t st[2];
   VK_CHECK(to_host(ctx, st, ctx->status, sizeof(st)));
@@ -568,7 +623,6 @@ vk_status vk_create(vk_ctx** out, int32_t n_levels, void* hip_stream) {
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->setup_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->la.aux, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->la.gathered, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->la.bulk_done, hipEventDisableTiming);
@@ -580,7 +634,6 @@ vk_status vk_create(vk_ctx** out, int32_t n_levels, void* hip_stream) {
     if (ctx->la.bulk_done) (void)hipEventDestroy(ctx->la.bulk_done);
     if (ctx->la.gathered) (void)hipEventDestroy(ctx->la.gathered);
     if (ctx->la.aux) (void)hipStreamDestroy(ctx->la.aux);
-    if (ctx->setup_ev) (void)hipEventDestroy(ctx->setup_ev);
     if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
     if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
@@ -608,7 +661,7 @@ void vk_destroy(vk_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->setup);
     (void)hipStreamDestroy(ctx->setup);
   }
-  if (ctx->setup_ev) (void)hipEventDestroy(ctx->setup_ev);
+  for (hipEvent_t e : ctx->patch_ev) (void)hipEventDestroy(e);
   if (ctx->side) (void)hipStreamSynchronize(ctx->side);
   if (ctx->la.aux) {
     (void)hipStreamSynchronize(ctx->la.aux);
@@ -641,6 +694,8 @@ vk_status vk_set_level_groups(vk_ctx* ctx, int32_t l, const vk_csr* J, const vk_
   if (ctx->setup) (void)hipStreamSynchronize(ctx->setup);  // and patch inversions after a failed setup
   ctx->coarse_pending = false;
   ctx->coarse_check_due = false;
+  ctx->patch_pending = 0;
+  ctx->patch_check_due = false;
   if (l < 0 || l >= ctx->n_levels) return fail(ctx, VK_ERR_ARG, "level index out of range");
   if (!csr_ok(J) || J->n_rows != J->n_cols || J->n_rows == 0)
     return fail(ctx, VK_ERR_ARG, "J must be a non-empty square CSR matrix with valid pointers");
@@ -786,6 +841,8 @@ vk_status vk_set_workspace(vk_ctx* ctx, void* dev, size_t bytes, vk_prec prec, i
   if (ctx->setup) (void)hipStreamSynchronize(ctx->setup);  // and patch inversions after a failed setup
   ctx->coarse_pending = false;
   ctx->coarse_check_due = false;
+  ctx->patch_pending = 0;
+  ctx->patch_check_due = false;
   if (prec != VK_F64 && prec != VK_F32 && prec != VK_BF16) return fail(ctx, VK_ERR_ARG, "unknown precision");
   if (restart < 1 || restart > VK_MAX_RESTART) return fail(ctx, VK_ERR_ARG, "restart must be in [1, 64]");
   std::string why;
@@ -831,6 +888,7 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
   ctx->setup_done = false;
   // the previous setup's block inversions (and their status words) come before this one's
   VK_CHECK(coarse_wait(ctx, false));
+  VK_CHECK(patch_settle(ctx, false));  // the last setup's coarser levels still write their status words
   ctx->coarse_check_due = false;
   // recorded graphs stay valid across setups unless omega, the mode or where an inverse lives changes
   if (omega != ctx->omega || mode != ctx->mode) ++ctx->gen;
@@ -899,7 +957,17 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
       if (L.ell_w > 0) VK_TRY(launch_dof_ell(ps, L));
     }
   }
-  for (int l = 1; l < ctx->n_levels; ++l) {
+  // The finest level first: the context stream waits for its inversions alone, while the coarser
+  // levels' run on beside the first V-cycle's finest-level sweeps (each level's event is waited
+  // for where that level is first smoothed).
+  if (ps != s && ctx->patch_ev.size() < (size_t)ctx->n_levels) {
+    for (size_t l = ctx->patch_ev.size(); l < (size_t)ctx->n_levels; ++l) {
+      hipEvent_t e = nullptr;
+      VK_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      ctx->patch_ev.push_back(e);
+    }
+  }
+  for (int l = ctx->n_levels - 1; l >= 1; --l) {
     vk_level& L = ctx->lv[l];
     Timed t(ctx, VK_KERNEL_PATCH_SETUP, l, ps);
     for (const vk_group& G : L.groups) {
@@ -916,10 +984,16 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
       if (!handled)
         VK_TRY(launch_patch_setup(ps, L.J, G, ctx->prec, ctx->big_scratch, ctx->big_chunk, ctx->status + 64 + l));
     }
+    if (ps != s) VK_TRY(hipEventRecord(ctx->patch_ev[l], ps));
   }
+  ctx->patch_pending = 0;
+  ctx->patch_check_due = false;
   if (ps != s) {
-    VK_TRY(hipEventRecord(ctx->setup_ev, ps));
-    VK_TRY(hipStreamWaitEvent(s, ctx->setup_ev, 0));
+    const int lf = ctx->n_levels - 1;
+    VK_TRY(hipStreamWaitEvent(s, ctx->patch_ev[lf], 0));
+    for (int l = 1; l < lf; ++l)
+      if (!ctx->lv[l].groups.empty()) ctx->patch_pending |= 1ull << l;
+    ctx->patch_check_due = ctx->patch_pending != 0;
   }
   // Block inversions on the side streams, concurrent with the patch inversions (enqueued after
   // them, so the host's launch work does not hold the patch kernels back).  The levels' chains are
@@ -1001,6 +1075,7 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
   int32_t st[64];
   VK_CHECK(to_host(ctx, st, ctx->status + 64, sizeof(st)));
   for (int l = 1; l < ctx->n_levels; ++l) {
+    if ((ctx->patch_pending >> l) & 1) continue;  // still running: read by the first solve
     if (st[l] != INT_MAX) {
       if (bad_level) *bad_level = l;
       if (bad_cell) *bad_cell = st[l];
@@ -1016,6 +1091,7 @@ vk_status vanka_setup(vk_ctx* ctx, double omega, vk_mode mode, int32_t* bad_leve
 
 vk_status vanka_smooth(vk_ctx* ctx, int32_t l, const double* b, double* d, int32_t sweeps, int32_t d_is_zero) {
   VK_CHECK(ready(ctx));
+  VK_CHECK(patch_settle(ctx, true));
   if (l < 1 || l >= ctx->n_levels) return fail(ctx, VK_ERR_ARG, "smoothing needs a level >= 1");
   if (!b || !d || sweeps < 0) return fail(ctx, VK_ERR_ARG, "null vector or negative sweep count");
   if (d_is_zero) {
@@ -1031,6 +1107,7 @@ vk_status vanka_smooth(vk_ctx* ctx, int32_t l, const double* b, double* d, int32
 vk_status vanka_smooth_noalloc(vk_ctx* ctx, int32_t l, const double* b, double* d, int32_t sweeps,
                                int32_t d_is_zero) {
   VK_CHECK(ready(ctx));
+  VK_CHECK(patch_settle(ctx, true));
   if (l < 1 || l >= ctx->n_levels) return fail(ctx, VK_ERR_ARG, "smoothing needs a level >= 1");
   if (!b || !d || sweeps < 0) return fail(ctx, VK_ERR_ARG, "null vector or negative sweep count");
   if (!ctx->noalloc) return fail(ctx, VK_ERR_STATE, "no fixed scratch on this device");
@@ -1061,6 +1138,7 @@ vk_status vcycle(vk_ctx* ctx, const double* b, double* x, int32_t nu_pre, int32_
   VK_CHECK(ready(ctx));
   if (!b || !x || b == x) return fail(ctx, VK_ERR_ARG, "b and x must be distinct non-null vectors");
   if (nu_pre < 0 || nu_post < 0) return fail(ctx, VK_ERR_ARG, "negative sweep count");
+  VK_CHECK(patch_settle(ctx, true));
   VK_CHECK(coarse_wait(ctx, true));
   const int64_t key[6] = {(int64_t)(uintptr_t)b, (int64_t)(uintptr_t)x, nu_pre, nu_post, 0, 0};
   return replay(ctx, 0, key, [&]() { return vcycle_level(ctx, ctx->n_levels - 1, b, x, nu_pre, nu_post); });
@@ -1322,6 +1400,7 @@ vk_status vk_get_patch_inverses(vk_ctx* ctx, int32_t l, int32_t cell0, int32_t n
     return fail(ctx, VK_ERR_ARG, "patch inverses exist on levels >= 1");
   const vk_group& G = ctx->lv[l].groups[0];
   if (cell0 < 0 || n < 0 || (int64_t)cell0 + n > G.n_cells || !out) return fail(ctx, VK_ERR_ARG, "cell range");
+  VK_CHECK(patch_settle(ctx, true));
   VK_TRY(launch_patch_export(ctx->stream, G, ctx->prec, cell0, n, out));
   return VK_OK;
 }
@@ -1363,6 +1442,7 @@ vk_status vk_patch_layout(const vk_ctx* ctx, int32_t l, int64_t* bytes_per_cell,
 
 vk_status vk_autotune(vk_ctx* ctx, int32_t reps) {
   VK_CHECK(ready(ctx));
+  VK_CHECK(patch_settle(ctx, true));
   ++ctx->gen;
   if (reps < 1) reps = 1;
   hipStream_t s = ctx->stream;

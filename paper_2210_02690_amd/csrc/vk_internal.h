@@ -233,7 +233,6 @@ struct vk_ctx {
   // internal stream for the patch inversions, masked to 3/4 of the CUs (when the runtime allows
   // it), so they do not hold back the side stream's short block-inversion launches
   hipStream_t setup = nullptr;
-  hipEvent_t setup_ev = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   // further side streams: the block inversions of different levels are independent chains, one
   // stream each (created when a setup first needs them); n_xside of them belong to the last setup
@@ -270,6 +269,11 @@ struct vk_ctx {
   // their status words
   bool coarse_pending = false;
   bool coarse_check_due = false;
+  // patch inversions of the levels below the finest, still running on the setup stream after
+  // vanka_setup: the context stream waits for level l's event before it first smooths on l
+  std::vector<hipEvent_t> patch_ev;  // per level, recorded on the setup stream
+  uint64_t patch_pending = 0;         // bit l: not yet waited for
+  bool patch_check_due = false;       // their status words not yet read
 
   void* Y = nullptr;          // per-cell products y_K of the additive sweep
   // batched GMRES: segments of the finest level solved as independent systems

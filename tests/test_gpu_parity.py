@@ -339,6 +339,46 @@ def test_singular_170_patch_reported(vk, variant):
     S.close()
 
 
+def test_singular_coarser_patch_reported_by_the_solve(vk):
+    """A zero pivot in a patch below the finest level.  The coarser levels' inversions run on beside
+    the next solve, so vanka_setup returns and the solve names the level and cell (vanka_setup does
+    where the library has no separate setup stream); setup must then run again."""
+    P = build_problem("channel2d_44x8_k1", shape=(8, 4), levels=3)
+    L = P.levels[1]
+    assert L.mesh.n_K == 42 and P.levels[2].mesh.n_cells > L.mesh.n_cells
+    cell = 5
+    pdof = int(L.cell_dofs[cell][18])   # a pressure DoF: it belongs to this cell only
+    J = L.J.tolil()
+    J[pdof, :] = 0.0
+    J = J.tocsr()
+    J.eliminate_zeros()
+    J.sort_indices()
+    L.J = J
+    S = vk.Solver([vk.upload_level(Lv, DEV) for Lv in P.levels])
+    S.vk_set_workspace("f64", 30, device=DEV)
+    b = torch.from_numpy(P.b).to(DEV)
+    x = torch.zeros_like(b)
+    try:
+        S.vanka_setup(0.7)
+    except vk.VkError as e:
+        assert e.status == vk.VK_ERR_SINGULAR and e.bad_level == 1 and e.bad_cell == cell
+        S.close()
+        return
+    with pytest.raises(vk.VkError) as e:
+        S.gmres_solve(b, x, rtol=1e-8)
+    assert e.value.status == vk.VK_ERR_SINGULAR
+    assert f"cell {cell} on level 1" in str(e.value)
+    with pytest.raises(vk.VkError) as e2:
+        S.vcycle(b, x, 2, 2)
+    assert e2.value.status == vk.VK_ERR_STATE
+    # the same through a direct entry point: vanka_smooth on the finest level reads the status
+    S.vanka_setup(0.7)
+    with pytest.raises(vk.VkError) as e3:
+        S.vanka_smooth(2, b, x, 1, d_is_zero=True)
+    assert e3.value.status == vk.VK_ERR_SINGULAR and f"cell {cell} on level 1" in str(e3.value)
+    S.close()
+
+
 def test_malformed_csr_rejected(vk):
     P = build_problem("channel2d_44x8_k1", shape=(8, 4), levels=2)
     lv = [vk.upload_level(L, DEV) for L in P.levels]
