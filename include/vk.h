@@ -344,7 +344,8 @@ vk_status vk_set_coarse_solver(vk_ctx* ctx, int32_t mode);
 int32_t vk_coarse_plan(vk_ctx* ctx, int32_t level, double* setup_flops);
 
 /* Autotuner: after vanka_setup, times each level's SpMV kernels (J, P, R)
- * with 4, 8, 16, 32 and 64 lanes per row and the patch GEMV with 1, 2, 4 and
+ * with 4, 8, 16, 32 and 64 lanes per row (also 1 and 2 for matrices with
+ * fewer than 16 entries per row on average, such as the transfers P) and the patch GEMV with 1, 2, 4 and
  * 8 cells per workgroup (`reps` launches each, HIP events) and keeps the
  * fastest for the context; on levels with one cell group the GEMV tiles are
  * then timed again inside V-cycles from the finest level (three rounds of

@@ -1460,7 +1460,7 @@ vk_status vk_autotune(vk_ctx* ctx, int32_t reps) {
     (void)hipEventElapsedTime(&ms, e0, e1);
     return ms;
   };
-  const int lprs[5] = {4, 8, 16, 32, 64};
+  const int lprs[7] = {1, 2, 4, 8, 16, 32, 64};
   for (int l = 0; l < ctx->n_levels; ++l) {
     vk_level& L = ctx->lv[l];
     VK_TRY(launch_fill(s, L.J.n_rows, 1.0, L.b));
@@ -1468,6 +1468,7 @@ vk_status vk_autotune(vk_ctx* ctx, int32_t reps) {
       int best = 4;
       float tb = 1e30f;
       for (int lpr : lprs) {
+        if (lpr < 4 && A.nnz >= 16 * A.n_rows) continue;  // one or two lanes only for short rows
         const float t = time_ms([&] { return launch_spmv(s, A, lpr, 1.0, x, 0.0, nullptr, y); });
         if (t < tb) { tb = t; best = lpr; }
       }

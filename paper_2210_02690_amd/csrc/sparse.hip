@@ -357,6 +357,8 @@ hipError_t launch_spmv(hipStream_t s, const vk_csr& A, int lpr, double alpha, co
   if (A.n_rows == 0) return hipSuccess;
   const unsigned grid = grid_for(A.n_rows * lpr, 256);
   switch (lpr) {
+    case 1: spmv_kernel<1><<<grid, 256, 0, s>>>(A.n_rows, A.row_ptr, A.col, A.val, x, alpha, beta, z, y); break;
+    case 2: spmv_kernel<2><<<grid, 256, 0, s>>>(A.n_rows, A.row_ptr, A.col, A.val, x, alpha, beta, z, y); break;
     case 4: spmv_kernel<4><<<grid, 256, 0, s>>>(A.n_rows, A.row_ptr, A.col, A.val, x, alpha, beta, z, y); break;
     case 8: spmv_kernel<8><<<grid, 256, 0, s>>>(A.n_rows, A.row_ptr, A.col, A.val, x, alpha, beta, z, y); break;
     case 16: spmv_kernel<16><<<grid, 256, 0, s>>>(A.n_rows, A.row_ptr, A.col, A.val, x, alpha, beta, z, y); break;
