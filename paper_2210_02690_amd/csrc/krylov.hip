@@ -48,7 +48,26 @@ __global__ __launch_bounds__(RB) void mdot_partial_kernel(int64_t n, const doubl
   double acc[MB];
 #pragma unroll
   for (int i = 0; i < MB; ++i) acc[i] = 0.0;
-  for (int64_t r = (int64_t)blockIdx.x * RB + threadIdx.x; r < n; r += (int64_t)gridDim.x * RB) {
+  // U of the thread's rows at a time: their loads are all issued before the first product, then
+  // the rows are added in order (the same sums, in the same order, as one row at a time)
+  constexpr int U = MB <= 8 ? 4 : (MB <= 16 ? 2 : 1);
+  const int64_t stride = (int64_t)gridDim.x * RB;
+  int64_t r = (int64_t)blockIdx.x * RB + threadIdx.x;
+  for (; r + (U - 1) * stride < n; r += U * stride) {
+    double wr[U], v[U][MB];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      wr[u] = w[r + u * stride];
+#pragma unroll
+      for (int i = 0; i < MB; ++i) v[u][i] = i < m ? V[(int64_t)i * ldv + r + u * stride] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+        if (i < m) acc[i] += v[u][i] * wr[u];
+  }
+  for (; r < n; r += stride) {
     const double wr = w[r];
 #pragma unroll
     for (int i = 0; i < MB; ++i)
