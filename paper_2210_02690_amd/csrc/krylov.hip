@@ -39,21 +39,13 @@ __global__ __launch_bounds__(RB) void reduce_kernel(int32_t np, const double* __
   if (threadIdx.x == 0) out[0] = sqrt_out ? sqrt(s) : s;
 }
 
-// partial[b * m + i] = sum over block b's rows of V_i . w
-template <int MB>
-__global__ __launch_bounds__(RB) void mdot_partial_kernel(int64_t n, const double* __restrict__ V, int64_t ldv,
-                                                          int32_t m, const double* __restrict__ w,
-                                                          double* partial) {
-  __shared__ double sh[RB / 64];
-  double acc[MB];
-#pragma unroll
-  for (int i = 0; i < MB; ++i) acc[i] = 0.0;
-  // U of the thread's rows at a time: their loads are all issued before the first product, then
-  // the rows are added in order (the same sums, in the same order, as one row at a time)
-  constexpr int U = MB <= 8 ? 4 : (MB <= 16 ? 2 : 1);
-  const int64_t stride = (int64_t)gridDim.x * RB;
-  int64_t r = (int64_t)blockIdx.x * RB + threadIdx.x;
-  for (; r + (U - 1) * stride < n; r += U * stride) {
+// acc[i] += V_i[r] w[r] over the rows r = r0, r0 + stride, ... below e.  U rows at a time: their loads
+// are all issued before the first product, then the rows are added in order (the same sums, in the
+// same order, as one row at a time)
+template <int MB, int U>
+__device__ inline void rows_mdot(int64_t r, int64_t e, int64_t stride, const double* __restrict__ V, int64_t ldv,
+                                 int32_t m, const double* __restrict__ w, double (&acc)[MB]) {
+  for (; r + (U - 1) * stride < e; r += U * stride) {
     double wr[U], v[U][MB];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -67,12 +59,26 @@ __global__ __launch_bounds__(RB) void mdot_partial_kernel(int64_t n, const doubl
       for (int i = 0; i < MB; ++i)
         if (i < m) acc[i] += v[u][i] * wr[u];
   }
-  for (; r < n; r += stride) {
+  for (; r < e; r += stride) {
     const double wr = w[r];
 #pragma unroll
     for (int i = 0; i < MB; ++i)
       if (i < m) acc[i] += V[(int64_t)i * ldv + r] * wr;
   }
+}
+
+// partial[b * m + i] = sum over block b's rows of V_i . w
+template <int MB>
+__global__ __launch_bounds__(RB) void mdot_partial_kernel(int64_t n, const double* __restrict__ V, int64_t ldv,
+                                                          int32_t m, const double* __restrict__ w,
+                                                          double* partial) {
+  __shared__ double sh[RB / 64];
+  double acc[MB];
+#pragma unroll
+  for (int i = 0; i < MB; ++i) acc[i] = 0.0;
+  // one workgroup per CU at most: the rows of a thread are many, so several are loaded at once
+  rows_mdot<MB, MB <= 8 ? 4 : (MB <= 16 ? 2 : 1)>((int64_t)blockIdx.x * RB + threadIdx.x, n, (int64_t)gridDim.x * RB, V,
+                                                  ldv, m, w, acc);
 #pragma unroll
   for (int i = 0; i < MB; ++i) {
     if (i < m) {  // m is uniform: the barriers inside block_sum are reached by all threads
@@ -205,12 +211,8 @@ __global__ __launch_bounds__(RB) void seg_mdot_partial_kernel(const int64_t* __r
   double acc[MB];
 #pragma unroll
   for (int i = 0; i < MB; ++i) acc[i] = 0.0;
-  for (int64_t r = seg[sg] + (int64_t)c * RB + threadIdx.x; r < e; r += (int64_t)nc * RB) {
-    const double wr = w[r];
-#pragma unroll
-    for (int i = 0; i < MB; ++i)
-      if (i < m) acc[i] += V[(int64_t)i * ldv + r] * wr;
-  }
+  // many workgroups: two rows at a time keeps the registers (and the occupancy) low
+  rows_mdot<MB, MB <= 8 ? 2 : 1>(seg[sg] + (int64_t)c * RB + threadIdx.x, e, (int64_t)nc * RB, V, ldv, m, w, acc);
 #pragma unroll
   for (int i = 0; i < MB; ++i) {
     if (i < m) {  // uniform
