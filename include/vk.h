@@ -206,7 +206,11 @@ vk_status vanka_smooth(vk_ctx* ctx, int32_t l, const double* b, double* d, int32
  * colour's cell count, each part rounded up to 256 bytes) are rejected with VK_ERR_ARG.
  * Every call on one GPU shares that GPU's array: calls that overlap in time on one GPU (from
  * different contexts, streams or threads) race and must be serialised by the caller.  Nothing is
- * assumed about the array's contents at entry.  Arguments, errors and stream as vanka_smooth. */
+ * assumed about the array's contents at entry.  Arguments, errors and stream as vanka_smooth.
+ * Like the other direct entry points, the first call after vanka_setup waits on the host for the
+ * coarser levels' patch inversions still running on the internal setup stream and reads their
+ * status words there (nothing is enqueued on the context's stream for it); a caller that captures
+ * a graph should make one call, or any other direct entry point, before capturing. */
 vk_status vanka_smooth_noalloc(vk_ctx* ctx, int32_t l, const double* b, double* d, int32_t sweeps,
                                int32_t d_is_zero);
 
