@@ -118,6 +118,10 @@ def test_grouped_csr_products_176x32(vk):
             assert np.abs(y.cpu().numpy() - ref).max() <= 1e-13 * np.abs(ref).max(), lanes
             S.vk_spmv(l, xt, y, alpha=-1.0, beta=1.0, z=zt)
             assert np.abs(y.cpu().numpy() - ref2).max() <= 1e-13 * np.abs(ref2).max(), lanes
+        for bad in (2, 3, 128, -1):
+            with pytest.raises(vk.VkError) as e:
+                S.vk_set_spmv_format(bad)
+            assert e.value.status == vk.VK_ERR_ARG
         S.vk_set_spmv_format(0)
         assert S.vk_spmv_format(l) == 0
         y2 = torch.empty_like(xt)
