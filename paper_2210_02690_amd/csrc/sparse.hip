@@ -82,7 +82,7 @@ __device__ inline double readlane_d(double v, int l) {
   return __builtin_bit_cast(double, r);
 }
 
-template <int LPR, bool NTL>
+template <int LPR>
 __global__ __launch_bounds__(256) void spmv_g_kernel(int64_t n_groups, const int32_t* __restrict__ g_row,
                                                      const int64_t* __restrict__ g_coff,
                                                      const int64_t* __restrict__ g_v0,
@@ -114,12 +114,11 @@ __global__ __launch_bounds__(256) void spmv_g_kernel(int64_t n_groups, const int
         if (G > 3) xv[3] = x[b + 3];
       }
     };
-    // two entries per lane and iteration: their value loads and gathers in flight together.  For
-    // a matrix far larger than the last-level cache the values and column words, read once, are
-    // loaded non-temporally (leaving the caches to x); a smaller one stays cacheable, since the
-    // next product can find it in the 256 MB cache
-    auto ldv = [&](int64_t i) { return NTL ? __builtin_nontemporal_load(v + i) : v[i]; };
-    auto ldc = [&](int64_t i) { return NTL ? __builtin_nontemporal_load(gcol + i) : gcol[i]; };
+    // two entries per lane and iteration: their value loads and gathers in flight together.  All
+    // loads go through the caches: non-temporal value and column loads made the batch's 1.8 GB J
+    // slower here (the autotuner then kept CSR for it), unlike in the one-group-per-wavefront kernel
+    auto ldv = [&](int64_t i) { return v[i]; };
+    auto ldc = [&](int64_t i) { return gcol[i]; };
     for (; j + LPR < m; j += 2 * LPR) {
       const uint32_t ca = ldc(c0 + j), cb = ldc(c0 + j + LPR);
       double xa[4], xb[4];
@@ -374,12 +373,7 @@ hipError_t launch_spmv_g(hipStream_t s, const vk_csr& A, const vk_gcsr& g, int l
   const unsigned grid = grid_for(g.n_groups * lpr, 256);
   const bool ntl = A.nnz * 12 > (1ll << 30);  // well beyond the 256 MB last-level cache
 #define VK_SPMV_G(LL)                                                                                          \
-  if (ntl)                                                                                                     \
-    spmv_g_kernel<LL, true><<<grid, 256, 0, s>>>(g.n_groups, g.g_row, g.g_coff, g.g_v0, g.gcol, A.val, x, alpha, \
-                                                  beta, z, y);                                                  \
-  else                                                                                                         \
-    spmv_g_kernel<LL, false><<<grid, 256, 0, s>>>(g.n_groups, g.g_row, g.g_coff, g.g_v0, g.gcol, A.val, x,      \
-                                                   alpha, beta, z, y)
+  spmv_g_kernel<LL><<<grid, 256, 0, s>>>(g.n_groups, g.g_row, g.g_coff, g.g_v0, g.gcol, A.val, x, alpha, beta, z, y)
   switch (lpr) {
     case 4: VK_SPMV_G(4); break;
     case 8: VK_SPMV_G(8); break;
