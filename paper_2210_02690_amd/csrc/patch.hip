@@ -1542,6 +1542,14 @@ hipError_t setup_rows(hipStream_t s, const vk_csr& J, const vk_group& L, int32_t
 // The DoF -> (cell, local index) lists are built at setup.
 // ===========================================================================
 
+// 16 bytes of a patch inverse, read once per sweep: loaded non-temporally, so the stream of
+// inverses does not push the defect, the DoF lists and the iterate out of the caches (the 3D finest
+// GEMV 0.519 -> 0.491 ms; the 176 x 32 channel's, whose inverses fit the last-level cache, gained too)
+__device__ inline uint4 ld_stream(const void* p) {
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  return __builtin_bit_cast(uint4, __builtin_nontemporal_load(reinterpret_cast<const v4u*>(p)));
+}
+
 template <int P>
 __global__ __launch_bounds__(VK_NT) void patch_gemv_kernel(const void* __restrict__ inv_, int32_t ld,
                                                            int64_t cell_stride, int32_t n_K, int32_t n_cells,
@@ -1573,7 +1581,7 @@ __global__ __launch_bounds__(VK_NT) void patch_gemv_kernel(const void* __restric
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
       const int j = g + q * G < n_K ? g + q * G : n_K - 1;
-      pre[q] = *reinterpret_cast<const uint4*>(base + (int64_t)j * ld);
+      pre[q] = ld_stream(base + (int64_t)j * ld);
     }
   }
   for (int j = t; j < n_K; j += tpc) srk[slot * n_K + j] = valid ? (A)r[cell_dofs[K * n_K + j]] : (A)0;
@@ -1597,7 +1605,7 @@ __global__ __launch_bounds__(VK_NT) void patch_gemv_kernel(const void* __restric
 #pragma unroll 4
     for (int j = g + PF * G; j < n_K; j += G) {
       A a[VW];
-      load_vec<P>(base + (int64_t)j * ld, a);
+      cvt_vec<P>(ld_stream(base + (int64_t)j * ld), a);
       const A rj = rk[j];
 #pragma unroll
       for (int e = 0; e < VW; ++e) acc[e] = fma(a[e], rj, acc[e]);
