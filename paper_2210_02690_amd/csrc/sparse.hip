@@ -177,35 +177,52 @@ __global__ __launch_bounds__(256) void spmv_g_kernel(int64_t n_groups, const int
 
 // One group per wavefront (64 lanes per group, the J of 3D patches with rows of a few hundred
 // entries).  The group is the same for the whole wavefront, so its description is read with scalar
-// loads and its size G selects straight-line code: per iteration a lane takes entries j, j + 64, ..
-// j + 64 (E - 1) of all G rows, issues the column words and all E G value loads first and then the
-// gathers of x, so the values stream while the gathers wait on their column words.  A lane past the
-// row's end reads the last entry again and keeps its sums (the order of the additions is that of
-// spmv_g_kernel).  x of a shifted entry's rows 1..G-1 is loaded only on the lanes that need it,
-// into registers that start at zero, so no loaded value is copied before the wait for it.  E = 2
-// keeps 8 wavefronts per SIMD (54 registers; E = 4 needs 94 and was slower).  With NTL the values,
-// read once, load non-temporally; the column words stay cacheable (a line of them is shared by
-// neighbouring groups).
+// loads and its size G selects straight-line code: per iteration a lane takes the adjacent entries
+// j and j + 1 of all G rows, issues its two column words and one 16-byte value load per row first and
+// then the gathers of x, so the values stream while the gathers wait on their column words (16-byte
+// value loads instead of two 8-byte ones: 0.667 -> 0.635 ms for the 3D finest J).  A lane past the
+// row's end keeps its sums.  x of a shifted entry's rows 1..G-1 is loaded only on the lanes that need
+// it, into registers that start at zero, so no loaded value is copied before the wait for it.  Two
+// entries per lane keep 8 wavefronts per SIMD (four entries needed 94 registers and were slower).
+// With NTL the values, read once, load non-temporally; the column words stay cacheable (a line of
+// them is shared by neighbouring groups).
 template <int G, int E, bool NTL>
 __device__ inline void group_dot64(int lane, int64_t m, const uint32_t* __restrict__ gc,
                                    const double* __restrict__ v, const double* __restrict__ x, double (&s)[4]) {
-  auto ldv = [&](int64_t i) { return NTL ? __builtin_nontemporal_load(v + i) : v[i]; };
-  for (int64_t jb = 0; jb < m; jb += 64 * E) {
-    bool ok[E];
-    int64_t ie[E];
-    uint32_t cw[E];
+  static_assert(E == 2, "a lane takes two adjacent entries");
+  if (m < 2) {  // a row of one entry (or none) has no pair: lane 0 alone
+    if (m == 1 && lane == 0) {
+      const uint32_t cw = gc[0];
+      const int64_t b0 = (int64_t)(cw & 0x7fffffffu);
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int64_t j = jb + lane + 64 * e;
-      ok[e] = j < m;
-      ie[e] = ok[e] ? j : m - 1;
-      cw[e] = gc[ie[e]];
+      for (int c = 0; c < G; ++c) s[c] = fma(v[c], x[b0 + ((cw >> 31) ? c : 0)], s[c]);
     }
+    return;
+  }
+  // the group's values through a buffer resource: 16-byte loads that need only 4-byte alignment
+  // (a row's pair starts on any 8-byte boundary), the non-temporal hint as an immediate
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<double*>(v), (short)0, (int)(G * m * (int64_t)sizeof(double)), 0x00020000);
+  for (int64_t jb = 0; jb < m; jb += 128) {
+    // entries j0 and j0 + 1 of every row; the 16-byte pair is read at p0, inside the row (near its
+    // end p0 = m - 2, and an odd last entry is the pair's second half)
+    const int64_t j0 = jb + 2 * lane;
+    bool ok[E];
+    uint32_t cw[E];
+    ok[0] = j0 < m;
+    ok[1] = j0 + 1 < m;
+    cw[0] = gc[ok[0] ? j0 : m - 1];
+    cw[1] = gc[ok[1] ? j0 + 1 : m - 1];
+    const int64_t p0 = j0 < m - 1 ? j0 : m - 2;
+    const bool second = j0 != p0;
     double vv[E][G];
 #pragma unroll
-    for (int e = 0; e < E; ++e)
-#pragma unroll
-      for (int c = 0; c < G; ++c) vv[e][c] = ldv(c * m + ie[e]);
+    for (int c = 0; c < G; ++c) {
+      const int off = (int)((c * m + p0) * (int64_t)sizeof(double));
+      const double2 d = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, NTL ? 2 : 0));
+      vv[0][c] = second ? d.y : d.x;
+      vv[1][c] = d.y;
+    }
     // the shifted entries' loads go first: the gathers at the columns come after the branches, so
     // the choice between the two cannot be folded into a branch's default value (which would copy
     // a gather, and wait for it, before the other entries' loads issue)
